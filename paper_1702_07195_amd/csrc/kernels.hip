@@ -1,0 +1,429 @@
+// HIP kernels for Smith-Waterman database search on gfx950 (CDNA4).
+//
+// Recurrences (Section 2, Eqs. 1-3), Goe = gap_open + gap_extend, Ge = gap_extend:
+//   H[i][j] = max{0, H[i-1][j-1] + SM(q_i, d_j), E[i][j], F[i][j]}
+//   E[i][j] = max{H[i][j-1] - Goe, E[i][j-1] - Ge}
+//   F[i][j] = max{H[i-1][j] - Goe, F[i-1][j] - Ge}
+//
+// All kernels keep E and F clamped at zero (E' = max(E, 0), F' = max(F, 0)), computed
+// with unsigned saturating subtraction.  Because H >= 0, max(0, x, E, F) equals
+// max(x, E', F'), and E'/F' obey the same recurrences with every intermediate clamped,
+// so H (and the score) is unchanged while the explicit "max with 0" disappears.
+//
+// Kernels:
+//   k_profile   query profiles (Section 4.3, QP): P[d][i] = SM(q_i, d), plus counters.
+//   k_pack      length-sorted groups of 64 sequences, interleaved and padded (Section 4,
+//               pre-processing: sort by length, group by lane count, pad with dummies).
+//   k_inter16   inter-task DP (Sections 1 and 4.1) in packed int16 with saturation
+//               (Section 4.2): one sequence per lane, two DP cells per 32-bit lane.
+//   k_intra32   intra-task DP (Section 1) for very long sequences and for the exact
+//               recompute of saturated alignments (Section 4.2), int32, anti-diagonal.
+#include "swmi_internal.h"
+
+namespace swmi {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// v_pk_add_i16 with clamp: per-half signed saturating add.
+__device__ __forceinline__ uint32_t pk_adds(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(
+      __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+}
+// v_pk_sub_u16 with clamp: per-half unsigned saturating subtract (floors at 0).
+__device__ __forceinline__ uint32_t pk_subu(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+      __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+// v_pk_max_i16: per-half signed max.
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(
+      __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+}
+// v_sub_u32 with clamp.
+__device__ __forceinline__ int32_t subu(int32_t a, int32_t b) {
+  return (int32_t)__builtin_elementwise_sub_sat((uint32_t)a, (uint32_t)b);
+}
+
+// ------------------------------------------------------------------------ profiles
+// Inter-task profile of query q: [nstrips][32 codes][2T rows] int16, so one strip's
+// slice is a contiguous block.  Intra-task profile: [32 codes][mpad32 rows] int16.
+// Rows past the query end and codes outside the alphabet (including the padding code)
+// score kPadScore.
+__global__ void k_profile(ProfileArgs a) {
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4)
+    reinterpret_cast<int32_t *>(a.ctr)[threadIdx.x] = 0;
+  const int q = blockIdx.y;
+  const QueryDesc d = a.queries[q];
+  const uint8_t *qs = a.query + a.qoff[q];
+  const int twoT = 2 * a.T;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n16 = (int64_t)d.nstrips * kCodes * twoT;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += stride) {
+    const int r = (int)(e % twoT);
+    const int code = (int)((e / twoT) % kCodes);
+    const int64_t i = (e / ((int64_t)twoT * kCodes)) * twoT + r;
+    int v = kPadScore;
+    if (i < d.m && code < a.alphabet) v = a.matrix[qs[i] * a.alphabet + code];
+    a.qp16[d.qp16 + e] = (int16_t)v;
+  }
+  const int64_t n32 = (int64_t)kCodes * d.mpad32;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n32; e += stride) {
+    const int64_t i = e % d.mpad32;
+    const int code = (int)(e / d.mpad32);
+    int v = kPadScore;
+    if (i < d.m && code < a.alphabet) v = a.matrix[qs[i] * a.alphabet + code];
+    a.qp32[d.qp32 + e] = (int16_t)v;
+  }
+}
+
+hipError_t launch_profile(const ProfileArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_profile, dim3(64, a.nqueries), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------ packing
+// One block per group.  Output dword (chunk c, lane l) holds residues 4c..4c+3 of the
+// group's sequence l; columns past a sequence's end hold kPadCode.
+__global__ void k_pack(PackArgs a) {
+  const GroupDesc d = a.groups[blockIdx.x];
+  const int lane = threadIdx.x & 63;
+  const int sub = threadIdx.x >> 6;
+  int64_t src = 0;
+  int64_t len = 0;
+  if (lane < d.count) {
+    const int orig = a.perm[d.first + lane];
+    src = a.offsets[orig];
+    len = a.offsets[orig + 1] - src;
+  }
+  uint32_t *out = reinterpret_cast<uint32_t *>(a.packed + d.base);
+  const int nchunks = d.ncols >> 2;
+  for (int c = sub; c < nchunks; c += blockDim.x >> 6) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t col = 4 * (int64_t)c + k;
+      const uint32_t r = col < len ? a.raw[src + col] : (uint32_t)kPadCode;
+      w |= r << (8 * k);
+    }
+    out[(int64_t)c * 64 + lane] = w;
+  }
+}
+
+hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
+  if (a.ngroups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack, dim3(a.ngroups), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------ inter-task
+// Persistent kernel, one wave per workgroup.  A work item is (query, group); each lane
+// aligns the query against one sequence of the group.  The query is cut into strips of
+// 2T rows.  In every 32-bit register the low int16 half holds strip rows [0, T) at
+// DB column j and the high half holds rows [T, 2T) of the same alignment at column
+// j - 1, so the hand-off from the low rows to the high rows stays in the lane.  Per
+// strip, the bottom row's (H, F) of each column goes to a per-wave boundary buffer
+// that the next strip reads back (layout [column][64 lanes] dwords: H low, F high).
+//
+// Saturation (Section 4.2): only H[i-1][j-1] + SM can exceed the int16 range, and the
+// clamped add then pins H at 32767, so the running maximum equals 32767 exactly when
+// the true score may be >= 32767.  Those alignments are appended to a list and
+// recomputed in int32; every other int16 score is exact.
+template <int T>
+__global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
+  static_assert(T % 8 == 0, "strip half-height must be a multiple of 8");
+  constexpr int RS = 4 * T + 16;  // LDS bytes per code row; RS/16 is odd (fewer conflicts)
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kCodes * RS];
+  const int lane = threadIdx.x;
+  uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
+  const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
+  const uint32_t ge2 = (uint32_t)a.ge * 0x10001u;
+
+  for (;;) {
+    int item = 0;
+    if (lane == 0) item = atomicAdd(&a.ctr->inter_next, 1);
+    item = __builtin_amdgcn_readfirstlane(item);
+    if (item >= a.nitems) break;
+    const int g = a.ngroups - 1 - item / a.nqueries;  // longest groups first
+    const int qi = item % a.nqueries;
+    const GroupDesc gd = a.groups[g];
+    const QueryDesc qd = a.queries[qi];
+    const int16_t *qp = a.qp16 + qd.qp16;
+    const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
+    const int nchunks = gd.ncols >> 2;
+    uint32_t vmax = 0;
+
+    for (int s = 0; s < qd.nstrips; ++s) {
+      // Stage this strip's profile slice (32 codes x 2T rows) into LDS.
+      __syncthreads();
+      {
+        const uint4 *src = reinterpret_cast<const uint4 *>(qp + (int64_t)s * kCodes * 2 * T);
+        constexpr int PER_CODE = T / 4;  // 16-byte pieces per code row
+        constexpr int PIECES = kCodes * PER_CODE;
+#pragma unroll
+        for (int c = lane; c < PIECES; c += 64) {
+          const int code = c / PER_CODE, k = c - code * PER_CODE;
+          *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
+        }
+      }
+      __syncthreads();
+
+      const bool first = (s == 0);
+      const bool last = (s == qd.nstrips - 1);
+      uint32_t Hs[T], Es[T];
+#pragma unroll
+      for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
+      uint32_t hd0 = 0, lastH = 0, fnext = 0, prev = kPadCode;
+
+      uint32_t rw = res[0];
+      uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+      if (!first) { b0 = bnd[0]; b1 = bnd[64]; b2 = bnd[128]; b3 = bnd[192]; }
+
+      for (int c = 0; c < nchunks; ++c) {
+        uint32_t rwn = 0, n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+        if (c + 1 < nchunks) {
+          rwn = res[(int64_t)(c + 1) * 64];
+          if (!first) {
+            const uint32_t *bp = bnd + (int64_t)(c + 1) * 256;
+            n0 = bp[0]; n1 = bp[64]; n2 = bp[128]; n3 = bp[192];
+          }
+        }
+        const uint32_t bv[4] = {b0, b1, b2, b3};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int j = c * 4 + k;
+          const uint32_t cur = (rw >> (8 * k)) & 0xffu;
+          const uint8_t *pl = lds + cur * RS;            // low rows, column j
+          const uint8_t *ph = lds + prev * RS + 2 * T;   // high rows, column j - 1
+          uint32_t hd = hd0;                              // diagonal input of row 0
+          hd0 = (bv[k] & 0xffffu) | (lastH << 16);        // (H above at j, low row T-1 at j-1)
+          uint32_t f = (bv[k] >> 16) | (fnext << 16);     // F entering row 0 of each half
+          uint32_t h = 0;
+#pragma unroll
+          for (int r8 = 0; r8 < T; r8 += 8) {
+            const uint4 A = *reinterpret_cast<const uint4 *>(pl + 2 * r8);
+            const uint4 B = *reinterpret_cast<const uint4 *>(ph + 2 * r8);
+            const uint32_t av[4] = {A.x, A.y, A.z, A.w};
+            const uint32_t bw[4] = {B.x, B.y, B.z, B.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int r = r8 + q;
+              const uint32_t sm = (q & 1) ? ((av[q >> 1] >> 16) | (bw[q >> 1] & 0xffff0000u))
+                                          : ((av[q >> 1] & 0xffffu) | (bw[q >> 1] << 16));
+              h = pk_max(pk_max(pk_adds(hd, sm), Es[r]), f);   // Eq. 1 (E, F clamped >= 0)
+              vmax = pk_max(vmax, h);
+              const uint32_t t = pk_subu(h, goe2);             // H - Goe, floored at 0
+              Es[r] = pk_max(pk_subu(Es[r], ge2), t);          // Eq. 2 for column j + 1
+              f = pk_max(pk_subu(f, ge2), t);                  // Eq. 3 for row r + 1
+              hd = Hs[r];
+              Hs[r] = h;
+            }
+          }
+          lastH = h;
+          fnext = f;
+          // high half's bottom row finished column j - 1: hand it to the next strip
+          if (!last && j > 0) bnd[(int64_t)(j - 1) * 64] = (lastH >> 16) | (fnext & 0xffff0000u);
+          prev = cur;
+        }
+        rw = rwn; b0 = n0; b1 = n1; b2 = n2; b3 = n3;
+      }
+      // the last column is padding; give the next strip a zero boundary there
+      if (!last) bnd[(int64_t)(gd.ncols - 1) * 64] = 0u;
+    }
+
+    const int lo = (int)(int16_t)(vmax & 0xffffu);
+    const int hi = (int)(int16_t)(vmax >> 16);
+    const int sc = lo > hi ? lo : hi;
+    if (lane < gd.count) {
+      const int p = gd.first + lane;
+      const int orig = a.perm[p];
+      if (sc >= kSat16 || a.recompute_all) {
+        const int k = atomicAdd(&a.ctr->flagged, 1);
+        PairItem it;
+        it.base = gd.base + 4 * lane;
+        it.cstride = 256;
+        it.len = a.lens[p];
+        it.out = (int32_t)0;
+        it.query = qi;
+        it.out = orig;
+        a.flagged[k] = it;
+      } else {
+        a.scores[qd.out + orig] = sc;
+      }
+    }
+  }
+}
+
+template <int T>
+static hipError_t launch_inter16_t(const InterArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_inter16<T>, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+bool inter16_supported(int T) { return T == 8 || T == 16 || T == 24 || T == 32 || T == 40; }
+
+int inter16_max_blocks_per_cu(int T) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (T) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<8>, 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<16>, 64, 0); break;
+    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<24>, 64, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<32>, 64, 0); break;
+    case 40: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<40>, 64, 0); break;
+    default: break;
+  }
+  return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s) {
+  if (a.nitems == 0 || grid == 0) return hipSuccess;
+  switch (T) {
+    case 8: return launch_inter16_t<8>(a, grid, s);
+    case 16: return launch_inter16_t<16>(a, grid, s);
+    case 24: return launch_inter16_t<24>(a, grid, s);
+    case 32: return launch_inter16_t<32>(a, grid, s);
+    case 40: return launch_inter16_t<40>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------------ intra-task
+// One (query, sequence) pair per workgroup of W waves, int32.  The query is cut into
+// bands of 64*R rows; lane l of the wave that owns band b holds rows
+// b*64R + l*R .. + R-1 and, at step s, works on DB column s - l (an anti-diagonal
+// sweep).  After every step the bottom row's H and the F entering the next lane's
+// first row move one lane down with a DPP wave shift; lane 0 takes them from the
+// boundary row of the band above instead, and lane 63 writes its bottom row for the
+// band below.  Bands go to waves round-robin and run as a pipeline: band b starts
+// kIntraLag chunks (of 64 steps) after band b-1, with a workgroup barrier after every
+// chunk, so every boundary value a band reads was written at least one barrier earlier.
+// Columns outside [0, n) carry the padding code and a zero boundary, which leaves every
+// in-range cell unchanged and never raises the maximum.
+__device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
+  // lanes 1..63 receive src from lane - 1; lane 0 keeps lane0_value
+  return __builtin_amdgcn_update_dpp(lane0_value, src, 0x138, 0xf, 0xf, false);
+}
+
+template <int R, int W>
+__global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
+  static_assert(R % 8 == 0, "rows per lane must be a multiple of 8");
+  __shared__ int s_item;
+  __shared__ int s_max[W];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int2 *ring = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_elems;
+
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int count = a.count_dev ? *a.count_dev : a.count;
+      const int it = atomicAdd(a.next, 1);
+      s_item = it < count ? it : -1;
+    }
+    __syncthreads();
+    const int it = s_item;
+    if (it < 0) break;
+    const PairItem pi = a.items[it];
+    const QueryDesc qd = a.queries[pi.query];
+    const int n = pi.len;
+    const int nb = qd.nbands;
+    int32_t vmax = 0;
+
+    if (n > 0 && nb > 0) {
+      const int nc = (n + 63 + 63) / 64;                 // chunks covering n + 63 steps
+      const int nce = nc > kIntraLag * W ? nc : kIntraLag * W;
+      const int lastb = nb - 1;
+      const int rounds = (lastb / W) * nce + kIntraLag * (lastb % W) + nc;
+      const uint8_t *resbase = a.packed + pi.base;
+      const int cs = pi.cstride;
+
+      int b = w;                       // band this wave works on
+      int32_t Hs[R], Es[R];
+      int32_t hbot = 0, fbot = 0, hdiag = 0, code = kPadCode;
+      int2 tq = make_int2(0, 0);       // band-top (H, F) for columns 64k + lane
+      int rq = kPadCode;               // residue of column 64k + lane
+#pragma unroll
+      for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
+
+      for (int rd = 0; rd < rounds; ++rd) {
+        if (b < nb) {
+          const int st = (b / W) * nce + kIntraLag * (b % W);
+          if (rd >= st && rd < st + nc) {
+            const int k = rd - st;
+            const int2 *top = ring + (int64_t)((b + W) % (W + 1)) * a.bnd_stride;
+            int2 *bot = ring + (int64_t)(b % (W + 1)) * a.bnd_stride;
+            const bool has_top = b > 0, has_bot = b < nb - 1;
+            if (k == 0) {
+#pragma unroll
+              for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
+              hbot = 0; fbot = 0; hdiag = 0; code = kPadCode;
+              tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
+              rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
+            }
+            const int col_next = 64 * (k + 1) + lane;
+            const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
+            const int rq_next = col_next < n
+                ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
+            const int16_t *prof = a.qp32 + qd.qp32 + (int64_t)b * 64 * R + lane * R;
+
+            for (int i = 0; i < 64; ++i) {
+              const int s = 64 * k + i;
+              code = wave_shr1(code, __builtin_amdgcn_readlane(rq, i));
+              const int hup = wave_shr1(hbot, __builtin_amdgcn_readlane(tq.x, i));
+              int f = wave_shr1(fbot, __builtin_amdgcn_readlane(tq.y, i));
+              int hd = hdiag;
+              hdiag = hup;
+              const uint4 *pp = reinterpret_cast<const uint4 *>(prof + (int64_t)code * qd.mpad32);
+              int h = 0;
+#pragma unroll
+              for (int r8 = 0; r8 < R; r8 += 8) {
+                const uint4 P = pp[r8 >> 3];
+                const uint32_t pv[4] = {P.x, P.y, P.z, P.w};
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                  const int r = r8 + q;
+                  const int sm = (q & 1) ? ((int32_t)pv[q >> 1] >> 16)
+                                         : (int32_t)(int16_t)(pv[q >> 1] & 0xffffu);
+                  h = max(max(hd + sm, Es[r]), f);          // Eq. 1 (E, F clamped >= 0)
+                  vmax = max(vmax, h);
+                  const int t = subu(h, a.goe);
+                  Es[r] = max(subu(Es[r], a.ge), t);        // Eq. 2
+                  f = max(subu(f, a.ge), t);                // Eq. 3
+                  hd = Hs[r];
+                  Hs[r] = h;
+                }
+              }
+              hbot = h;
+              fbot = f;
+              if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
+            }
+            tq = tq_next;
+            rq = rq_next;
+            if (k == nc - 1) b += W;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // workgroup max
+    for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
+    if (lane == 0) s_max[w] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int m = 0;
+      for (int i = 0; i < W; ++i) m = max(m, s_max[i]);
+      a.scores[a.queries[pi.query].out + pi.out] = m;
+    }
+  }
+}
+
+hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  if (R != kIntraR || waves != kIntraWaves) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_intra32<kIntraR, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+}  // namespace swmi

@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP kernels (kernels.hip) and the host side of the
+// C ABI (api.hip).  Not installed; the public interface is include/swmi.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swmi {
+
+// Residue code reserved for padding.  Its substitution score against every query
+// residue is kPadScore (<= 0), so padded columns or rows never raise a score.
+constexpr int kPadCode = 31;
+constexpr int kCodes = 32;          // profile rows per query position (codes 0..31)
+constexpr int kPadScore = -127;
+constexpr int kGroup = 64;          // database sequences per group (one per lane)
+constexpr int kColChunk = 4;        // residues per lane per dword in the packed layout
+constexpr int kSat16 = 32767;       // int16 saturation value (overflow flag)
+
+// One group of up to 64 length-sorted database sequences.  Residues live in the packed
+// buffer at `base`, laid out [ncols/4][64 lanes][4 residues]; `ncols` is the padded
+// width (a multiple of 4, at least max length + 1, so the last column is all padding).
+struct GroupDesc {
+  int64_t base;
+  int32_t ncols;
+  int32_t first;   // sorted position of lane 0 (sequence `first + lane`)
+  int32_t count;   // live lanes (<= 64)
+  int32_t maxlen;
+};
+
+// One (query, database sequence) pair for the int32 intra-task kernel.  Residue of
+// column c sits at packed[base + (c >> 2) * cstride + (c & 3)].
+struct PairItem {
+  int64_t base;
+  int32_t cstride;  // 256 for a sequence inside a group, 4 for a contiguous one
+  int32_t len;
+  int32_t out;      // index into the score array (caller's database order)
+  int32_t query;    // query index (batched search), 0 otherwise
+};
+
+// Per-query data used by both kernels.
+struct QueryDesc {
+  int64_t qp16;      // element offset of this query's strip profile in the int16 arena
+  int64_t qp32;      // element offset of this query's [32][mpad32] profile in the arena
+  int32_t m;         // query length
+  int32_t nstrips;   // inter-task strips (2*T rows each)
+  int32_t mpad32;    // rows of the intra-task profile (multiple of 64 * R)
+  int32_t nbands;    // intra-task bands of 64 * R rows
+  int64_t out;       // element offset of this query's scores in the output array
+};
+
+// Counters in device memory, cleared by the profile kernel at the start of a search.
+struct Counters {
+  int32_t inter_next;     // next inter-task work item
+  int32_t flagged;        // number of saturated pairs appended to the recompute list
+  int32_t intra_next;     // next intra-task work item (long list)
+  int32_t recompute_next; // next intra-task work item (recompute list)
+};
+
+struct InterArgs {
+  const uint8_t *packed;
+  const GroupDesc *groups;
+  int32_t ngroups;
+  int32_t nqueries;
+  const QueryDesc *queries;
+  const int16_t *qp16;
+  const int32_t *perm;       // sorted position -> caller's index
+  const int32_t *lens;       // sorted position -> length
+  int32_t goe, ge;
+  int32_t *scores;
+  PairItem *flagged;
+  Counters *ctr;
+  uint32_t *bnd;             // boundary scratch, one slot per persistent wave
+  int64_t bnd_slot_words;    // dwords per slot
+  int32_t recompute_all;
+  int32_t nitems;            // ngroups * nqueries
+};
+
+struct IntraArgs {
+  const uint8_t *packed;
+  const PairItem *items;     // static list (long sequences) or recompute list
+  const int32_t *count_dev;  // if non-null, the item count is read here (recompute list)
+  int32_t count;             // otherwise the item count
+  int32_t *next;             // work counter
+  const QueryDesc *queries;
+  const int16_t *qp32;
+  int32_t goe, ge;
+  int32_t *scores;
+  int2 *bnd;                 // band boundary scratch, one slot per persistent workgroup
+  int64_t bnd_slot_elems;    // int2 elements per slot
+  int32_t bnd_stride;        // int2 elements per band buffer (>= max len + 128)
+};
+
+struct ProfileArgs {
+  const uint8_t *query;      // concatenated queries
+  const int64_t *qoff;       // query offsets (nqueries + 1)
+  const QueryDesc *queries;
+  int32_t nqueries;
+  const int32_t *matrix;     // alphabet x alphabet
+  int32_t alphabet;
+  int32_t T;                 // inter-task half-strip rows
+  int16_t *qp16;
+  int16_t *qp32;
+  Counters *ctr;
+};
+
+struct PackArgs {
+  const uint8_t *raw;        // concatenated residues in caller order
+  const int64_t *offsets;    // caller offsets
+  const int32_t *perm;       // sorted position -> caller index
+  const GroupDesc *groups;
+  int32_t ngroups;
+  uint8_t *packed;
+};
+
+// Launchers (kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_profile(const ProfileArgs &a, hipStream_t s);
+hipError_t launch_pack(const PackArgs &a, hipStream_t s);
+hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s);
+hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s);
+
+// Strip heights compiled for the inter-task kernel, and band rows per lane for the
+// intra-task kernel.
+bool inter16_supported(int T);
+int inter16_max_blocks_per_cu(int T);
+constexpr int kIntraR = 16;
+constexpr int kIntraWaves = 4;
+constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
+
+}  // namespace swmi

@@ -1,0 +1,214 @@
+"""Thin ctypes binding of the C ABI in ``include/swmi.h`` (argument marshalling only).
+
+Every step of a search runs inside ``libswmi.so`` (HIP kernels for gfx950).  There is
+no Python or CPU fallback: if the library is missing this module raises on import of
+the library, and every call fails loudly with the library's error code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswmi.so")
+
+SW_OK = 0
+SW_EINVAL = -1
+SW_ENOMEM = -2
+SW_EDEVICE = -3
+SW_ENODB = -4
+
+SW_KNOB_INTRA_MIN_LEN = 1
+SW_KNOB_RECOMPUTE_ALL = 2
+SW_KNOB_STRIP_ROWS = 3
+SW_KNOB_GRID_WAVES = 4
+SW_KNOB_MEM_CAP_MB = 5
+
+# Every entry point declared in include/swmi.h.
+SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_async",
+           "sw_search_batch", "sw_strerror", "sw_timing_enable", "sw_timing_read",
+           "sw_set_knob", "sw_get_knob")
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+_lib = None
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def lib():
+    """Load libswmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        # torch bundles its own HIP runtime with the same soname (libamdhip64.so.7).
+        # Loading torch first makes libswmi.so bind to that runtime, so the process has
+        # one HIP runtime and torch tensors/streams are valid inside the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        L.sw_db_load.restype = ctypes.c_int
+        L.sw_db_load.argtypes = [_u8p, _i64p, ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.POINTER(_vp)]
+        L.sw_db_size.restype = ctypes.c_int64
+        L.sw_db_size.argtypes = [_vp]
+        L.sw_db_free.restype = None
+        L.sw_db_free.argtypes = [_vp]
+        L.sw_search.restype = ctypes.c_int
+        L.sw_search.argtypes = [_vp, _u8p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                ctypes.c_int32, _i32p]
+        L.sw_search_async.restype = ctypes.c_int
+        L.sw_search_async.argtypes = [_vp, _u8p, ctypes.c_int32, _i32p, ctypes.c_int32,
+                                      ctypes.c_int32, _vp, _vp]
+        L.sw_search_batch.restype = ctypes.c_int
+        L.sw_search_batch.argtypes = [_vp, _u8p, _i64p, ctypes.c_int64, _i32p, ctypes.c_int32,
+                                      ctypes.c_int32, _i32p]
+        L.sw_strerror.restype = ctypes.c_char_p
+        L.sw_strerror.argtypes = [ctypes.c_int]
+        L.sw_timing_enable.restype = ctypes.c_int
+        L.sw_timing_enable.argtypes = [_vp, ctypes.c_int32]
+        L.sw_timing_read.restype = ctypes.c_int
+        L.sw_timing_read.argtypes = [_vp, _i64p, ctypes.POINTER(ctypes.c_double)]
+        L.sw_set_knob.restype = ctypes.c_int
+        L.sw_set_knob.argtypes = [ctypes.c_int32, ctypes.c_int64]
+        L.sw_get_knob.restype = ctypes.c_int64
+        L.sw_get_knob.argtypes = [ctypes.c_int32]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().sw_strerror(int(code)).decode()
+
+
+def _check(rc: int, where: str):
+    if rc != SW_OK:
+        raise SwError(rc, where)
+
+
+def _u8(a):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    return a, a.ctypes.data_as(_u8p)
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_i32p)
+
+
+def _i64(a):
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    return a, a.ctypes.data_as(_i64p)
+
+
+def set_knob(knob: int, value: int):
+    _check(lib().sw_set_knob(knob, int(value)), "sw_set_knob")
+
+
+def get_knob(knob: int) -> int:
+    return int(lib().sw_get_knob(knob))
+
+
+def sw_db_load(residues, offsets, alphabet: int) -> "SwDb":
+    """Pre-process and upload a database (see sw_db_load in include/swmi.h)."""
+    res, pres = _u8(residues)
+    offs, poffs = _i64(offsets)
+    handle = _vp()
+    rc = lib().sw_db_load(pres, poffs, len(offs) - 1, int(alphabet), ctypes.byref(handle))
+    _check(rc, "sw_db_load")
+    return SwDb(handle, len(offs) - 1, int(alphabet))
+
+
+class SwDb:
+    """Owner of a loaded database handle."""
+
+    def __init__(self, handle, n_seqs: int, alphabet: int):
+        self._h = handle
+        self.n_seqs = n_seqs
+        self.alphabet = alphabet
+
+    @property
+    def handle(self):
+        if self._h is None or not self._h.value:
+            raise SwError(SW_ENODB, "database")
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().sw_db_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+    def size(self) -> int:
+        return int(lib().sw_db_size(self.handle))
+
+    def search(self, query, matrix, gap_open: int, gap_extend: int) -> np.ndarray:
+        """Scores of one query against every sequence, in the caller's order."""
+        q, pq = _u8(query)
+        m, pm = _i32(matrix)
+        out = np.zeros(self.n_seqs, dtype=np.int32)
+        rc = lib().sw_search(self.handle, pq, len(q), pm, int(gap_open), int(gap_extend),
+                             out.ctypes.data_as(_i32p))
+        _check(rc, "sw_search")
+        return out
+
+    def search_async(self, query, matrix, gap_open: int, gap_extend: int, scores_dev,
+                     stream=None):
+        """Enqueue a search on a torch CUDA(HIP) stream; ``scores_dev`` is an int32
+        device tensor of ``n_seqs`` elements."""
+        q, pq = _u8(query)
+        m, pm = _i32(matrix)
+        sptr = 0 if stream is None else int(stream.cuda_stream)
+        rc = lib().sw_search_async(self.handle, pq, len(q), pm, int(gap_open), int(gap_extend),
+                                   _vp(scores_dev.data_ptr()), _vp(sptr))
+        _check(rc, "sw_search_async")
+
+    def search_batch(self, queries, matrix, gap_open: int, gap_extend: int) -> np.ndarray:
+        """Scores of many queries (a list of code arrays) in one launch: [n_queries, n_seqs]."""
+        qs = [np.ascontiguousarray(x, dtype=np.uint8) for x in queries]
+        offs = np.zeros(len(qs) + 1, dtype=np.int64)
+        np.cumsum([len(x) for x in qs], out=offs[1:])
+        cat = np.concatenate(qs) if qs else np.zeros(0, np.uint8)
+        if len(cat) == 0:
+            cat = np.zeros(1, np.uint8)
+        c, pc = _u8(cat)
+        o, po = _i64(offs)
+        m, pm = _i32(matrix)
+        out = np.zeros((len(qs), self.n_seqs), dtype=np.int32)
+        rc = lib().sw_search_batch(self.handle, pc, po, len(qs), pm, int(gap_open),
+                                   int(gap_extend), out.ctypes.data_as(_i32p))
+        _check(rc, "sw_search_batch")
+        return out
+
+    def timing_enable(self, on: bool = True):
+        _check(lib().sw_timing_enable(self.handle, 1 if on else 0), "sw_timing_enable")
+
+    def timing_read(self):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        _check(lib().sw_timing_read(self.handle, ctypes.byref(n), ctypes.byref(ms)),
+               "sw_timing_read")
+        return int(n.value), float(ms.value)

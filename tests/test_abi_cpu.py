@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI that need no GPU: exports and argument validation."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1702_07195_amd import swmi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swmi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert declared_functions() == sorted(swmi.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = swmi.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_codes():
+    for code in (swmi.SW_OK, swmi.SW_EINVAL, swmi.SW_ENOMEM, swmi.SW_EDEVICE, swmi.SW_ENODB):
+        assert swmi.strerror(code)
+    assert swmi.strerror(-99) == "unknown error"
+
+
+def _load(res, offs, alpha):
+    L = swmi.lib()
+    r = np.ascontiguousarray(res, np.uint8)
+    o = np.ascontiguousarray(offs, np.int64)
+    h = ctypes.c_void_p()
+    rc = L.sw_db_load(r.ctypes.data_as(swmi._u8p), o.ctypes.data_as(swmi._i64p), len(o) - 1,
+                      alpha, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("res,offs,alpha", [
+    ([0, 1, 2], [0, 2, 3], 0),          # alphabet too small
+    ([0, 1, 2], [0, 2, 3], 32),         # alphabet too large
+    ([0, 1, 5], [0, 2, 3], 5),          # residue >= alphabet
+    ([0, 1, 2], [1, 2, 3], 5),          # offsets[0] != 0
+    ([0, 1, 2], [0, 2, 1], 5),          # decreasing offsets
+])
+def test_db_load_rejects_bad_arguments(res, offs, alpha):
+    rc, h = _load(res, offs, alpha)
+    assert rc == swmi.SW_EINVAL
+    assert not h.value
+
+
+def test_db_load_null_pointers():
+    L = swmi.lib()
+    h = ctypes.c_void_p()
+    o = np.array([0, 3], np.int64)
+    assert L.sw_db_load(None, o.ctypes.data_as(swmi._i64p), 1, 5, ctypes.byref(h)) == swmi.SW_EINVAL
+    assert L.sw_db_load(None, None, 1, 5, ctypes.byref(h)) == swmi.SW_EINVAL
+    assert L.sw_db_load(None, o.ctypes.data_as(swmi._i64p), 1, 5, None) == swmi.SW_EINVAL
+
+
+def test_search_without_database():
+    L = swmi.lib()
+    q = np.zeros(4, np.uint8)
+    m = np.zeros(25, np.int32)
+    out = np.zeros(4, np.int32)
+    rc = L.sw_search(None, q.ctypes.data_as(swmi._u8p), 4, m.ctypes.data_as(swmi._i32p), 10, 2,
+                     out.ctypes.data_as(swmi._i32p))
+    assert rc == swmi.SW_ENODB
+    assert L.sw_db_size(None) == swmi.SW_ENODB
+    L.sw_db_free(None)  # no-op
+
+
+def test_knobs_validate_and_round_trip():
+    old = swmi.get_knob(swmi.SW_KNOB_STRIP_ROWS)
+    with pytest.raises(swmi.SwError):
+        swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, 12)
+    swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, 16)
+    assert swmi.get_knob(swmi.SW_KNOB_STRIP_ROWS) == 16
+    swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, old)
+    with pytest.raises(swmi.SwError):
+        swmi.set_knob(99, 1)

@@ -1,0 +1,191 @@
+"""GPU parity: scores from the HIP path (through the C ABI) equal the oracle's exactly.
+
+Inputs are seeded synthetic databases and queries at sizes the oracle finishes in
+seconds, spanning several groups of 64 sequences, several strips and bands, and ragged
+tails.  Integer scores must match bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_07195_amd import swmi, synth
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = len(synth.ALPHABET)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def small_db():
+    rng = np.random.Generator(np.random.PCG64(20250))
+    lengths = synth.lognormal_lengths(rng, 700, 120, 0.9, 0, 900)
+    lengths[:5] = [0, 1, 2, 3, 0]
+    return synth.db_from_lengths(rng, lengths)
+
+
+@pytest.fixture(scope="module")
+def small_handle(small_db):
+    _say(f"load small db: {small_db.n_seqs} seqs, {small_db.offsets[-1]} residues")
+    h = swmi.sw_db_load(small_db.residues, small_db.offsets, ALPHA)
+    yield h
+    h.free()
+
+
+def _oracle(q, db, sm, go, ge):
+    return oracle.search(q, db.residues, db.offsets, sm, go, ge)
+
+
+@pytest.mark.parametrize("m", [1, 5, 31, 32, 33, 47, 48, 64, 65, 144, 200, 511])
+def test_query_lengths_blosum62(small_db, small_handle, m):
+    rng = np.random.Generator(np.random.PCG64(1000 + m))
+    q = synth.residues(rng, m)
+    _say(f"search m={m}")
+    got = small_handle.search(q, synth.BLOSUM62, 10, 2)
+    assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
+
+
+@pytest.mark.parametrize("mat,go,ge", [("BLOSUM50", 10, 2), ("BLOSUM62", 11, 1),
+                                        ("BLOSUM50", 11, 1), ("BLOSUM62", 0, 0),
+                                        ("BLOSUM62", 0, 5), ("BLOSUM62", 40, 0),
+                                        ("BLOSUM62", 16383, 0)])
+def test_matrices_and_gaps(small_db, small_handle, mat, go, ge):
+    rng = np.random.Generator(np.random.PCG64(77))
+    q = synth.residues(rng, 180)
+    sm = synth.MATRICES[mat]
+    _say(f"search {mat} {go}/{ge}")
+    assert np.array_equal(small_handle.search(q, sm, go, ge), _oracle(q, small_db, sm, go, ge))
+
+
+def test_asymmetric_small_alphabet():
+    rng = np.random.Generator(np.random.PCG64(31337))
+    alpha = 4
+    lengths = synth.lognormal_lengths(rng, 200, 60, 0.8, 0, 300)
+    seqs = [rng.integers(0, alpha, size=int(n)).astype(np.uint8) for n in lengths]
+    db = synth.db_from_seqs(seqs)
+    sm = synth.random_matrix(rng, alpha, -9, 12)
+    q = rng.integers(0, alpha, size=97).astype(np.uint8)
+    _say("search asymmetric alphabet 4")
+    with swmi.sw_db_load(db.residues, db.offsets, alpha) as h:
+        assert np.array_equal(h.search(q, sm, 3, 1), _oracle(q, db, sm, 3, 1))
+
+
+@pytest.mark.parametrize("T", [8, 16, 24, 32, 40])
+def test_strip_heights_agree(small_db, small_handle, T):
+    rng = np.random.Generator(np.random.PCG64(5))
+    q = synth.residues(rng, 150)
+    swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, T)
+    try:
+        _say(f"search strip rows T={T}")
+        got = small_handle.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, 0)
+    assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
+
+
+def test_recompute_all_changes_nothing(small_db, small_handle):
+    rng = np.random.Generator(np.random.PCG64(6))
+    q = synth.residues(rng, 260)
+    swmi.set_knob(swmi.SW_KNOB_RECOMPUTE_ALL, 1)
+    try:
+        _say("search recompute-all")
+        got = small_handle.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_RECOMPUTE_ALL, 0)
+    assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
+
+
+@pytest.mark.parametrize("cut", [0, 50, 300])
+def test_long_route_threshold(small_db, cut):
+    rng = np.random.Generator(np.random.PCG64(8))
+    q = synth.residues(rng, 1500)  # two intra-task bands
+    old = swmi.get_knob(swmi.SW_KNOB_INTRA_MIN_LEN)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_MIN_LEN, cut)
+    try:
+        _say(f"load with intra threshold {cut}")
+        with swmi.sw_db_load(small_db.residues, small_db.offsets, ALPHA) as h:
+            got = h.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_INTRA_MIN_LEN, old)
+    assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
+
+
+def test_saturation_and_exact_recompute():
+    # SM(a, a) = 7: a^4680 scores 32760 (exact in int16), a^4681 = 32767 and
+    # a^4682 = 32774 saturate and must be recomputed exactly in int32; neighbours in the
+    # same group keep their int16 scores.
+    sm = np.array([[7, -3], [-3, 7]], dtype=np.int32)
+    rng = np.random.Generator(np.random.PCG64(9))
+    seqs = [np.zeros(4680, np.uint8), np.zeros(4681, np.uint8), np.zeros(4682, np.uint8)]
+    seqs += [rng.integers(0, 2, size=int(n)).astype(np.uint8) for n in rng.integers(4000, 4700, 70)]
+    db = synth.db_from_seqs(seqs)
+    q = np.zeros(4682, np.uint8)
+    _say("search saturation")
+    with swmi.sw_db_load(db.residues, db.offsets, 2) as h:
+        got = h.search(q, sm, 10, 2)
+    want = _oracle(q, db, sm, 10, 2)
+    assert list(want[:3]) == [32760, 32767, 32774]
+    assert np.array_equal(got, want)
+
+
+def test_empty_cases():
+    _say("empty database")
+    with swmi.sw_db_load(np.zeros(0, np.uint8), np.zeros(1, np.int64), ALPHA) as h:
+        assert h.size() == 0
+        assert h.search(synth.encode("ACDE"), synth.BLOSUM62, 10, 2).shape == (0,)
+    db = synth.db_from_seqs([synth.encode("ACDEFG"), np.zeros(0, np.uint8), synth.encode("W")])
+    _say("empty query / empty sequences")
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        assert list(h.search(np.zeros(0, np.uint8), synth.BLOSUM62, 10, 2)) == [0, 0, 0]
+        got = h.search(synth.encode("CDEF"), synth.BLOSUM62, 10, 2)
+        assert np.array_equal(got, _oracle(synth.encode("CDEF"), db, synth.BLOSUM62, 10, 2))
+
+
+def test_bad_search_arguments(small_handle):
+    with pytest.raises(swmi.SwError) as e:
+        small_handle.search(np.array([0, 40], np.uint8), synth.BLOSUM62, 10, 2)
+    assert e.value.code == swmi.SW_EINVAL
+    bad = synth.BLOSUM62.copy()
+    bad[0, 0] = 128
+    with pytest.raises(swmi.SwError):
+        small_handle.search(synth.encode("ACD"), bad, 10, 2)
+    with pytest.raises(swmi.SwError):
+        small_handle.search(synth.encode("ACD"), synth.BLOSUM62, -1, 2)
+    with pytest.raises(swmi.SwError):
+        small_handle.search(synth.encode("ACD"), synth.BLOSUM62, 16383, 1)
+
+
+def test_batch_equals_separate(small_db, small_handle):
+    qs = synth.batched_queries(6, 1, 400, seed=11)
+    _say("batched search of 6 queries")
+    got = small_handle.search_batch(qs, synth.BLOSUM62, 10, 2)
+    for k, q in enumerate(qs):
+        assert np.array_equal(got[k], _oracle(q, small_db, synth.BLOSUM62, 10, 2)), k
+
+
+def test_async_on_torch_stream(small_db, small_handle):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(12))
+    q = synth.residues(rng, 222)
+    out = torch.full((small_db.n_seqs,), -1, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.Stream()
+    _say("async search on a torch stream")
+    small_handle.search_async(q, synth.BLOSUM62, 10, 2, out, stream)
+    stream.synchronize()
+    assert np.array_equal(out.cpu().numpy(), _oracle(q, small_db, synth.BLOSUM62, 10, 2))
+
+
+def test_order_independence(small_db, small_handle):
+    rng = np.random.Generator(np.random.PCG64(13))
+    q = synth.residues(rng, 120)
+    perm = rng.permutation(small_db.n_seqs)
+    pdb = synth.db_from_seqs([small_db.seq(int(k)) for k in perm])
+    base = small_handle.search(q, synth.BLOSUM62, 10, 2)
+    _say("permuted database")
+    with swmi.sw_db_load(pdb.residues, pdb.offsets, ALPHA) as h:
+        assert np.array_equal(h.search(q, synth.BLOSUM62, 10, 2), base[perm])
