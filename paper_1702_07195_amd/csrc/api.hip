@@ -198,22 +198,23 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
   return SW_OK;
 }
 
-// Strip half-height T for the inter-task kernel: the fewest padded rows, preferring
-// taller strips (fewer boundary round trips) when the padding is about equal.
+// Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
+// by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
+// at three waves per SIMD and was fastest on the full-scale search).
 int choose_T(const std::vector<int64_t> &lens) {
   const int64_t forced = g_knob_strip_rows.load();
   if (forced > 0 && inter16_supported((int)forced)) return (int)forced;
-  int best = 32;
+  struct Cand { int T; double speed; };
+  const Cand cands[] = {{24, 1.0}, {40, 0.985}, {32, 0.968}, {16, 0.89}};
+  int best = 24;
   double best_cost = 1e300;
-  for (int T : {32, 24, 16}) {
+  for (const Cand &c : cands) {
     double cost = 0;
-    for (int64_t m : lens) {
-      const int64_t strips = (m + 2 * T - 1) / (2 * T);
-      cost += (double)strips * (2.0 * T + 6.0);  // ~6 rows' worth of per-column overhead
-    }
+    for (int64_t m : lens) cost += (double)((m + 2 * c.T - 1) / (2 * c.T)) * 2.0 * c.T;
+    cost /= c.speed;
     if (cost < best_cost * 0.999) {
       best_cost = cost;
-      best = T;
+      best = c.T;
     }
   }
   return best;
@@ -496,7 +497,7 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
       g.first = (int32_t)f;
       g.count = (int32_t)std::min<int64_t>(kGroup, n_short - f);
       g.maxlen = (int32_t)len_of(order[f + g.count - 1]);
-      g.ncols = ((g.maxlen + 1 + 3) / 4) * 4;
+      g.ncols = ((g.maxlen + 2 + 3) / 4) * 4;
       g.base = bytes;
       bytes += (int64_t)g.ncols * 64;
       db->max_ncols = std::max(db->max_ncols, g.ncols);

@@ -120,17 +120,46 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
 // Persistent kernel, one wave per workgroup.  A work item is (query, group); each lane
 // aligns the query against one sequence of the group.  The query is cut into strips of
 // 2T rows.  In every 32-bit register the low int16 half holds strip rows [0, T) at
-// DB column j and the high half holds rows [T, 2T) of the same alignment at column
-// j - 1, so the hand-off from the low rows to the high rows stays in the lane.  Per
-// strip, the bottom row's (H, F) of each column goes to a per-wave boundary buffer
-// that the next strip reads back (layout [column][64 lanes] dwords: H low, F high).
+// DB column c and the high half holds rows [T, 2T) of the same alignment at column
+// c - 2, so the hand-off from the low rows to the high rows stays in the lane.  Columns
+// are processed two at a time ("lead" c and "lag" c + 1, the lag one row behind the
+// lead), which gives every wave two independent dependency chains.  Per strip, the
+// bottom row's (H, F) of each column goes to a per-wave boundary buffer that the next
+// strip reads back (layout [column][64 lanes] dwords: H low half, F high half).
 //
 // Saturation (Section 4.2): only H[i-1][j-1] + SM can exceed the int16 range, and the
 // clamped add then pins H at 32767, so the running maximum equals 32767 exactly when
 // the true score may be >= 32767.  Those alignments are appended to a list and
 // recomputed in int32; every other int16 score is exact.
-template <int T>
-__global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
+
+// (lo16 of a) | (lo16 of b) << 16
+__device__ __forceinline__ uint32_t pack_lo(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x05040100u);
+}
+// (hi16 of a) | (hi16 of b) << 16
+__device__ __forceinline__ uint32_t pack_hi(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+// (hi16 of a) | (lo16 of b) << 16
+__device__ __forceinline__ uint32_t pack_hl(uint32_t a, uint32_t b) {
+  return __builtin_amdgcn_perm(b, a, 0x05040302u);
+}
+
+// One DP cell pair (both int16 halves) of Eqs. 1-3 with E and F clamped at zero:
+// returns H; E becomes E of the next column and f becomes F of the next row.
+__device__ __forceinline__ uint32_t cell16(uint32_t hd, uint32_t sm, uint32_t &E, uint32_t &f,
+                                           uint32_t &vmax, uint32_t goe2, uint32_t ge2) {
+  const uint32_t h = pk_max(pk_max(pk_adds(hd, sm), E), f);
+  vmax = pk_max(vmax, h);
+  const uint32_t t = pk_subu(h, goe2);
+  E = pk_max(pk_subu(E, ge2), t);
+  f = pk_max(pk_subu(f, ge2), t);
+  return h;
+}
+
+template <int T, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_inter16(InterArgs a) {
   static_assert(T % 8 == 0, "strip half-height must be a multiple of 8");
   constexpr int RS = 4 * T + 16;  // LDS bytes per code row; RS/16 is odd (fewer conflicts)
   __shared__ __attribute__((aligned(16))) uint8_t lds[kCodes * RS];
@@ -151,7 +180,7 @@ __global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
     const int16_t *qp = a.qp16 + qd.qp16;
     const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
     const int nchunks = gd.ncols >> 2;
-    uint32_t vmax = 0;
+    uint32_t vmaxA = 0, vmaxB = 0;
 
     for (int s = 0; s < qd.nstrips; ++s) {
       // Stage this strip's profile slice (32 codes x 2T rows) into LDS.
@@ -173,7 +202,12 @@ __global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
       uint32_t Hs[T], Es[T];
 #pragma unroll
       for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
-      uint32_t hd0 = 0, lastH = 0, fnext = 0, prev = kPadCode;
+      // low-half outputs of earlier columns, handed to the high half two columns later
+      uint32_t hA = 0, fA = 0;   // lead of the previous pair (column c - 2)
+      uint32_t hB = 0, fB = 0;   // lag of the previous pair (column c - 1)
+      uint32_t hBB = 0;          // lag of the pair before (column c - 3)
+      uint32_t hbnd_prev = 0;    // boundary H of column c - 1
+      uint32_t rwp = 0x1f1f1f1fu;  // codes of the previous 4 columns (all padding)
 
       uint32_t rw = res[0];
       uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
@@ -189,48 +223,80 @@ __global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
           }
         }
         const uint32_t bv[4] = {b0, b1, b2, b3};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int j = c * 4 + k;
-          const uint32_t cur = (rw >> (8 * k)) & 0xffu;
-          const uint8_t *pl = lds + cur * RS;            // low rows, column j
-          const uint8_t *ph = lds + prev * RS + 2 * T;   // high rows, column j - 1
-          uint32_t hd = hd0;                              // diagonal input of row 0
-          hd0 = (bv[k] & 0xffffu) | (lastH << 16);        // (H above at j, low row T-1 at j-1)
-          uint32_t f = (bv[k] >> 16) | (fnext << 16);     // F entering row 0 of each half
-          uint32_t h = 0;
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+          const int J = c * 4 + 2 * p;  // lead column (low half); lag is J + 1
+          const uint32_t dJ = (rw >> (16 * p)) & 0xffu;
+          const uint32_t dJ1 = (rw >> (16 * p + 8)) & 0xffu;
+          const uint32_t dJm2 = p == 0 ? (rwp >> 16) & 0xffu : rw & 0xffu;
+          const uint32_t dJm1 = p == 0 ? (rwp >> 24) : (rw >> 8) & 0xffu;
+          const uint8_t *plA = lds + dJ * RS;               // lead low rows, column J
+          const uint8_t *phA = lds + dJm2 * RS + 2 * T;     // lead high rows, column J - 2
+          const uint8_t *plB = lds + dJ1 * RS;              // lag low rows, column J + 1
+          const uint8_t *phB = lds + dJm1 * RS + 2 * T;     // lag high rows, column J - 1
+          const uint32_t bJ = bv[2 * p], bJ1 = bv[2 * p + 1];
+          // row-0 inputs: low half from the boundary row, high half from the low rows
+          uint32_t hdA = pack_lo(hbnd_prev, hBB);  // H(row-1, col-1)
+          uint32_t fa = pack_hl(bJ, fA);           // F entering row 0
+          uint32_t hdB = pack_lo(bJ, hA);
+          uint32_t fb = pack_hl(bJ1, fB);
+          // Row r of the lead column runs next to row r - 1 of the lag column: the lead
+          // reads Hs[r-1] (H of column J - 1) just before the lag overwrites it with
+          // column J + 1, so every row keeps one H and one E register.
+          uint32_t ha = 0, hb = 0;
+          uint32_t dA1 = hdB, dA2 = 0;  // lead H of rows r-1 and r-2 (lag diagonals)
+          uint32_t smB_prev = 0;
 #pragma unroll
           for (int r8 = 0; r8 < T; r8 += 8) {
-            const uint4 A = *reinterpret_cast<const uint4 *>(pl + 2 * r8);
-            const uint4 B = *reinterpret_cast<const uint4 *>(ph + 2 * r8);
-            const uint32_t av[4] = {A.x, A.y, A.z, A.w};
-            const uint32_t bw[4] = {B.x, B.y, B.z, B.w};
+            // 8 profile rows per stream: one 16-byte LDS read each
+            const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 2 * r8);
+            const uint4 A2 = *reinterpret_cast<const uint4 *>(phA + 2 * r8);
+            const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 2 * r8);
+            const uint4 B2 = *reinterpret_cast<const uint4 *>(phB + 2 * r8);
+            const uint32_t a1[4] = {A1.x, A1.y, A1.z, A1.w}, a2[4] = {A2.x, A2.y, A2.z, A2.w};
+            const uint32_t b1v[4] = {B1.x, B1.y, B1.z, B1.w}, b2v[4] = {B2.x, B2.y, B2.z, B2.w};
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               const int r = r8 + q;
-              const uint32_t sm = (q & 1) ? ((av[q >> 1] >> 16) | (bw[q >> 1] & 0xffff0000u))
-                                          : ((av[q >> 1] & 0xffffu) | (bw[q >> 1] << 16));
-              h = pk_max(pk_max(pk_adds(hd, sm), Es[r]), f);   // Eq. 1 (E, F clamped >= 0)
-              vmax = pk_max(vmax, h);
-              const uint32_t t = pk_subu(h, goe2);             // H - Goe, floored at 0
-              Es[r] = pk_max(pk_subu(Es[r], ge2), t);          // Eq. 2 for column j + 1
-              f = pk_max(pk_subu(f, ge2), t);                  // Eq. 3 for row r + 1
-              hd = Hs[r];
-              Hs[r] = h;
+              const uint32_t smA = (q & 1) ? pack_hi(a1[q >> 1], a2[q >> 1])
+                                           : pack_lo(a1[q >> 1], a2[q >> 1]);
+              const uint32_t smB = (q & 1) ? pack_hi(b1v[q >> 1], b2v[q >> 1])
+                                           : pack_lo(b1v[q >> 1], b2v[q >> 1]);
+              // lead, row r
+              const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], smA, Es[r], fa, vmaxA,
+                                        goe2, ge2);
+              // lag, row r - 1 (its diagonal is the lead's H of row r - 2)
+              if (r >= 1) Hs[r - 1] = cell16(dA2, smB_prev, Es[r - 1], fb, vmaxB, goe2, ge2);
+              dA2 = dA1;
+              dA1 = h;
+              smB_prev = smB;
             }
+            __builtin_amdgcn_sched_barrier(0);
           }
-          lastH = h;
-          fnext = f;
-          // high half's bottom row finished column j - 1: hand it to the next strip
-          if (!last && j > 0) bnd[(int64_t)(j - 1) * 64] = (lastH >> 16) | (fnext & 0xffff0000u);
-          prev = cur;
+          ha = dA1;
+          hb = cell16(dA2, smB_prev, Es[T - 1], fb, vmaxB, goe2, ge2);
+          Hs[T - 1] = hb;
+          // high halves finished columns J - 2 (lead) and J - 1 (lag): hand them down
+          if (!last) {
+            if (J >= 2) bnd[(int64_t)(J - 2) * 64] = pack_hi(ha, fa);
+            if (J >= 1) bnd[(int64_t)(J - 1) * 64] = pack_hi(hb, fb);
+          }
+          hBB = hB;
+          hA = ha; fA = fa;
+          hB = hb; fB = fb;
+          hbnd_prev = bJ1;
         }
+        rwp = rw;
         rw = rwn; b0 = n0; b1 = n1; b2 = n2; b3 = n3;
       }
-      // the last column is padding; give the next strip a zero boundary there
-      if (!last) bnd[(int64_t)(gd.ncols - 1) * 64] = 0u;
+      // the last two columns are padding that the high half never reaches
+      if (!last) {
+        bnd[(int64_t)(gd.ncols - 2) * 64] = 0u;
+        bnd[(int64_t)(gd.ncols - 1) * 64] = 0u;
+      }
     }
 
+    const uint32_t vmax = pk_max(vmaxA, vmaxB);
     const int lo = (int)(int16_t)(vmax & 0xffffu);
     const int hi = (int)(int16_t)(vmax >> 16);
     const int sc = lo > hi ? lo : hi;
@@ -243,9 +309,8 @@ __global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
         it.base = gd.base + 4 * lane;
         it.cstride = 256;
         it.len = a.lens[p];
-        it.out = (int32_t)0;
-        it.query = qi;
         it.out = orig;
+        it.query = qi;
         a.flagged[k] = it;
       } else {
         a.scores[qd.out + orig] = sc;
@@ -254,9 +319,12 @@ __global__ __launch_bounds__(64) void k_inter16(InterArgs a) {
   }
 }
 
+// Minimum waves per SIMD requested from the register allocator for each strip height.
+template <int T> struct Inter16Occ { static constexpr int wpe = T <= 8 ? 6 : (T <= 16 ? 4 : (T <= 24 ? 3 : 2)); };
+
 template <int T>
 static hipError_t launch_inter16_t(const InterArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_inter16<T>, dim3(grid), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((k_inter16<T, Inter16Occ<T>::wpe>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -266,11 +334,11 @@ int inter16_max_blocks_per_cu(int T) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (T) {
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<8>, 64, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<16>, 64, 0); break;
-    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<24>, 64, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<32>, 64, 0); break;
-    case 40: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<40>, 64, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<8, Inter16Occ<8>::wpe>, 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<16, Inter16Occ<16>::wpe>, 64, 0); break;
+    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<24, Inter16Occ<24>::wpe>, 64, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<32, Inter16Occ<32>::wpe>, 64, 0); break;
+    case 40: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16<40, Inter16Occ<40>::wpe>, 64, 0); break;
     default: break;
   }
   return e == hipSuccess ? n : 0;

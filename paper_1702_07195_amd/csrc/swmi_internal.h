@@ -9,7 +9,7 @@ namespace swmi {
 
 // Residue code reserved for padding.  Its substitution score against every query
 // residue is kPadScore (<= 0), so padded columns or rows never raise a score.
-constexpr int kPadCode = 31;
+constexpr int kPadCode = 31;  // 0x1f: four padding codes fill a dword as 0x1f1f1f1f
 constexpr int kCodes = 32;          // profile rows per query position (codes 0..31)
 constexpr int kPadScore = -127;
 constexpr int kGroup = 64;          // database sequences per group (one per lane)
@@ -18,7 +18,7 @@ constexpr int kSat16 = 32767;       // int16 saturation value (overflow flag)
 
 // One group of up to 64 length-sorted database sequences.  Residues live in the packed
 // buffer at `base`, laid out [ncols/4][64 lanes][4 residues]; `ncols` is the padded
-// width (a multiple of 4, at least max length + 1, so the last column is all padding).
+// width (a multiple of 4, at least max length + 2, so the last two columns are padding).
 struct GroupDesc {
   int64_t base;
   int32_t ncols;
