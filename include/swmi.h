@@ -146,18 +146,22 @@ int sw_timing_read(const sw_db *db, int64_t *launches, double *total_ms);
 /*
  * Tuning and debug knobs (process-wide; read at the next search):
  *   SW_KNOB_INTRA_MIN_LEN  database sequences longer than this go to the intra-task
- *                          kernel (read at sw_db_load; default 12000);
+ *                          kernel (read at sw_db_load; default 8192);
  *   SW_KNOB_RECOMPUTE_ALL  non-zero: recompute every score in int32 (debug; the
  *                          result must not change);
  *   SW_KNOB_STRIP_ROWS     rows per inter-task strip (0 = automatic choice);
  *   SW_KNOB_GRID_WAVES     persistent waves per compute unit (0 = automatic);
- *   SW_KNOB_MEM_CAP_MB     refuse workspaces beyond this many MiB (0 = no cap).
+ *   SW_KNOB_MEM_CAP_MB     refuse workspaces beyond this many MiB (0 = no cap);
+ *   SW_KNOB_ROUTE_LEN      database groups whose longest sequence exceeds this go to the
+ *                          intra-task kernel for the search (0 = automatic: about twice
+ *                          the residues per inter-task lane).
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
 #define SW_KNOB_STRIP_ROWS     3
 #define SW_KNOB_GRID_WAVES     4
 #define SW_KNOB_MEM_CAP_MB     5
+#define SW_KNOB_ROUTE_LEN      6
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

@@ -25,6 +25,7 @@ std::atomic<int64_t> g_knob_recompute_all{0};
 std::atomic<int64_t> g_knob_strip_rows{0};
 std::atomic<int64_t> g_knob_grid_waves{0};
 std::atomic<int64_t> g_knob_mem_cap_mb{0};
+std::atomic<int64_t> g_knob_route_len{0};
 
 struct HipFail {
   hipError_t err;
@@ -92,6 +93,10 @@ struct sw_db {
     int32_t orig;
   };
   std::vector<LongSeq> longs;  // sorted by decreasing length
+  std::vector<GroupDesc> hgroups;   // host copy of the group table
+  std::vector<int32_t> hperm;       // host copy: sorted position -> caller index
+  std::vector<int32_t> hlens;       // host copy: sorted position -> length
+  int64_t short_residues = 0;       // residues in groups
   std::mutex mu;
   std::vector<Workspace *> pool;
   std::atomic<bool> timing{false};
@@ -222,6 +227,8 @@ int choose_T(const std::vector<int64_t> &lens) {
 
 struct Plan {
   int T = 32;
+  int32_t ngroups_inter = 0;
+  int32_t n_wide = 0;
   int grid16 = 0;
   int grid_long = 0;
   int grid_re = 0;
@@ -255,23 +262,64 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     p.qp16_elems += (int64_t)d.nstrips * kCodes * 2 * p.T;
     p.qp32_elems += (int64_t)kCodes * d.mpad32;
   }
-  for (int64_t q = 0; q < nq; ++q)
-    for (const auto &L : db->longs) {
-      PairItem it;
-      it.base = L.base;
-      it.cstride = 4;
-      it.len = L.len;
-      it.out = L.orig;
-      it.query = (int32_t)q;
-      p.longitems.push_back(it);
-    }
-
-  // launch geometry
-  const int64_t nitems16 = (int64_t)db->ngroups * nq;
+  // launch geometry of the inter-task kernel
   int per_cu = (int)g_knob_grid_waves.load();
   if (per_cu <= 0) per_cu = std::max(1, inter16_max_blocks_per_cu(p.T));
+  const int64_t lanes = (int64_t)per_cu * db->num_cu * 64;
+
+  // Route the longest groups to the intra-task kernel.  One lane runs a whole alignment
+  // in the inter-task kernel, so a group of length L costs about L * m on one wave; keep
+  // L below twice the average number of residues per lane (weighted by the number of
+  // equally long queries), else that wave becomes the critical path.
+  int64_t sum_m = 0, max_m = 1;
+  for (int64_t q = 0; q < nq; ++q) { sum_m += lens[q]; max_m = std::max(max_m, lens[q]); }
+  const double weight = (double)sum_m / (double)max_m;
+  int64_t route = (int64_t)(2.0 * (double)db->short_residues * weight / (double)lanes);
+  route = std::max<int64_t>(route, 64);
+  const int64_t forced_route = g_knob_route_len.load();
+  if (forced_route > 0) route = forced_route;
+  int32_t ninter = db->ngroups;
+  while (ninter > 0 && db->hgroups[ninter - 1].maxlen > route) --ninter;
+  p.ngroups_inter = ninter;
+
+  // intra-task items: long sequences and the sequences of routed groups, for every query;
+  // "wide" (a whole workgroup per pair) when the pair has several bands and enough
+  // columns to fill the band pipeline, else "narrow" (one wave per pair); each part
+  // longest first
+  std::vector<std::pair<double, PairItem>> wide, narrow;
+  auto add_item = [&](int64_t base, int32_t cstride, int32_t len, int32_t orig, int64_t q) {
+    PairItem it;
+    it.base = base;
+    it.cstride = cstride;
+    it.len = len;
+    it.out = orig;
+    it.query = (int32_t)q;
+    const double cost = (double)len * (double)lens[q];
+    const bool is_wide = len >= 64 * 6 * kIntraLag && p.qd[q].nbands >= 2;
+    (is_wide ? wide : narrow).emplace_back(cost, it);
+  };
+  for (int64_t q = 0; q < nq; ++q) {
+    if (lens[q] == 0) continue;
+    for (const auto &L : db->longs) add_item(L.base, 4, L.len, L.orig, q);
+    for (int32_t g = ninter; g < db->ngroups; ++g) {
+      const GroupDesc &gd = db->hgroups[g];
+      for (int32_t l = 0; l < gd.count; ++l)
+        add_item(gd.base + 4 * l, 256, db->hlens[gd.first + l], db->hperm[gd.first + l], q);
+    }
+  }
+  auto by_cost = [](const std::pair<double, PairItem> &x, const std::pair<double, PairItem> &y) {
+    return x.first > y.first;
+  };
+  std::stable_sort(wide.begin(), wide.end(), by_cost);
+  std::stable_sort(narrow.begin(), narrow.end(), by_cost);
+  p.n_wide = (int32_t)wide.size();
+  for (auto &x : wide) p.longitems.push_back(x.second);
+  for (auto &x : narrow) p.longitems.push_back(x.second);
+
+  const int64_t nitems16 = (int64_t)ninter * nq;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
-  p.grid_long = (int)std::min<int64_t>((int64_t)p.longitems.size(), 2LL * db->num_cu);
+  p.grid_long = (int)std::min<int64_t>((int64_t)wide.size() + ((int64_t)narrow.size() + kIntraWaves - 1) / kIntraWaves,
+                                       4LL * db->num_cu);
   p.grid_re = (db->n_short > 0 && nq > 0) ? db->num_cu : 0;
   const int grid32 = p.grid_long + p.grid_re;
 
@@ -279,7 +327,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const int64_t qbytes = qoff[nq];
   const size_t bnd16_slot = (size_t)db->max_ncols * 64;  // dwords
   const int bnd32_stride = ((db->max_len + 128 + 63) / 64) * 64;
-  const size_t bnd32_slot = (size_t)(kIntraWaves + 1) * bnd32_stride;
+  const size_t bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * bnd32_stride;
   const size_t need_flagged = (size_t)std::max<int64_t>(1, db->n_short * nq);
   const int64_t cap_mb = g_knob_mem_cap_mb.load();
   {
@@ -348,6 +396,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.count_dev = nullptr;
     ia.count = (int32_t)p.longitems.size();
     ia.next = &ctr->intra_next;
+    ia.next_narrow = &ctr->intra_narrow;
+    ia.n_wide = p.n_wide;
     ia.queries = (const QueryDesc *)w->qdesc.ptr;
     ia.qp32 = (const int16_t *)w->qp32.ptr;
     ia.goe = gap_open + gap_extend;
@@ -360,11 +410,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     hip_check(hipEventRecord(w->join, w->aux));
   }
 
-  if (p.grid16 > 0) {
+  if (nq > 0) {
     InterArgs ia;
     ia.packed = (const uint8_t *)db->packed.ptr;
     ia.groups = (const GroupDesc *)db->groups.ptr;
-    ia.ngroups = db->ngroups;
+    ia.ngroups = p.ngroups_inter;
     ia.nqueries = (int32_t)nq;
     ia.queries = (const QueryDesc *)w->qdesc.ptr;
     ia.qp16 = (const int16_t *)w->qp16.ptr;
@@ -394,6 +444,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.count_dev = &ctr->flagged;
     ra.count = 0;
     ra.next = &ctr->recompute_next;
+    ra.next_narrow = &ctr->recompute_narrow;
+    ra.n_wide = 0;
     ra.queries = (const QueryDesc *)w->qdesc.ptr;
     ra.qp32 = (const int16_t *)w->qp32.ptr;
     ra.goe = gap_open + gap_extend;
@@ -432,6 +484,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       g_knob_strip_rows = value; return SW_OK;
     case SW_KNOB_GRID_WAVES: if (value < 0 || value > 64) return SW_EINVAL; g_knob_grid_waves = value; return SW_OK;
     case SW_KNOB_MEM_CAP_MB: if (value < 0) return SW_EINVAL; g_knob_mem_cap_mb = value; return SW_OK;
+    case SW_KNOB_ROUTE_LEN: if (value < 0) return SW_EINVAL; g_knob_route_len = value; return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -443,6 +496,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_STRIP_ROWS: return g_knob_strip_rows.load();
     case SW_KNOB_GRID_WAVES: return g_knob_grid_waves.load();
     case SW_KNOB_MEM_CAP_MB: return g_knob_mem_cap_mb.load();
+    case SW_KNOB_ROUTE_LEN: return g_knob_route_len.load();
     default: return SW_EINVAL;
   }
 }
@@ -504,6 +558,7 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
       groups.push_back(g);
     }
     db->ngroups = (int32_t)groups.size();
+    for (int64_t p = 0; p < n_short; ++p) db->short_residues += len_of(order[p]);
     std::vector<int32_t> lens((size_t)std::max<int64_t>(1, n_short));
     for (int64_t p = 0; p < n_short; ++p) lens[p] = (int32_t)len_of(order[p]);
     for (int64_t p = n_seqs - 1; p >= n_short; --p) {  // longest first
@@ -553,6 +608,9 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
       hip_check(hipFree(d_off));
       d_off = nullptr;
     }
+    db->hgroups = std::move(groups);
+    db->hperm = std::move(order);
+    db->hlens = std::move(lens);
   } catch (const HipFail &f) {
     if (d_raw) (void)hipFree(d_raw);
     if (d_off) (void)hipFree(d_off);

@@ -51,7 +51,7 @@ __device__ __forceinline__ int32_t subu(int32_t a, int32_t b) {
 // Rows past the query end and codes outside the alphabet (including the padding code)
 // score kPadScore.
 __global__ void k_profile(ProfileArgs a) {
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 4)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < sizeof(Counters) / 4)
     reinterpret_cast<int32_t *>(a.ctr)[threadIdx.x] = 0;
   const int q = blockIdx.y;
   const QueryDesc d = a.queries[q];
@@ -167,11 +167,15 @@ void k_inter16(InterArgs a) {
   uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
   const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
   const uint32_t ge2 = (uint32_t)a.ge * 0x10001u;
+  __shared__ int s_item;
 
   for (;;) {
-    int item = 0;
-    if (lane == 0) item = atomicAdd(&a.ctr->inter_next, 1);
-    item = __builtin_amdgcn_readfirstlane(item);
+    // claim the next item: lane 0 takes it, the (single-wave) workgroup barrier makes the
+    // value visible to every lane and keeps the wave converged around the claim
+    __syncthreads();
+    if (lane == 0) s_item = atomicAdd(&a.ctr->inter_next, 1);
+    __syncthreads();
+    const int item = s_item;
     if (item >= a.nitems) break;
     const int g = a.ngroups - 1 - item / a.nqueries;  // longest groups first
     const int qi = item % a.nqueries;
@@ -357,132 +361,160 @@ hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------ intra-task
-// One (query, sequence) pair per workgroup of W waves, int32.  The query is cut into
-// bands of 64*R rows; lane l of the wave that owns band b holds rows
+// One (query, sequence) pair is swept by NW cooperating waves, int32.  The query is cut
+// into bands of 64*R rows; lane l of the wave that owns band b holds rows
 // b*64R + l*R .. + R-1 and, at step s, works on DB column s - l (an anti-diagonal
 // sweep).  After every step the bottom row's H and the F entering the next lane's
 // first row move one lane down with a DPP wave shift; lane 0 takes them from the
 // boundary row of the band above instead, and lane 63 writes its bottom row for the
-// band below.  Bands go to waves round-robin and run as a pipeline: band b starts
+// band below.  Bands go to the NW waves round-robin and run as a pipeline: band b starts
 // kIntraLag chunks (of 64 steps) after band b-1, with a workgroup barrier after every
 // chunk, so every boundary value a band reads was written at least one barrier earlier.
-// Columns outside [0, n) carry the padding code and a zero boundary, which leaves every
+// With NW = 1 a single wave runs the bands in order and needs no barrier.  Columns
+// outside [0, n) carry the padding code and a zero boundary, which leaves every
 // in-range cell unchanged and never raises the maximum.
 __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
   // lanes 1..63 receive src from lane - 1; lane 0 keeps lane0_value
   return __builtin_amdgcn_update_dpp(lane0_value, src, 0x138, 0xf, 0xf, false);
 }
 
+// Returns this lane's running maximum of H over the cells it computed.  `ring` holds
+// NW + 1 band-boundary buffers of a.bnd_stride (H, F) pairs.
+template <int R, int NW>
+__device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const QueryDesc &qd,
+                              int w, int2 *ring) {
+  const int lane = threadIdx.x & 63;
+  const int n = pi.len;
+  const int nb = qd.nbands;
+  int32_t vmax = 0;
+  if (n <= 0 || nb <= 0) return 0;
+  const int nc = (n + 63 + 63) / 64;  // chunks covering n + 63 steps
+  const int nce = nc > kIntraLag * NW ? nc : kIntraLag * NW;
+  const int lastb = nb - 1;
+  const int rounds = (lastb / NW) * nce + kIntraLag * (lastb % NW) + nc;
+  const uint8_t *resbase = a.packed + pi.base;
+  const int cs = pi.cstride;
+
+  int b = w;  // band this wave works on
+  int32_t Hs[R], Es[R];
+  int32_t hbot = 0, fbot = 0, hdiag = 0, code = kPadCode;
+  int2 tq = make_int2(0, 0);  // band-top (H, F) for columns 64k + lane
+  int rq = kPadCode;          // residue of column 64k + lane
+#pragma unroll
+  for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
+
+  for (int rd = 0; rd < rounds; ++rd) {
+    if (b < nb) {
+      const int st = (b / NW) * nce + kIntraLag * (b % NW);
+      if (rd >= st && rd < st + nc) {
+        const int k = rd - st;
+        const int2 *top = ring + (int64_t)((b + NW) % (NW + 1)) * a.bnd_stride;
+        int2 *bot = ring + (int64_t)(b % (NW + 1)) * a.bnd_stride;
+        const bool has_top = b > 0, has_bot = b < nb - 1;
+        if (k == 0) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
+          hbot = 0; fbot = 0; hdiag = 0; code = kPadCode;
+          tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
+          rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
+        }
+        const int col_next = 64 * (k + 1) + lane;
+        const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
+        const int rq_next = col_next < n
+            ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
+        const int16_t *prof = a.qp32 + qd.qp32 + (int64_t)b * 64 * R + lane * R;
+
+        for (int i = 0; i < 64; ++i) {
+          const int s = 64 * k + i;
+          code = wave_shr1(code, __builtin_amdgcn_readlane(rq, i));
+          const int hup = wave_shr1(hbot, __builtin_amdgcn_readlane(tq.x, i));
+          int f = wave_shr1(fbot, __builtin_amdgcn_readlane(tq.y, i));
+          int hd = hdiag;
+          hdiag = hup;
+          const uint4 *pp = reinterpret_cast<const uint4 *>(prof + (int64_t)code * qd.mpad32);
+          int h = 0;
+#pragma unroll
+          for (int r8 = 0; r8 < R; r8 += 8) {
+            const uint4 P = pp[r8 >> 3];
+            const uint32_t pv[4] = {P.x, P.y, P.z, P.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int r = r8 + q;
+              const int sm = (q & 1) ? ((int32_t)pv[q >> 1] >> 16)
+                                     : (int32_t)(int16_t)(pv[q >> 1] & 0xffffu);
+              h = max(max(hd + sm, Es[r]), f);          // Eq. 1 (E, F clamped >= 0)
+              vmax = max(vmax, h);
+              const int t = subu(h, a.goe);
+              Es[r] = max(subu(Es[r], a.ge), t);        // Eq. 2
+              f = max(subu(f, a.ge), t);                // Eq. 3
+              hd = Hs[r];
+              Hs[r] = h;
+            }
+          }
+          hbot = h;
+          fbot = f;
+          if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
+        }
+        tq = tq_next;
+        rq = rq_next;
+        if (k == nc - 1) b += NW;
+      }
+    }
+    if (NW > 1) __syncthreads();
+  }
+  return vmax;
+}
+
+// Items [0, n_wide) are swept by a whole workgroup each ("wide"); items [n_wide, count)
+// by a single wave each ("narrow").  Each workgroup first takes wide items, then its waves
+// take narrow items independently.
 template <int R, int W>
 __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
-  static_assert(R % 8 == 0, "rows per lane must be a multiple of 8");
   __shared__ int s_item;
   __shared__ int s_max[W];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  int2 *ring = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_elems;
+  int2 *slot = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_elems;
+  const int count = a.count_dev ? *a.count_dev : a.count;
+  const int n_wide = a.n_wide < count ? a.n_wide : count;
 
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) {
-      const int count = a.count_dev ? *a.count_dev : a.count;
       const int it = atomicAdd(a.next, 1);
-      s_item = it < count ? it : -1;
+      s_item = it < n_wide ? it : -1;
     }
     __syncthreads();
     const int it = s_item;
     if (it < 0) break;
     const PairItem pi = a.items[it];
     const QueryDesc qd = a.queries[pi.query];
-    const int n = pi.len;
-    const int nb = qd.nbands;
-    int32_t vmax = 0;
-
-    if (n > 0 && nb > 0) {
-      const int nc = (n + 63 + 63) / 64;                 // chunks covering n + 63 steps
-      const int nce = nc > kIntraLag * W ? nc : kIntraLag * W;
-      const int lastb = nb - 1;
-      const int rounds = (lastb / W) * nce + kIntraLag * (lastb % W) + nc;
-      const uint8_t *resbase = a.packed + pi.base;
-      const int cs = pi.cstride;
-
-      int b = w;                       // band this wave works on
-      int32_t Hs[R], Es[R];
-      int32_t hbot = 0, fbot = 0, hdiag = 0, code = kPadCode;
-      int2 tq = make_int2(0, 0);       // band-top (H, F) for columns 64k + lane
-      int rq = kPadCode;               // residue of column 64k + lane
-#pragma unroll
-      for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
-
-      for (int rd = 0; rd < rounds; ++rd) {
-        if (b < nb) {
-          const int st = (b / W) * nce + kIntraLag * (b % W);
-          if (rd >= st && rd < st + nc) {
-            const int k = rd - st;
-            const int2 *top = ring + (int64_t)((b + W) % (W + 1)) * a.bnd_stride;
-            int2 *bot = ring + (int64_t)(b % (W + 1)) * a.bnd_stride;
-            const bool has_top = b > 0, has_bot = b < nb - 1;
-            if (k == 0) {
-#pragma unroll
-              for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
-              hbot = 0; fbot = 0; hdiag = 0; code = kPadCode;
-              tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
-              rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
-            }
-            const int col_next = 64 * (k + 1) + lane;
-            const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
-            const int rq_next = col_next < n
-                ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
-            const int16_t *prof = a.qp32 + qd.qp32 + (int64_t)b * 64 * R + lane * R;
-
-            for (int i = 0; i < 64; ++i) {
-              const int s = 64 * k + i;
-              code = wave_shr1(code, __builtin_amdgcn_readlane(rq, i));
-              const int hup = wave_shr1(hbot, __builtin_amdgcn_readlane(tq.x, i));
-              int f = wave_shr1(fbot, __builtin_amdgcn_readlane(tq.y, i));
-              int hd = hdiag;
-              hdiag = hup;
-              const uint4 *pp = reinterpret_cast<const uint4 *>(prof + (int64_t)code * qd.mpad32);
-              int h = 0;
-#pragma unroll
-              for (int r8 = 0; r8 < R; r8 += 8) {
-                const uint4 P = pp[r8 >> 3];
-                const uint32_t pv[4] = {P.x, P.y, P.z, P.w};
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                  const int r = r8 + q;
-                  const int sm = (q & 1) ? ((int32_t)pv[q >> 1] >> 16)
-                                         : (int32_t)(int16_t)(pv[q >> 1] & 0xffffu);
-                  h = max(max(hd + sm, Es[r]), f);          // Eq. 1 (E, F clamped >= 0)
-                  vmax = max(vmax, h);
-                  const int t = subu(h, a.goe);
-                  Es[r] = max(subu(Es[r], a.ge), t);        // Eq. 2
-                  f = max(subu(f, a.ge), t);                // Eq. 3
-                  hd = Hs[r];
-                  Hs[r] = h;
-                }
-              }
-              hbot = h;
-              fbot = f;
-              if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
-            }
-            tq = tq_next;
-            rq = rq_next;
-            if (k == nc - 1) b += W;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // workgroup max
+    int32_t vmax = intra_pair<R, W>(a, pi, qd, w, slot);
     for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
     if (lane == 0) s_max[w] = vmax;
     __syncthreads();
     if (threadIdx.x == 0) {
       int m = 0;
       for (int i = 0; i < W; ++i) m = max(m, s_max[i]);
-      a.scores[a.queries[pi.query].out + pi.out] = m;
+      a.scores[qd.out + pi.out] = m;
     }
+  }
+
+  // Narrow phase.  The waves run independently, so the claim cannot go through LDS and a
+  // barrier.  It must not sit in a lane-0-only branch either: the compiler may then split
+  // the wave across the loop back-edge and let lanes 1..63 re-read a stale item forever.
+  // Every lane therefore executes the atomic (adding 1 from lane 0, 0 elsewhere; lane 0
+  // gets the old value), and every lane stores the same reduced score.
+  int2 *ring = slot + (int64_t)w * 2 * a.bnd_stride;  // two band buffers per wave
+  for (;;) {
+    const int claimed = atomicAdd(a.next_narrow, lane == 0 ? 1 : 0);
+    const int it = __builtin_amdgcn_readfirstlane(claimed) + n_wide;
+    if (it >= count) break;
+    const PairItem pi = a.items[it];
+    const QueryDesc qd = a.queries[pi.query];
+    int32_t vmax = intra_pair<R, 1>(a, pi, qd, 0, ring);
+    for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
+    a.scores[qd.out + pi.out] = vmax;
   }
 }
 

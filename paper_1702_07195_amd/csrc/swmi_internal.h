@@ -52,8 +52,11 @@ struct QueryDesc {
 struct Counters {
   int32_t inter_next;     // next inter-task work item
   int32_t flagged;        // number of saturated pairs appended to the recompute list
-  int32_t intra_next;     // next intra-task work item (long list)
-  int32_t recompute_next; // next intra-task work item (recompute list)
+  int32_t intra_next;     // next wide intra-task item (long list)
+  int32_t recompute_next; // next wide intra-task item (recompute list)
+  int32_t intra_narrow;   // next narrow intra-task item (long list)
+  int32_t recompute_narrow;  // next narrow intra-task item (recompute list)
+  int32_t pad[2];
 };
 
 struct InterArgs {
@@ -80,13 +83,15 @@ struct IntraArgs {
   const PairItem *items;     // static list (long sequences) or recompute list
   const int32_t *count_dev;  // if non-null, the item count is read here (recompute list)
   int32_t count;             // otherwise the item count
-  int32_t *next;             // work counter
+  int32_t *next;             // work counter of the wide items
+  int32_t *next_narrow;      // work counter of the narrow items
+  int32_t n_wide;            // items [0, n_wide) take a whole workgroup each
   const QueryDesc *queries;
   const int16_t *qp32;
   int32_t goe, ge;
   int32_t *scores;
   int2 *bnd;                 // band boundary scratch, one slot per persistent workgroup
-  int64_t bnd_slot_elems;    // int2 elements per slot
+  int64_t bnd_slot_elems;    // int2 elements per slot (>= 2 * waves * bnd_stride)
   int32_t bnd_stride;        // int2 elements per band buffer (>= max len + 128)
 };
 
@@ -123,7 +128,7 @@ hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStr
 bool inter16_supported(int T);
 int inter16_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
-constexpr int kIntraWaves = 4;
+constexpr int kIntraWaves = 8;
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
 
 }  // namespace swmi

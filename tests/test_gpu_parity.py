@@ -41,11 +41,32 @@ def _oracle(q, db, sm, go, ge):
     return oracle.search(q, db.residues, db.offsets, sm, go, ge)
 
 
-@pytest.mark.parametrize("m", [1, 5, 31, 32, 33, 47, 48, 64, 65, 144, 200, 511])
-def test_query_lengths_blosum62(small_db, small_handle, m):
+# Search-time routing of long groups: everything through the inter-task kernel, the
+# automatic threshold, or everything through the intra-task kernel.
+ROUTES = {"inter": 1 << 30, "auto": 0, "intra": 1}
+
+
+@pytest.fixture(params=sorted(ROUTES))
+def route(request):
+    old = swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN)
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, ROUTES[request.param])
+    yield request.param
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
+
+
+@pytest.fixture
+def inter_only():
+    old = swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN)
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1 << 30)
+    yield
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
+
+
+@pytest.mark.parametrize("m", [1, 5, 31, 32, 33, 47, 48, 64, 65, 144, 200, 511, 1025, 2100])
+def test_query_lengths_blosum62(small_db, small_handle, m, route):
     rng = np.random.Generator(np.random.PCG64(1000 + m))
     q = synth.residues(rng, m)
-    _say(f"search m={m}")
+    _say(f"search m={m} route={route}")
     got = small_handle.search(q, synth.BLOSUM62, 10, 2)
     assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
 
@@ -54,7 +75,7 @@ def test_query_lengths_blosum62(small_db, small_handle, m):
                                         ("BLOSUM50", 11, 1), ("BLOSUM62", 0, 0),
                                         ("BLOSUM62", 0, 5), ("BLOSUM62", 40, 0),
                                         ("BLOSUM62", 16383, 0)])
-def test_matrices_and_gaps(small_db, small_handle, mat, go, ge):
+def test_matrices_and_gaps(small_db, small_handle, mat, go, ge, route):
     rng = np.random.Generator(np.random.PCG64(77))
     q = synth.residues(rng, 180)
     sm = synth.MATRICES[mat]
@@ -76,7 +97,7 @@ def test_asymmetric_small_alphabet():
 
 
 @pytest.mark.parametrize("T", [8, 16, 24, 32, 40])
-def test_strip_heights_agree(small_db, small_handle, T):
+def test_strip_heights_agree(small_db, small_handle, T, inter_only):
     rng = np.random.Generator(np.random.PCG64(5))
     q = synth.residues(rng, 150)
     swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, T)
@@ -88,7 +109,7 @@ def test_strip_heights_agree(small_db, small_handle, T):
     assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
 
 
-def test_recompute_all_changes_nothing(small_db, small_handle):
+def test_recompute_all_changes_nothing(small_db, small_handle, route):
     rng = np.random.Generator(np.random.PCG64(6))
     q = synth.residues(rng, 260)
     swmi.set_knob(swmi.SW_KNOB_RECOMPUTE_ALL, 1)
@@ -115,7 +136,7 @@ def test_long_route_threshold(small_db, cut):
     assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
 
 
-def test_saturation_and_exact_recompute():
+def test_saturation_and_exact_recompute(route):
     # SM(a, a) = 7: a^4680 scores 32760 (exact in int16), a^4681 = 32767 and
     # a^4682 = 32774 saturate and must be recomputed exactly in int32; neighbours in the
     # same group keep their int16 scores.
@@ -160,7 +181,7 @@ def test_bad_search_arguments(small_handle):
         small_handle.search(synth.encode("ACD"), synth.BLOSUM62, 16383, 1)
 
 
-def test_batch_equals_separate(small_db, small_handle):
+def test_batch_equals_separate(small_db, small_handle, route):
     qs = synth.batched_queries(6, 1, 400, seed=11)
     _say("batched search of 6 queries")
     got = small_handle.search_batch(qs, synth.BLOSUM62, 10, 2)
