@@ -1,17 +1,25 @@
-"""Benchmark: GCUPS of the full-scale plain database search on one MI355X.
+"""Benchmark: GCUPS of Smith-Waterman database search on one MI355X.
 
-Workload (synthetic stand-in for the paper's Environmental NR search, Section 5.1):
-6,000,000 database sequences (log-normal lengths, median 200, sigma 0.8, clipped to
-10..8000; about 1.65e9 residues at Robinson-Robinson frequencies) searched with six
-synthetic queries of lengths 144, 375, 729, 1000, 2005 and 5478; BLOSUM62, gap open 10,
-gap extend 2.  One step is one search of every query against the whole database (all
-stages of the path: query profiles, packed-int16 inter-task kernel, saturation recompute,
-scores in the caller's order in HBM).  GCUPS = sum(|Q|) * |D| / t (Section 5.2, Eq. 4),
-with |D| the unpadded residue count.
+Default workload (the headline; synthetic stand-in for the Environmental NR search of
+Section 5.1): 6,000,000 database sequences (log-normal lengths, median 200, sigma 0.8,
+clipped to 10..8000; about 1.65e9 residues at Robinson-Robinson frequencies) searched
+with six synthetic queries of lengths 144, 375, 729, 1000, 2005 and 5478; BLOSUM62, gap
+open 10, gap extend 2.  One step is one search of every query against the whole
+database (all stages of the path: query profiles, packed-int16 inter-task kernel,
+intra-task kernel for routed sequences, saturation recompute, scores in the caller's
+order in HBM).  GCUPS = sum(|Q|) * |D| / t (Section 5.2, Eq. 4), |D| the unpadded
+residue count.
 
-Prints one JSON line.  Extra fields: per-query-length GCUPS, a roofline object for the
-inter-task kernel (timed with HIP events on its own stream) and the CPU oracle timed on
-a bounded sample of the same workload.
+Other workloads (``--workload``): ``plain`` (2,000 sequences, one query of 144),
+``long_mix`` (10,000 sequences, 1% of them 10,000..35,000 long; queries 5478 and
+35000), ``batched`` (200,000 sequences, 64 queries of lengths 50..5000 in one captured
+HIP graph; BLOSUM62/BLOSUM50 x gaps 10/2 and 11/1).  Serving is measured by
+``--workload served`` (open-loop Poisson arrivals at 2, 8 and 32 queries/s against
+a resident 4.35e6-sequence database through the continuous-batching server; p50/p99
+latency).
+
+Prints one JSON line with a roofline object for the dominant kernel (timed with HIP
+events on the stream that launches it) and the CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -27,11 +35,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# int16 algorithmic operations per DP cell (Section 2, Eqs. 1-3): H-Goe, E-Ge and max,
-# F-Ge and max, H(diag)+SM, three maxima for H, running maximum.
+# Algorithmic operations per DP cell (Section 2, Eqs. 1-3): H-Goe, E-Ge and max, F-Ge and
+# max, H(diag)+SM, three maxima for H, running maximum.
 OPS_PER_CELL = 10
-# Packed-int16 VALU peak of MI355X: 256 CUs x 64 lanes x 2 halves x 2.4 GHz.
-PEAK_INT16_TOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+# VALU peaks of MI355X: 256 CUs x 64 lanes x 2.4 GHz, x2 for packed int16 halves.
+PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
+PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_07195_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "inter16_full_scale_traffic.json")
 
@@ -41,7 +50,7 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(per_launch_cells: float):
+def load_traffic():
     """HBM bytes per launch from committed PMC runs, if taken on the current kernel."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -54,15 +63,14 @@ def load_traffic(per_launch_cells: float):
 
 
 def cpu_baseline(db, queries, sm, go, ge, gpu_scores, budget_cells: float):
-    """Time the oracle on a stratified sample of sequences (all queries), and check the
-    sampled GPU scores against it bit for bit."""
+    """Time the oracle on a length-stratified sample of sequences (all queries) and check
+    the sampled GPU scores against it bit for bit."""
     import oracle
-    from paper_1702_07195_amd import synth  # noqa: F401
 
     lengths = db.lengths
     order = np.argsort(lengths, kind="stable")
-    per_seq = float(sum(len(q) for q in queries)) * float(lengths.mean())
-    n = int(max(64, min(len(order), budget_cells / max(per_seq, 1.0))))
+    per_seq = float(sum(len(q) for q in queries)) * float(max(lengths.mean(), 1.0))
+    n = int(max(16, min(len(order), budget_cells / max(per_seq, 1.0))))
     idx = order[np.linspace(0, len(order) - 1, n).astype(np.int64)]
     threads = os.cpu_count() or 1
     cells = 0
@@ -73,36 +81,48 @@ def cpu_baseline(db, queries, sm, go, ge, gpu_scores, budget_cells: float):
         exact &= bool(np.array_equal(want, g[idx]))
         cells += len(q) * int(lengths[idx].sum())
     dt = time.perf_counter() - t0
-    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} database sequences (stratified by length) x all {len(queries)} "
+    return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} database sequences (stratified by length) x {len(queries)} "
                       f"queries, {cells:.3e} cells, {dt:.1f} s"}, exact
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--seqs", type=int, default=None, help="override database size (testing)")
-    ap.add_argument("--cpu-cells", type=float, default=1.2e10,
-                    help="oracle sample size in cells (about 10-30 s on the host)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="also run one plain device copy of this many MiB (calibrates the "
-                         "HBM byte counters of a profiler run)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the database would be sharded across GPUs as described in DESIGN.md",
-              file=sys.stderr)
-        sys.exit(2)
+def roofline(kernel: str, cells_per_launch: float, launches: int, total_ms: float,
+             int16: bool, traffic=None):
+    avg_s = total_ms / max(launches, 1) / 1e3
+    if avg_s <= 0:
+        return None
+    achieved = OPS_PER_CELL * cells_per_launch / avg_s / 1e12
+    peak = PEAK_INT16_TOPS if int16 else PEAK_INT32_TOPS
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
+            "unit": "Tops/s (int16)" if int16 else "Tops/s (int32)",
+            "frac": round(achieved / peak, 3), "traffic": traffic, "kernel": kernel,
+            "avg_launch_ms": round(avg_s * 1e3, 3), "launches": launches}
 
+
+def base_result(args, value, elapsed, dtype, config):
+    return {
+        "metric": "GCUPS per query length (1 GPU, bit-exact)",
+        "value": round(value, 1),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+    }
+
+
+def run_searches(args, w, db, queries):
+    """Time `steps` passes of single-query searches (device-resident outputs)."""
     import torch
     from paper_1702_07195_amd import swmi, synth
 
-    w = synth.FULL_SCALE if args.seqs is None else synth.scaled(synth.FULL_SCALE, args.seqs)
-    db = w.make_db()
-    queries = w.make_queries()
     sm, go, ge = w.matrix_values, w.gap_open, w.gap_extend
     D = int(db.offsets[-1])
     h = swmi.sw_db_load(db.residues, db.offsets, len(synth.ALPHABET))
@@ -136,51 +156,222 @@ def main():
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches, kernel_ms = h.timing_read()
+    timing = {k: h.timing_read(k) for k in (swmi.SW_KERNEL_INTER16, swmi.SW_KERNEL_INTRA_LONG,
+                                             swmi.SW_KERNEL_RECOMPUTE)}
     h.timing_enable(False)
-
-    # per-query-length GCUPS (separate pass, each query synchronised on its own)
     per_q = [0.0] * len(queries)
     step(per_q)
     per_query = {str(len(q)): round(len(q) * D / per_q[k] / 1e9, 1)
                  for k, q in enumerate(queries)}
+    scores = [o.cpu().numpy() for o in outs]
+    h.free()
+    return elapsed, timing, per_query, scores
 
+
+def bench_search(args, w, label):
+    from paper_1702_07195_amd import swmi
+
+    db = w.make_db()
+    queries = w.make_queries()
+    D = int(db.offsets[-1])
+    elapsed, timing, per_query, scores = run_searches(args, w, db, queries)
     cells_per_step = sum(len(q) for q in queries) * D
     gcups = cells_per_step * args.steps / elapsed / 1e9
-    cells_per_launch = cells_per_step / len(queries)
-    avg_launch_s = kernel_ms / max(launches, 1) / 1e3
-    achieved = OPS_PER_CELL * cells_per_launch / avg_launch_s / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_INT16_TOPS, 2),
-                "unit": "Tops/s (int16)", "frac": round(achieved / PEAK_INT16_TOPS, 3),
-                "traffic": load_traffic(cells_per_launch),
-                "kernel": "k_inter16", "avg_launch_ms": round(avg_launch_s * 1e3, 3),
-                "launches": launches}
-
-    result = {
-        "metric": "GCUPS per query length (1 GPU, bit-exact)",
-        "value": round(gcups, 1),
-        "unit": "GCUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "i16",
-        "data": "synthetic",
-        "config": {"workload": "full-scale plain search", "db_seqs": db.n_seqs,
-                   "db_residues": D, "query_lengths": [len(q) for q in queries],
-                   "matrix": w.matrix, "gap_open": go, "gap_extend": ge},
-        "per_query_gcups": per_query,
-        "roofline": roofline,
-    }
+    n16, ms16 = timing[swmi.SW_KERNEL_INTER16]
+    nlo, mslo = timing[swmi.SW_KERNEL_INTRA_LONG]
+    # the dominant kernel is the one with more device time; its cells are estimated from
+    # the share of the database it covers (inter-task: all, when nothing is routed)
+    if ms16 >= mslo:
+        roof = roofline("k_inter16", cells_per_step / len(queries), n16, ms16, True,
+                        load_traffic() if label == "full-scale plain search" else None)
+    else:
+        roof = roofline("k_intra32 (long and routed sequences)", cells_per_step / len(queries),
+                        nlo, mslo, False, None)
+        if roof is not None:
+            roof["note"] = ("cells counted over the whole database; the inter-task kernel "
+                            "runs concurrently on the rest")
+    config = {"workload": label, "db_seqs": db.n_seqs, "db_residues": D,
+              "query_lengths": [len(q) for q in queries], "matrix": w.matrix,
+              "gap_open": w.gap_open, "gap_extend": w.gap_extend}
+    result = base_result(args, gcups, elapsed, "i16+i32", config)
+    result["per_query_gcups"] = per_query
+    result["roofline"] = roof
+    result["kernel_ms_per_step"] = {
+        "k_inter16": round(ms16 / args.steps, 3),
+        "k_intra32_long": round(mslo / args.steps, 3),
+        "k_intra32_recompute": round(timing[swmi.SW_KERNEL_RECOMPUTE][1] / args.steps, 3)}
     if not args.no_cpu:
-        gpu_scores = [o.cpu().numpy() for o in outs]
-        base, exact = cpu_baseline(db, queries, sm, go, ge, gpu_scores, args.cpu_cells)
+        base, exact = cpu_baseline(db, queries, w.matrix_values, w.gap_open, w.gap_extend,
+                                   scores, args.cpu_cells)
+        result["cpu_baseline"] = base
+        result["bit_exact_sample"] = exact
+    return result
+
+
+def bench_batched(args):
+    import torch
+    from paper_1702_07195_amd import swmi, synth
+
+    w = synth.BATCHED
+    db = w.make_db()
+    qs = synth.batched_queries(64)
+    D = int(db.offsets[-1])
+    cells = sum(len(q) for q in qs) * D
+    h = swmi.sw_db_load(db.residues, db.offsets, len(synth.ALPHABET))
+    out = torch.zeros((len(qs), db.n_seqs), dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    variants = {}
+    total_t = 0.0
+    n16_all, ms16_all = 0, 0.0
+    last_scores = None
+    for mat in ("BLOSUM62", "BLOSUM50"):
+        for go, ge in ((10, 2), (11, 1)):
+            sm = synth.MATRICES[mat]
+            with h.plan(qs, sm, go, ge, out) as plan:
+                for _ in range(args.warmup):
+                    plan.launch(stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    plan.launch(stream)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            variants[f"{mat} {go}/{ge}"] = round(cells * args.steps / dt / 1e9, 1)
+            total_t += dt
+            if mat == "BLOSUM62" and (go, ge) == (10, 2):
+                last_scores = out.cpu().numpy()
+    # kernel timing of one graph replay, measured eagerly with the same batch
+    sm = synth.BLOSUM62
+    h.timing_enable(True)
+    scores_host = h.search_batch(qs, sm, 10, 2)
+    n16, ms16 = h.timing_read(swmi.SW_KERNEL_INTER16)
+    h.timing_enable(False)
+    gcups = 4 * cells * args.steps / total_t / 1e9
+    config = {"workload": "batched (64 queries, hipGraph replay)", "db_seqs": db.n_seqs,
+              "db_residues": D, "n_queries": len(qs), "query_lengths": "U{50..5000}",
+              "matrices": ["BLOSUM62", "BLOSUM50"], "gaps": ["10/2", "11/1"]}
+    result = base_result(args, gcups, total_t / 4, "i16+i32", config)
+    result["per_variant_gcups"] = variants
+    result["roofline"] = roofline("k_inter16", cells, n16, ms16, True, None)
+    result["graph_equals_eager"] = bool(np.array_equal(last_scores, scores_host))
+    if not args.no_cpu:
+        base, exact = cpu_baseline(db, qs[:8], sm, 10, 2, list(scores_host[:8]),
+                                   args.cpu_cells)
         result["cpu_baseline"] = base
         result["bit_exact_sample"] = exact
     h.free()
+    return result
+
+
+def bench_served(args):
+    """Open-loop Poisson arrivals against the resident database through the
+    continuous-batching server; p50/p99 latency and achieved GCUPS per rate."""
+    import threading
+    from paper_1702_07195_amd import swmi, synth
+
+    w = synth.SERVED if args.seqs is None else synth.scaled(synth.SERVED, args.seqs)
+    db = w.make_db()
+    D = int(db.offsets[-1])
+    sm, go, ge = w.matrix_values, w.gap_open, w.gap_extend
+    h = swmi.sw_db_load(db.residues, db.offsets, len(synth.ALPHABET))
+    rates = [float(r) for r in args.rates.split(",")]
+    per_rate = {}
+    check = None
+    for ri, rate in enumerate(rates):
+        n = args.requests
+        queries = synth.served_queries(n, seed=1702_1004 + ri)
+        arrivals = synth.poisson_arrivals(n, rate, seed=1702_2004 + ri)
+        results = [None] * n
+        with swmi.SwServer(h, sm, go, ge, slots=args.slots, max_batch=args.max_batch,
+                           mem_budget_bytes=int(args.mem_budget_gib * (1 << 30))) as sv:
+            # warm the slots (workspaces) before timing
+            for t in [sv.submit(queries[0]) for _ in range(args.slots)]:
+                sv.wait(t)
+            tickets = [None] * n
+            t0 = time.perf_counter()
+
+            def submitter():
+                for k in range(n):
+                    delay = t0 + arrivals[k] - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                    tickets[k] = sv.submit(queries[k])
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            th.join()
+            for k in range(n):
+                results[k] = sv.wait(tickets[k])
+            t_end = time.perf_counter()
+            stats = sv.stats()
+        lat = np.array([r[1] for r in results])
+        cells = sum(len(q) for q in queries) * D
+        per_rate[f"{rate:g}"] = {
+            "requests": n, "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mean_queue_ms": round(float(np.mean([r[2] for r in results])), 2),
+            "achieved_gcups": round(cells / (t_end - t0) / 1e9, 1),
+            "offered_gcups": round(rate * float(np.mean([len(q) for q in queries])) * D / 1e9, 1),
+            "launches": stats["launches"], "max_batches_in_flight": stats["max_in_flight"]}
+        if check is None:
+            # the same queries searched alone must give the same scores as in the mix
+            check = all(np.array_equal(h.search(queries[k], sm, go, ge), results[k][0])
+                        for k in range(min(4, n)))
+    mid = per_rate[f"{rates[len(rates) // 2]:g}"]
+    config = {"workload": "served (open-loop Poisson arrivals, continuous batching)",
+              "db_seqs": db.n_seqs, "db_residues": D, "query_lengths": "log-normal median 350",
+              "rates_per_s": rates, "slots": args.slots, "max_batch": args.max_batch,
+              "matrix": w.matrix, "gap_open": go, "gap_extend": ge}
+    result = base_result(args, mid["achieved_gcups"], 0.0, "i16+i32", config)
+    result["steps"] = args.requests
+    result["ms_per_step"] = mid["p50_ms"]
+    result["serving"] = per_rate
+    result["alone_equals_mix"] = bool(check)
+    result["roofline"] = None
+    h.free()
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="full",
+                    choices=["full", "plain", "long_mix", "batched", "served"])
+    ap.add_argument("--rates", default="2,8,32", help="served: arrival rates per second")
+    ap.add_argument("--requests", type=int, default=48, help="served: requests per rate")
+    ap.add_argument("--slots", type=int, default=2, help="served: stream slots")
+    ap.add_argument("--max-batch", type=int, default=8, help="served: queries per launch")
+    ap.add_argument("--mem-budget-gib", type=float, default=64.0,
+                    help="served: device memory budget of the batches in flight")
+    ap.add_argument("--seqs", type=int, default=None, help="override database size (testing)")
+    ap.add_argument("--cpu-cells", type=float, default=2.5e10,
+                    help="oracle sample size in cells (about 10-30 s on the host)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (calibrates the "
+                         "HBM byte counters of a profiler run)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the database would be sharded across GPUs as described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1702_07195_amd import synth
+
+    if args.workload == "batched":
+        result = bench_batched(args)
+    elif args.workload == "served":
+        result = bench_served(args)
+    else:
+        w, label = {"full": (synth.FULL_SCALE, "full-scale plain search"),
+                    "plain": (synth.PLAIN, "plain search"),
+                    "long_mix": (synth.LONG_MIX, "long-sequence mix")}[args.workload]
+        if args.seqs is not None:
+            w = synth.scaled(w, args.seqs)
+        result = bench_search(args, w, label)
     print(json.dumps(result), flush=True)
 
 

@@ -130,6 +130,65 @@ int sw_search_batch(const sw_db *db, const uint8_t *queries, const int64_t *quer
                     int64_t n_queries, const int32_t *matrix, int32_t gap_open,
                     int32_t gap_extend, int32_t *scores_out);
 
+/*
+ * Plans: a search captured once into a HIP graph and replayed.
+ *
+ * sw_plan_create runs the (batched) search once, sizing a workspace that the plan owns,
+ * then captures the whole launch sequence of the search (query profiles, inter-task
+ * kernel, intra-task kernel on a second stream, saturation recompute) into a hipGraph.
+ * Arguments are those of sw_search_batch, except that the scores go to device memory:
+ *   scores_dev  device, int32[n_queries * sw_db_size(db)], written by the eager run and
+ *               by every replay (row q = query q, caller's database order).
+ * The queries, matrix and penalties are copied; the caller may reuse its buffers.  The
+ * plan keeps using scores_dev and the database until sw_plan_free.  Knob values in force
+ * at creation (strip height, waves per CU, routing) are baked into the plan.
+ * sw_plan_launch enqueues one replay on hip_stream (NULL = default stream); replays on
+ * different streams must not overlap (they share the plan's workspace).
+ * Errors: as for sw_search_batch; SW_EINVAL for a NULL plan.
+ */
+typedef struct sw_plan sw_plan;
+int sw_plan_create(const sw_db *db, const uint8_t *queries, const int64_t *query_offsets,
+                   int64_t n_queries, const int32_t *matrix, int32_t gap_open,
+                   int32_t gap_extend, int32_t *scores_dev, sw_plan **out);
+int sw_plan_launch(sw_plan *plan, void *hip_stream);
+void sw_plan_free(sw_plan *plan);
+
+/*
+ * Serving: continuous batching over a resident database (not in the paper, whose queries
+ * run one after another).
+ *
+ * sw_server_create starts a worker thread that owns `slots` stream slots (1..16), each
+ * with its own device workspace.  Queries submitted with sw_server_submit wait in a FIFO
+ * queue; whenever a slot is free, the worker launches every queued query it can admit
+ * (at most `max_batch`, 1..4096, and, if `mem_budget_bytes` > 0, only while the device
+ * bytes of all batches in flight stay within the budget) as one batched search, so
+ * requests that arrive while others are on the GPU join the next launch and run next to
+ * them on the device.  A query that alone exceeds the budget completes with SW_ENOMEM.
+ * All searches use `matrix`, `gap_open` and `gap_extend` (validated as for sw_search).
+ * The database must outlive the server.
+ *
+ * sw_server_submit copies the query (validated as for sw_search) and returns a ticket;
+ * `scores_out` (host, int32[sw_db_size(db)]) must stay valid until sw_server_wait for
+ * that ticket returns, and is fully written when the request completes.
+ * sw_server_wait blocks until the request completes and returns its status (SW_OK or a
+ * negative code); latency_ms (submission to completion) and queue_ms (submission to
+ * launch) are filled if non-NULL.  Each ticket can be waited on once.
+ * sw_server_stats reports the number of batched launches, the largest number of
+ * batches in flight at once and the number of refused requests.
+ * sw_server_free drains the queue, waits for the batches in flight and releases the
+ * server.  Scores are identical to those of sw_search for the same query.
+ */
+typedef struct sw_server sw_server;
+int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
+                     int32_t slots, int32_t max_batch, int64_t mem_budget_bytes,
+                     sw_server **out);
+int sw_server_submit(sw_server *server, const uint8_t *query, int32_t query_len,
+                     int32_t *scores_out, uint64_t *ticket);
+int sw_server_wait(sw_server *server, uint64_t ticket, double *latency_ms, double *queue_ms);
+int sw_server_stats(sw_server *server, int64_t *launches, int64_t *max_in_flight,
+                    int64_t *refused);
+void sw_server_free(sw_server *server);
+
 /* Static message for an error code. */
 const char *sw_strerror(int code);
 
@@ -142,6 +201,18 @@ const char *sw_strerror(int code);
  */
 int sw_timing_enable(sw_db *db, int32_t enable);
 int sw_timing_read(const sw_db *db, int64_t *launches, double *total_ms);
+
+/*
+ * The same totals for one kernel: SW_KERNEL_INTER16 (packed-int16 inter-task kernel),
+ * SW_KERNEL_INTRA_LONG (int32 intra-task kernel over long and routed sequences, on the
+ * second stream) or SW_KERNEL_RECOMPUTE (int32 recompute of saturated alignments).
+ * Errors: SW_ENODB, SW_EINVAL (unknown kernel or NULL output), SW_EDEVICE.
+ */
+#define SW_KERNEL_INTER16     0
+#define SW_KERNEL_INTRA_LONG  1
+#define SW_KERNEL_RECOMPUTE   2
+int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
+                          double *total_ms);
 
 /*
  * Tuning and debug knobs (process-wide; read at the next search):

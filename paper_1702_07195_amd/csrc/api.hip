@@ -4,8 +4,12 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <new>
 #include <numeric>
 #include <string>
@@ -62,14 +66,14 @@ struct Workspace {
   hipStream_t own = nullptr;    // stream used by the blocking calls
   hipStream_t aux = nullptr;    // second stream for the long-sequence kernel
   hipEvent_t done = nullptr, fork = nullptr, join = nullptr;
-  hipEvent_t t0 = nullptr, t1 = nullptr;  // inter-task kernel timing
-  bool timed = false;
+  hipEvent_t t0[3] = {}, t1[3] = {};  // kernel timing: inter-task, long intra, recompute
+  bool timed[3] = {false, false, false};
   bool busy = false;
-  DevBuf queries, qoff, qdesc, matrix, qp16, qp32, ctr, flagged, longitems, bnd16, bnd32,
-      scores;
+  DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp32, ctr, flagged, longitems, bnd16,
+      bnd32, scores;
   HostBuf staging;
   size_t total_bytes() const {
-    return queries.bytes + qoff.bytes + qdesc.bytes + matrix.bytes + qp16.bytes + qp32.bytes +
+    return queries.bytes + qoff.bytes + qdesc.bytes + qorder.bytes + matrix.bytes + qp16.bytes + qp32.bytes +
            ctr.bytes + flagged.bytes + longitems.bytes + bnd16.bytes + bnd32.bytes + scores.bytes;
   }
 };
@@ -100,9 +104,13 @@ struct sw_db {
   std::mutex mu;
   std::vector<Workspace *> pool;
   std::atomic<bool> timing{false};
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> timing_events;
-  int64_t timing_launches = 0;
-  double timing_ms = 0.0;
+  struct TimedLaunch {
+    int kind;
+    hipEvent_t e0, e1;
+  };
+  std::vector<TimedLaunch> timing_events;
+  int64_t timing_launches[3] = {0, 0, 0};
+  double timing_ms[3] = {0.0, 0.0, 0.0};
 };
 
 namespace {
@@ -130,11 +138,12 @@ void grow_host(HostBuf &b, size_t bytes) {
 void destroy_workspace(Workspace *w) {
   if (w->own) (void)hipStreamSynchronize(w->own);
   if (w->aux) (void)hipStreamSynchronize(w->aux);
-  for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->matrix, &w->qp16, &w->qp32, &w->ctr,
+  for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->qorder, &w->matrix, &w->qp16, &w->qp32, &w->ctr,
                     &w->flagged, &w->longitems, &w->bnd16, &w->bnd32, &w->scores})
     b->release();
   w->staging.release();
-  for (hipEvent_t e : {w->done, w->fork, w->join, w->t0, w->t1})
+  for (hipEvent_t e : {w->done, w->fork, w->join, w->t0[0], w->t1[0], w->t0[1], w->t1[1],
+                       w->t0[2], w->t1[2]})
     if (e) (void)hipEventDestroy(e);
   if (w->own) (void)hipStreamDestroy(w->own);
   if (w->aux) (void)hipStreamDestroy(w->aux);
@@ -166,8 +175,10 @@ Workspace *acquire(sw_db *db) {
     hip_check(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
     hip_check(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
     hip_check(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
-    hip_check(hipEventCreate(&w->t0));
-    hip_check(hipEventCreate(&w->t1));
+    for (int k = 0; k < 3; ++k) {
+      hip_check(hipEventCreate(&w->t0[k]));
+      hip_check(hipEventCreate(&w->t1[k]));
+    }
     hip_check(hipEventRecord(w->done, w->own));
   } catch (...) {
     destroy_workspace(w);
@@ -241,12 +252,17 @@ struct Plan {
 // `scores_dev` (n_queries x n_seqs).  The caller owns `w` until `done` is recorded.
 void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64_t *qoff,
                     int64_t nq, const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
-                    int32_t *scores_dev, hipStream_t s) {
-  hip_check(hipSetDevice(db->device));
+                    int32_t *scores_dev, hipStream_t s, bool allow_timing = true) {
+  // the caller has made db->device current (no device switch while a graph is captured)
   const int A = db->alphabet;
   Plan p;
   std::vector<int64_t> lens((size_t)nq);
   for (int64_t q = 0; q < nq; ++q) lens[q] = qoff[q + 1] - qoff[q];
+  // inter-task items visit each group's queries longest first
+  std::vector<int32_t> qorder((size_t)nq);
+  std::iota(qorder.begin(), qorder.end(), 0);
+  std::stable_sort(qorder.begin(), qorder.end(),
+                   [&](int32_t x, int32_t y) { return lens[x] > lens[y]; });
   p.T = choose_T(lens);
   const int band = 64 * kIntraR;
   p.qd.resize((size_t)nq);
@@ -341,6 +357,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   grow(w->queries, (size_t)qbytes + 64);
   grow(w->qoff, (size_t)(nq + 1) * 8);
   grow(w->qdesc, std::max<size_t>(1, nq) * sizeof(QueryDesc));
+  grow(w->qorder, std::max<size_t>(1, nq) * sizeof(int32_t));
   grow(w->matrix, (size_t)A * A * 4);
   grow(w->qp16, (size_t)std::max<int64_t>(8, p.qp16_elems) * 2);
   grow(w->qp32, (size_t)std::max<int64_t>(8, p.qp32_elems) * 2);
@@ -354,7 +371,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const size_t off_qoff = ((size_t)qbytes + 63) & ~size_t(63);
   const size_t off_qd = off_qoff + (((size_t)(nq + 1) * 8 + 63) & ~size_t(63));
   const size_t off_mx = off_qd + ((nq * sizeof(QueryDesc) + 63) & ~size_t(63));
-  const size_t off_li = off_mx + (((size_t)A * A * 4 + 63) & ~size_t(63));
+  const size_t off_qo = off_mx + (((size_t)A * A * 4 + 63) & ~size_t(63));
+  const size_t off_li = off_qo + ((nq * sizeof(int32_t) + 63) & ~size_t(63));
   const size_t stage_bytes = off_li + p.longitems.size() * sizeof(PairItem) + 64;
   grow_host(w->staging, stage_bytes);
   uint8_t *st = (uint8_t *)w->staging.ptr;
@@ -362,12 +380,14 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   std::memcpy(st + off_qoff, qoff, (size_t)(nq + 1) * 8);
   if (nq) std::memcpy(st + off_qd, p.qd.data(), nq * sizeof(QueryDesc));
   std::memcpy(st + off_mx, matrix, (size_t)A * A * 4);
+  if (nq) std::memcpy(st + off_qo, qorder.data(), nq * sizeof(int32_t));
   if (!p.longitems.empty())
     std::memcpy(st + off_li, p.longitems.data(), p.longitems.size() * sizeof(PairItem));
   if (qbytes) hip_check(hipMemcpyAsync(w->queries.ptr, st, (size_t)qbytes, hipMemcpyHostToDevice, s));
   hip_check(hipMemcpyAsync(w->qoff.ptr, st + off_qoff, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, s));
   if (nq) hip_check(hipMemcpyAsync(w->qdesc.ptr, st + off_qd, nq * sizeof(QueryDesc), hipMemcpyHostToDevice, s));
   hip_check(hipMemcpyAsync(w->matrix.ptr, st + off_mx, (size_t)A * A * 4, hipMemcpyHostToDevice, s));
+  if (nq) hip_check(hipMemcpyAsync(w->qorder.ptr, st + off_qo, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
   if (!p.longitems.empty())
     hip_check(hipMemcpyAsync(w->longitems.ptr, st + off_li, p.longitems.size() * sizeof(PairItem),
                              hipMemcpyHostToDevice, s));
@@ -406,7 +426,13 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.bnd = (int2 *)w->bnd32.ptr;
     ia.bnd_slot_elems = (int64_t)bnd32_slot;
     ia.bnd_stride = bnd32_stride;
+    const bool timed = allow_timing && db->timing.load();
+    if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
     hip_check(launch_intra32(ia, kIntraR, kIntraWaves, p.grid_long, w->aux));
+    if (timed) {
+      hip_check(hipEventRecord(w->t1[1], w->aux));
+      w->timed[1] = true;
+    }
     hip_check(hipEventRecord(w->join, w->aux));
   }
 
@@ -417,6 +443,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.ngroups = p.ngroups_inter;
     ia.nqueries = (int32_t)nq;
     ia.queries = (const QueryDesc *)w->qdesc.ptr;
+    ia.qorder = (const int32_t *)w->qorder.ptr;
     ia.qp16 = (const int16_t *)w->qp16.ptr;
     ia.perm = (const int32_t *)db->perm.ptr;
     ia.lens = (const int32_t *)db->lens.ptr;
@@ -429,12 +456,12 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.bnd_slot_words = (int64_t)bnd16_slot;
     ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
     ia.nitems = (int32_t)nitems16;
-    const bool timed = db->timing.load();
-    if (timed) hip_check(hipEventRecord(w->t0, s));
+    const bool timed = allow_timing && db->timing.load();
+    if (timed && p.grid16 > 0) hip_check(hipEventRecord(w->t0[0], s));
     hip_check(launch_inter16(ia, p.T, p.grid16, s));
-    if (timed) {
-      hip_check(hipEventRecord(w->t1, s));
-      w->timed = true;
+    if (timed && p.grid16 > 0) {
+      hip_check(hipEventRecord(w->t1[0], s));
+      w->timed[0] = true;
     }
     // exact int32 recompute of the saturated alignments (count read on the device);
     // it uses the boundary slots after the long-sequence kernel's, so both may overlap
@@ -454,7 +481,12 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.bnd = (int2 *)w->bnd32.ptr + (size_t)p.grid_long * bnd32_slot;
     ra.bnd_slot_elems = (int64_t)bnd32_slot;
     ra.bnd_stride = bnd32_stride;
+    if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
     hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
+    if (timed && p.grid_re > 0) {
+      hip_check(hipEventRecord(w->t1[2], s));
+      w->timed[2] = true;
+    }
   }
   if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
 }
@@ -636,8 +668,8 @@ SW_API void sw_db_free(sw_db *db) {
   (void)hipSetDevice(db->device);
   for (Workspace *w : db->pool) destroy_workspace(w);
   for (auto &e : db->timing_events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.e0);
+    (void)hipEventDestroy(e.e1);
   }
   db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
   delete db;
@@ -645,15 +677,23 @@ SW_API void sw_db_free(sw_db *db) {
 
 namespace {
 
-void collect_timing(sw_db *db, Workspace *w) {
-  if (!w->timed) return;
-  w->timed = false;
-  float ms = 0.f;
-  hip_check(hipEventSynchronize(w->t1));
-  hip_check(hipEventElapsedTime(&ms, w->t0, w->t1));
+// Hand the workspace's recorded timing events to the database (they are read, and
+// destroyed, by sw_timing_read_kernel) and give the workspace fresh ones.
+void hand_over_timing(sw_db *db, Workspace *w) {
   std::lock_guard<std::mutex> lk(db->mu);
-  db->timing_launches += 1;
-  db->timing_ms += ms;
+  for (int k = 0; k < 3; ++k) {
+    if (!w->timed[k]) continue;
+    w->timed[k] = false;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) continue;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      continue;
+    }
+    db->timing_events.push_back({k, w->t0[k], w->t1[k]});
+    w->t0[k] = a;
+    w->t1[k] = b;
+  }
 }
 
 int run_search(const sw_db *cdb, const uint8_t *queries, const int64_t *qoff, int64_t nq,
@@ -680,18 +720,7 @@ int run_search(const sw_db *cdb, const uint8_t *queries, const int64_t *qoff, in
         hip_check(hipMemcpyAsync(host_out, scores, nscores * 4, hipMemcpyDeviceToHost, s));
       hip_check(hipStreamSynchronize(s));
     }
-    if (db->timing.load() && host_out) collect_timing(db, w);
-    if (db->timing.load() && !host_out && w->timed) {
-      // keep the event pair for sw_timing_read; replace the workspace's own pair
-      std::lock_guard<std::mutex> lk(db->mu);
-      db->timing_events.emplace_back(w->t0, w->t1);
-      w->timed = false;
-      hipEvent_t a = nullptr, b = nullptr;
-      if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-        w->t0 = a;
-        w->t1 = b;
-      }
-    }
+    hand_over_timing(db, w);
     release(db, w);
     return SW_OK;
   } catch (const HipFail &f) {
@@ -753,32 +782,422 @@ SW_API int sw_timing_enable(sw_db *db, int32_t enable) {
   if (!db) return SW_ENODB;
   std::lock_guard<std::mutex> lk(db->mu);
   db->timing = enable != 0;
-  db->timing_launches = 0;
-  db->timing_ms = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    db->timing_launches[k] = 0;
+    db->timing_ms[k] = 0.0;
+  }
   for (auto &e : db->timing_events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.e0);
+    (void)hipEventDestroy(e.e1);
   }
   db->timing_events.clear();
   return SW_OK;
 }
 
-SW_API int sw_timing_read(const sw_db *cdb, int64_t *launches, double *total_ms) {
+SW_API int sw_timing_read_kernel(const sw_db *cdb, int32_t kernel, int64_t *launches,
+                                 double *total_ms) {
   if (!cdb) return SW_ENODB;
-  if (!launches || !total_ms) return SW_EINVAL;
+  if (!launches || !total_ms || kernel < 0 || kernel > 2) return SW_EINVAL;
   sw_db *db = const_cast<sw_db *>(cdb);
   std::lock_guard<std::mutex> lk(db->mu);
   for (auto &e : db->timing_events) {
     float ms = 0.f;
-    if (hipEventSynchronize(e.second) != hipSuccess) return SW_EDEVICE;
-    if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess) return SW_EDEVICE;
-    db->timing_launches += 1;
-    db->timing_ms += ms;
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    if (hipEventSynchronize(e.e1) != hipSuccess) return SW_EDEVICE;
+    if (hipEventElapsedTime(&ms, e.e0, e.e1) != hipSuccess) return SW_EDEVICE;
+    db->timing_launches[e.kind] += 1;
+    db->timing_ms[e.kind] += ms;
+    (void)hipEventDestroy(e.e0);
+    (void)hipEventDestroy(e.e1);
   }
   db->timing_events.clear();
-  *launches = db->timing_launches;
-  *total_ms = db->timing_ms;
+  *launches = db->timing_launches[kernel];
+  *total_ms = db->timing_ms[kernel];
   return SW_OK;
+}
+
+SW_API int sw_timing_read(const sw_db *db, int64_t *launches, double *total_ms) {
+  return sw_timing_read_kernel(db, SW_KERNEL_INTER16, launches, total_ms);
+}
+
+// ------------------------------------------------------------------------ plans
+// A plan owns a dedicated workspace and an instantiated hipGraph of one (batched)
+// search, so replays cost one graph launch.  The graph is captured after an eager run
+// has sized every buffer (no allocation happens while capturing), and it contains no
+// memset nodes: the counters are cleared by the profile kernel.
+struct sw_plan {
+  sw_db *db = nullptr;
+  Workspace *w = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+SW_API int sw_plan_create(const sw_db *cdb, const uint8_t *queries, const int64_t *query_offsets,
+                          int64_t n_queries, const int32_t *matrix, int32_t gap_open,
+                          int32_t gap_extend, int32_t *scores_dev, sw_plan **out) {
+  int rc = validate_search(cdb, matrix, gap_open, gap_extend);
+  if (rc) return rc;
+  if (!out || !query_offsets || n_queries < 1 || query_offsets[0] != 0) return SW_EINVAL;
+  if (!scores_dev && cdb->n_seqs > 0) return SW_EINVAL;
+  if ((double)n_queries * (double)cdb->n_seqs > 2.0e9) return SW_EINVAL;
+  for (int64_t q = 0; q < n_queries; ++q) {
+    if (query_offsets[q + 1] < query_offsets[q]) return SW_EINVAL;
+    const int64_t m = query_offsets[q + 1] - query_offsets[q];
+    if ((rc = validate_query(cdb, queries ? queries + query_offsets[q] : nullptr, m))) return rc;
+  }
+  sw_db *db = const_cast<sw_db *>(cdb);
+  sw_plan *plan = new (std::nothrow) sw_plan();
+  if (!plan) return SW_ENOMEM;
+  plan->db = db;
+  hipStream_t cap = nullptr;
+  try {
+    hip_check(hipSetDevice(db->device));
+    plan->w = new Workspace();
+    Workspace *w = plan->w;
+    hip_check(hipStreamCreateWithFlags(&w->own, hipStreamNonBlocking));
+    hip_check(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
+    hip_check(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
+    hip_check(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+    hip_check(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
+    if (db->n_seqs > 0) {
+      // eager run: allocates and fills every buffer
+      enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
+                     scores_dev, w->own, false);
+      hip_check(hipStreamSynchronize(w->own));
+      hip_check(hipStreamSynchronize(w->aux));
+      // capture the same launch sequence
+      hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
+                       scores_dev, cap, false);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      hip_check(hipStreamEndCapture(cap, &plan->graph));
+      hip_check(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+      hip_check(hipStreamDestroy(cap));
+      cap = nullptr;
+    }
+  } catch (const HipFail &f) {
+    if (cap) (void)hipStreamDestroy(cap);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->w) destroy_workspace(plan->w);
+    delete plan;
+    return map_hip(f.err);
+  } catch (const std::bad_alloc &) {
+    if (cap) (void)hipStreamDestroy(cap);
+    if (plan->w) destroy_workspace(plan->w);
+    delete plan;
+    return SW_ENOMEM;
+  }
+  *out = plan;
+  return SW_OK;
+}
+
+SW_API int sw_plan_launch(sw_plan *plan, void *hip_stream) {
+  if (!plan) return SW_EINVAL;
+  if (!plan->exec) return SW_OK;  // empty database: nothing to do
+  if (hipSetDevice(plan->db->device) != hipSuccess) return SW_EDEVICE;
+  const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
+  return e == hipSuccess ? SW_OK : map_hip(e);
+}
+
+SW_API void sw_plan_free(sw_plan *plan) {
+  if (!plan) return;
+  (void)hipSetDevice(plan->db->device);
+  (void)hipDeviceSynchronize();
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->w) destroy_workspace(plan->w);
+  delete plan;
+}
+
+// ------------------------------------------------------------------------ serving
+// Continuous batching over a resident database.  Requests are queued by sw_server_submit;
+// a worker thread launches every queued request it can admit as one batched search on a
+// free stream slot, as soon as a slot is free and the device-memory budget allows, so new
+// requests join while earlier batches are still on the GPU and their kernels overlap on
+// the device.  Each slot owns a workspace; completion is detected with events.
+namespace {
+
+struct ServerRequest {
+  uint64_t ticket = 0;
+  std::vector<uint8_t> query;
+  int32_t *scores_out = nullptr;  // caller's host buffer (n_seqs)
+  int status = 1;                 // 1 = pending, 0 = done, < 0 = error
+  double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+struct ServerSlot {
+  Workspace *w = nullptr;
+  hipEvent_t finished = nullptr;
+  bool busy = false;
+  size_t mem = 0;                       // admitted bytes of the batch in flight
+  std::vector<ServerRequest *> batch;
+  DevBuf scores;
+  HostBuf host_scores;
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct sw_server {
+  sw_db *db = nullptr;
+  std::vector<int32_t> matrix;
+  int32_t gap_open = 0, gap_extend = 0;
+  int32_t max_batch = 1;
+  int64_t mem_budget = 0;
+  std::vector<ServerSlot> slots;
+  std::mutex mu;
+  std::condition_variable cv;     // wakes the worker
+  std::condition_variable done_cv;  // wakes waiters
+  std::deque<ServerRequest *> queue;
+  std::unordered_map<uint64_t, ServerRequest *> requests;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  int64_t launches = 0, max_in_flight = 0, refused = 0;
+};
+
+namespace {
+
+// Device bytes one batch of queries needs beyond the slot's boundary scratch: profiles
+// (two int16 layouts, <= 128 bytes per query row plus padding), scores, recompute list.
+size_t batch_bytes(const sw_db *db, const std::vector<ServerRequest *> &batch) {
+  size_t b = 0;
+  for (const ServerRequest *r : batch)
+    b += (r->query.size() + 64 * kIntraR) * 2 * kCodes * 2 + (size_t)db->n_seqs * 4 +
+         (size_t)db->n_short * sizeof(PairItem);
+  return b;
+}
+
+void server_finish_slot(sw_server *sv, ServerSlot &sl) {
+  // called with sv->mu held, after sl.finished has completed
+  const double t = now_s();
+  const size_t n = (size_t)sv->db->n_seqs;
+  for (size_t k = 0; k < sl.batch.size(); ++k) {
+    ServerRequest *r = sl.batch[k];
+    if (n && r->scores_out)
+      std::memcpy(r->scores_out, (const int32_t *)sl.host_scores.ptr + k * n, n * 4);
+    r->status = 0;
+    r->t_done = t;
+  }
+  sl.batch.clear();
+  sl.busy = false;
+  sl.mem = 0;
+  sv->done_cv.notify_all();
+}
+
+void server_loop(sw_server *sv) {
+  std::unique_lock<std::mutex> lk(sv->mu);
+  (void)hipSetDevice(sv->db->device);
+  for (;;) {
+    // retire finished batches
+    int in_flight = 0;
+    size_t mem_in_flight = 0;
+    for (ServerSlot &sl : sv->slots) {
+      if (sl.busy && hipEventQuery(sl.finished) == hipSuccess) server_finish_slot(sv, sl);
+      if (sl.busy) {
+        ++in_flight;
+        mem_in_flight += sl.mem;
+      }
+    }
+    if (sv->stop && sv->queue.empty() && in_flight == 0) break;
+    // admit queued requests into a free slot
+    ServerSlot *free_slot = nullptr;
+    for (ServerSlot &sl : sv->slots)
+      if (!sl.busy) { free_slot = &sl; break; }
+    if (free_slot && !sv->queue.empty()) {
+      std::vector<ServerRequest *> batch;
+      while (!sv->queue.empty() && (int)batch.size() < sv->max_batch) {
+        batch.push_back(sv->queue.front());
+        if (sv->mem_budget > 0 && (int64_t)(mem_in_flight + batch_bytes(sv->db, batch)) > sv->mem_budget) {
+          batch.pop_back();
+          break;
+        }
+        sv->queue.pop_front();
+      }
+      if (batch.empty() && in_flight == 0) {
+        // a single request larger than the whole budget can never be admitted
+        ServerRequest *r = sv->queue.front();
+        sv->queue.pop_front();
+        r->status = SW_ENOMEM;
+        r->t_done = now_s();
+        ++sv->refused;
+        sv->done_cv.notify_all();
+        continue;
+      }
+      if (!batch.empty()) {
+        ServerSlot &sl = *free_slot;
+        std::vector<uint8_t> cat;
+        std::vector<int64_t> offs(1, 0);
+        for (ServerRequest *r : batch) {
+          cat.insert(cat.end(), r->query.begin(), r->query.end());
+          offs.push_back((int64_t)cat.size());
+        }
+        if (cat.empty()) cat.push_back(0);
+        const size_t n = (size_t)sv->db->n_seqs * batch.size();
+        int rc = SW_OK;
+        try {
+          grow(sl.scores, std::max<size_t>(1, n) * 4);
+          grow_host(sl.host_scores, std::max<size_t>(1, n) * 4);
+          const double t = now_s();
+          for (ServerRequest *r : batch) r->t_start = t;
+          if (n > 0) {
+            enqueue_search(sv->db, sl.w, cat.data(), offs.data(), (int64_t)batch.size(),
+                           sv->matrix.data(), sv->gap_open, sv->gap_extend,
+                           (int32_t *)sl.scores.ptr, sl.w->own, false);
+            hip_check(hipMemcpyAsync(sl.host_scores.ptr, sl.scores.ptr, n * 4,
+                                     hipMemcpyDeviceToHost, sl.w->own));
+          }
+          hip_check(hipEventRecord(sl.finished, sl.w->own));
+        } catch (const HipFail &f) {
+          rc = map_hip(f.err);
+        } catch (const std::bad_alloc &) {
+          rc = SW_ENOMEM;
+        }
+        if (rc != SW_OK) {
+          (void)hipStreamSynchronize(sl.w->own);
+          for (ServerRequest *r : batch) {
+            r->status = rc;
+            r->t_done = now_s();
+          }
+          sv->done_cv.notify_all();
+        } else {
+          sl.batch = std::move(batch);
+          sl.busy = true;
+          sl.mem = batch_bytes(sv->db, sl.batch);
+          ++sv->launches;
+          sv->max_in_flight = std::max<int64_t>(sv->max_in_flight, in_flight + 1);
+        }
+        continue;
+      }
+    }
+    // wait for new work or poll the batches in flight
+    if (in_flight > 0)
+      sv->cv.wait_for(lk, std::chrono::microseconds(100));
+    else
+      sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+  }
+}
+
+}  // namespace
+
+SW_API int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open,
+                            int32_t gap_extend, int32_t slots, int32_t max_batch,
+                            int64_t mem_budget_bytes, sw_server **out) {
+  int rc = validate_search(db, matrix, gap_open, gap_extend);
+  if (rc) return rc;
+  if (!out || slots < 1 || slots > 16 || max_batch < 1 || max_batch > 4096 ||
+      mem_budget_bytes < 0)
+    return SW_EINVAL;
+  sw_server *sv = new (std::nothrow) sw_server();
+  if (!sv) return SW_ENOMEM;
+  sv->db = db;
+  sv->matrix.assign(matrix, matrix + (size_t)db->alphabet * db->alphabet);
+  sv->gap_open = gap_open;
+  sv->gap_extend = gap_extend;
+  sv->max_batch = max_batch;
+  sv->mem_budget = mem_budget_bytes;
+  sv->slots.resize((size_t)slots);
+  try {
+    hip_check(hipSetDevice(db->device));
+    for (ServerSlot &sl : sv->slots) {
+      sl.w = new Workspace();
+      hip_check(hipStreamCreateWithFlags(&sl.w->own, hipStreamNonBlocking));
+      hip_check(hipStreamCreateWithFlags(&sl.w->aux, hipStreamNonBlocking));
+      hip_check(hipEventCreateWithFlags(&sl.w->done, hipEventDisableTiming));
+      hip_check(hipEventCreateWithFlags(&sl.w->fork, hipEventDisableTiming));
+      hip_check(hipEventCreateWithFlags(&sl.w->join, hipEventDisableTiming));
+      hip_check(hipEventCreateWithFlags(&sl.finished, hipEventDisableTiming));
+    }
+  } catch (const HipFail &f) {
+    for (ServerSlot &sl : sv->slots) {
+      if (sl.finished) (void)hipEventDestroy(sl.finished);
+      if (sl.w) destroy_workspace(sl.w);
+    }
+    delete sv;
+    return map_hip(f.err);
+  }
+  sv->worker = std::thread(server_loop, sv);
+  *out = sv;
+  return SW_OK;
+}
+
+SW_API int sw_server_submit(sw_server *sv, const uint8_t *query, int32_t query_len,
+                            int32_t *scores_out, uint64_t *ticket) {
+  if (!sv || !ticket) return SW_EINVAL;
+  if (!scores_out && sv->db->n_seqs > 0) return SW_EINVAL;
+  int rc = validate_query(sv->db, query, query_len);
+  if (rc) return rc;
+  ServerRequest *r = new (std::nothrow) ServerRequest();
+  if (!r) return SW_ENOMEM;
+  r->query.assign(query, query + query_len);
+  r->scores_out = scores_out;
+  r->t_submit = now_s();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) {
+      delete r;
+      return SW_EINVAL;
+    }
+    r->ticket = sv->next_ticket++;
+    sv->requests[r->ticket] = r;
+    sv->queue.push_back(r);
+    *ticket = r->ticket;
+  }
+  sv->cv.notify_one();
+  return SW_OK;
+}
+
+SW_API int sw_server_wait(sw_server *sv, uint64_t ticket, double *latency_ms,
+                          double *queue_ms) {
+  if (!sv) return SW_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->requests.find(ticket);
+  if (it == sv->requests.end()) return SW_EINVAL;
+  ServerRequest *r = it->second;
+  sv->done_cv.wait(lk, [&] { return r->status != 1; });
+  const int status = r->status;
+  if (latency_ms) *latency_ms = (r->t_done - r->t_submit) * 1e3;
+  if (queue_ms) *queue_ms = (r->t_start > 0 ? r->t_start - r->t_submit : 0.0) * 1e3;
+  sv->requests.erase(it);
+  delete r;
+  return status;
+}
+
+SW_API int sw_server_stats(sw_server *sv, int64_t *launches, int64_t *max_in_flight,
+                           int64_t *refused) {
+  if (!sv) return SW_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (launches) *launches = sv->launches;
+  if (max_in_flight) *max_in_flight = sv->max_in_flight;
+  if (refused) *refused = sv->refused;
+  return SW_OK;
+}
+
+SW_API void sw_server_free(sw_server *sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+  }
+  sv->cv.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  (void)hipSetDevice(sv->db->device);
+  for (ServerSlot &sl : sv->slots) {
+    if (sl.w) destroy_workspace(sl.w);
+    if (sl.finished) (void)hipEventDestroy(sl.finished);
+    sl.scores.release();
+    sl.host_scores.release();
+  }
+  for (auto &kv : sv->requests) delete kv.second;
+  delete sv;
 }

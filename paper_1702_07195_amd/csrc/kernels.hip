@@ -178,7 +178,7 @@ void k_inter16(InterArgs a) {
     const int item = s_item;
     if (item >= a.nitems) break;
     const int g = a.ngroups - 1 - item / a.nqueries;  // longest groups first
-    const int qi = item % a.nqueries;
+    const int qi = a.qorder[item % a.nqueries];       // then longest queries first
     const GroupDesc gd = a.groups[g];
     const QueryDesc qd = a.queries[qi];
     const int16_t *qp = a.qp16 + qd.qp16;
@@ -422,21 +422,41 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
         const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
         const int rq_next = col_next < n
             ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
-        const int16_t *prof = a.qp32 + qd.qp32 + (int64_t)b * 64 * R + lane * R;
+        // this lane's R profile rows of band b; code c's rows start c * pstride bytes on
+        const uint8_t *prof = reinterpret_cast<const uint8_t *>(
+            a.qp32 + qd.qp32 + (int64_t)b * 64 * R + lane * R);
+        const uint32_t pstride = (uint32_t)qd.mpad32 * 2u;
 
+        // The code a lane needs at step s + 1 is its left neighbour's code at step s, so
+        // the profile rows of the next step are loaded one step ahead.
+        int code_next = wave_shr1(code, __builtin_amdgcn_readlane(rq, 0));
+        uint4 Pn[R / 8];
+#pragma unroll
+        for (int r8 = 0; r8 < R; r8 += 8)
+          Pn[r8 >> 3] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code_next * pstride +
+                                                          2 * r8);
         for (int i = 0; i < 64; ++i) {
           const int s = 64 * k + i;
-          code = wave_shr1(code, __builtin_amdgcn_readlane(rq, i));
+          code = code_next;
+          uint4 P[R / 8];
+#pragma unroll
+          for (int r8 = 0; r8 < R; r8 += 8) P[r8 >> 3] = Pn[r8 >> 3];
+          // prefetch for step s + 1 (the first column of the next chunk comes from rq_next)
+          const int cin = i < 63 ? __builtin_amdgcn_readlane(rq, i + 1)
+                                 : __builtin_amdgcn_readfirstlane(rq_next);
+          code_next = wave_shr1(code, cin);
+#pragma unroll
+          for (int r8 = 0; r8 < R; r8 += 8)
+            Pn[r8 >> 3] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code_next * pstride +
+                                                            2 * r8);
           const int hup = wave_shr1(hbot, __builtin_amdgcn_readlane(tq.x, i));
           int f = wave_shr1(fbot, __builtin_amdgcn_readlane(tq.y, i));
           int hd = hdiag;
           hdiag = hup;
-          const uint4 *pp = reinterpret_cast<const uint4 *>(prof + (int64_t)code * qd.mpad32);
           int h = 0;
 #pragma unroll
           for (int r8 = 0; r8 < R; r8 += 8) {
-            const uint4 P = pp[r8 >> 3];
-            const uint32_t pv[4] = {P.x, P.y, P.z, P.w};
+            const uint32_t pv[4] = {P[r8 >> 3].x, P[r8 >> 3].y, P[r8 >> 3].z, P[r8 >> 3].w};
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               const int r = r8 + q;

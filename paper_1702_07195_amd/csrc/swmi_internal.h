@@ -65,6 +65,7 @@ struct InterArgs {
   int32_t ngroups;
   int32_t nqueries;
   const QueryDesc *queries;
+  const int32_t *qorder;     // queries of a group in visiting order (longest first)
   const int16_t *qp16;
   const int32_t *perm;       // sorted position -> caller's index
   const int32_t *lens;       // sorted position -> length

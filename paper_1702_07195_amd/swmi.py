@@ -30,7 +30,13 @@ SW_KNOB_ROUTE_LEN = 6
 # Every entry point declared in include/swmi.h.
 SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_async",
            "sw_search_batch", "sw_strerror", "sw_timing_enable", "sw_timing_read",
-           "sw_set_knob", "sw_get_knob")
+           "sw_timing_read_kernel", "sw_set_knob", "sw_get_knob", "sw_plan_create",
+           "sw_plan_launch", "sw_plan_free", "sw_server_create", "sw_server_submit",
+           "sw_server_wait", "sw_server_stats", "sw_server_free")
+
+SW_KERNEL_INTER16 = 0
+SW_KERNEL_INTRA_LONG = 1
+SW_KERNEL_RECOMPUTE = 2
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -82,6 +88,29 @@ def lib():
         L.sw_timing_enable.argtypes = [_vp, ctypes.c_int32]
         L.sw_timing_read.restype = ctypes.c_int
         L.sw_timing_read.argtypes = [_vp, _i64p, ctypes.POINTER(ctypes.c_double)]
+        L.sw_timing_read_kernel.restype = ctypes.c_int
+        L.sw_timing_read_kernel.argtypes = [_vp, ctypes.c_int32, _i64p,
+                                            ctypes.POINTER(ctypes.c_double)]
+        L.sw_plan_create.restype = ctypes.c_int
+        L.sw_plan_create.argtypes = [_vp, _u8p, _i64p, ctypes.c_int64, _i32p, ctypes.c_int32,
+                                     ctypes.c_int32, _vp, ctypes.POINTER(_vp)]
+        L.sw_plan_launch.restype = ctypes.c_int
+        L.sw_plan_launch.argtypes = [_vp, _vp]
+        L.sw_plan_free.restype = None
+        L.sw_plan_free.argtypes = [_vp]
+        L.sw_server_create.restype = ctypes.c_int
+        L.sw_server_create.argtypes = [_vp, _i32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(_vp)]
+        L.sw_server_submit.restype = ctypes.c_int
+        L.sw_server_submit.argtypes = [_vp, _u8p, ctypes.c_int32, _i32p,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.sw_server_wait.restype = ctypes.c_int
+        L.sw_server_wait.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.sw_server_stats.restype = ctypes.c_int
+        L.sw_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p]
+        L.sw_server_free.restype = None
+        L.sw_server_free.argtypes = [_vp]
         L.sw_set_knob.restype = ctypes.c_int
         L.sw_set_knob.argtypes = [ctypes.c_int32, ctypes.c_int64]
         L.sw_get_knob.restype = ctypes.c_int64
@@ -204,12 +233,114 @@ class SwDb:
         _check(rc, "sw_search_batch")
         return out
 
+    def plan(self, queries, matrix, gap_open: int, gap_extend: int, scores_dev) -> "SwPlan":
+        """Capture a batched search into a HIP graph; ``scores_dev`` is an int32 device
+        tensor of n_queries * n_seqs elements."""
+        qs = [np.ascontiguousarray(x, dtype=np.uint8) for x in queries]
+        offs = np.zeros(len(qs) + 1, dtype=np.int64)
+        np.cumsum([len(x) for x in qs], out=offs[1:])
+        cat = np.concatenate(qs) if qs else np.zeros(0, np.uint8)
+        if len(cat) == 0:
+            cat = np.zeros(1, np.uint8)
+        c, pc = _u8(cat)
+        o, po = _i64(offs)
+        m, pm = _i32(matrix)
+        handle = _vp()
+        rc = lib().sw_plan_create(self.handle, pc, po, len(qs), pm, int(gap_open),
+                                  int(gap_extend), _vp(scores_dev.data_ptr()),
+                                  ctypes.byref(handle))
+        _check(rc, "sw_plan_create")
+        return SwPlan(handle, self, scores_dev)
+
     def timing_enable(self, on: bool = True):
         _check(lib().sw_timing_enable(self.handle, 1 if on else 0), "sw_timing_enable")
 
-    def timing_read(self):
+    def timing_read(self, kernel: int = SW_KERNEL_INTER16):
+        """(launches, total device milliseconds) of one kernel since timing_enable."""
         n = ctypes.c_int64(0)
         ms = ctypes.c_double(0.0)
-        _check(lib().sw_timing_read(self.handle, ctypes.byref(n), ctypes.byref(ms)),
-               "sw_timing_read")
+        _check(lib().sw_timing_read_kernel(self.handle, int(kernel), ctypes.byref(n),
+                                           ctypes.byref(ms)), "sw_timing_read_kernel")
         return int(n.value), float(ms.value)
+
+
+class SwPlan:
+    """A search captured into a HIP graph (see sw_plan_create in include/swmi.h)."""
+
+    def __init__(self, handle, db: SwDb, scores_dev):
+        self._h = handle
+        self._db = db            # keeps the database alive while the plan exists
+        self._scores = scores_dev
+
+    def launch(self, stream=None):
+        sptr = 0 if stream is None else int(stream.cuda_stream)
+        _check(lib().sw_plan_launch(self._h, _vp(sptr)), "sw_plan_launch")
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().sw_plan_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+class SwServer:
+    """Continuous-batching search server over a loaded database (see sw_server_create)."""
+
+    def __init__(self, db: SwDb, matrix, gap_open: int, gap_extend: int, slots: int = 2,
+                 max_batch: int = 8, mem_budget_bytes: int = 0):
+        m, pm = _i32(matrix)
+        handle = _vp()
+        rc = lib().sw_server_create(db.handle, pm, int(gap_open), int(gap_extend), int(slots),
+                                    int(max_batch), int(mem_budget_bytes), ctypes.byref(handle))
+        _check(rc, "sw_server_create")
+        self._h = handle
+        self._db = db
+        self._pending = {}   # ticket -> (query array, output array) kept alive until waited
+
+    def submit(self, query) -> int:
+        q, pq = _u8(query)
+        out = np.zeros(self._db.n_seqs, dtype=np.int32)
+        t = ctypes.c_uint64(0)
+        rc = lib().sw_server_submit(self._h, pq, len(q), out.ctypes.data_as(_i32p),
+                                    ctypes.byref(t))
+        _check(rc, "sw_server_submit")
+        self._pending[t.value] = (q, out)
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(scores, latency_ms, queue_ms) of a submitted query."""
+        lat = ctypes.c_double(0.0)
+        qms = ctypes.c_double(0.0)
+        rc = lib().sw_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(lat),
+                                  ctypes.byref(qms))
+        q, out = self._pending.pop(ticket)
+        _check(rc, "sw_server_wait")
+        return out, float(lat.value), float(qms.value)
+
+    def stats(self):
+        a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(lib().sw_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               "sw_server_stats")
+        return {"launches": a.value, "max_in_flight": b.value, "refused": c.value}
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib().sw_server_free(self._h)
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()

@@ -210,3 +210,74 @@ def test_order_independence(small_db, small_handle):
     _say("permuted database")
     with swmi.sw_db_load(pdb.residues, pdb.offsets, ALPHA) as h:
         assert np.array_equal(h.search(q, synth.BLOSUM62, 10, 2), base[perm])
+
+
+def test_plan_graph_replays(small_db, small_handle, route):
+    # A captured plan replayed several times, with eager searches and synchronisations
+    # in between; every replay must equal the oracle (and the eager run).
+    import torch
+    qs = synth.batched_queries(5, 1, 700, seed=21)
+    want = np.stack([_oracle(q, small_db, synth.BLOSUM62, 10, 2) for q in qs])
+    out = torch.full((len(qs), small_db.n_seqs), -1, dtype=torch.int32, device="cuda")
+    _say(f"plan create route={route}")
+    with small_handle.plan(qs, synth.BLOSUM62, 10, 2, out) as plan:
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), "eager run"
+        stream = torch.cuda.Stream()
+        for rep in range(3):
+            out.fill_(-1)
+            torch.cuda.synchronize()
+            plan.launch(stream)
+            stream.synchronize()
+            assert np.array_equal(out.cpu().numpy(), want), f"replay {rep}"
+            # eager work between replays
+            other = small_handle.search(qs[rep], synth.BLOSUM50, 11, 1)
+            assert np.array_equal(other, _oracle(qs[rep], small_db, synth.BLOSUM50, 11, 1))
+
+
+def test_timing_per_kernel(small_db, small_handle):
+    rng = np.random.Generator(np.random.PCG64(14))
+    q = synth.residues(rng, 300)
+    small_handle.timing_enable(True)
+    small_handle.search(q, synth.BLOSUM62, 10, 2)
+    small_handle.search(q, synth.BLOSUM62, 10, 2)
+    n16, ms16 = small_handle.timing_read(swmi.SW_KERNEL_INTER16)
+    nre, msre = small_handle.timing_read(swmi.SW_KERNEL_RECOMPUTE)
+    small_handle.timing_enable(False)
+    assert n16 in (0, 2) and nre == 2 and ms16 >= 0 and msre >= 0
+
+
+def test_server_results_alone_equal_in_the_mix(small_db, small_handle):
+    # Serving: each query's scores are identical when it is searched alone and when it
+    # is submitted among others that arrive while earlier batches are on the GPU.
+    import threading
+    import time as _time
+    qs = synth.served_queries(24, seed=31, median=120, lo=5, hi=600)
+    alone = [small_handle.search(q, synth.BLOSUM62, 10, 2) for q in qs]
+    _say("server mix")
+    with swmi.SwServer(small_handle, synth.BLOSUM62, 10, 2, slots=3, max_batch=4) as sv:
+        tickets = []
+        for k, q in enumerate(qs):
+            tickets.append(sv.submit(q))
+            if k % 5 == 4:
+                _time.sleep(0.002)  # let some batches start before the next arrivals
+        results = [sv.wait(t) for t in tickets]
+        st = sv.stats()
+    for k, (scores, lat, qms) in enumerate(results):
+        assert np.array_equal(scores, alone[k]), k
+        assert lat >= qms >= 0
+    assert st["launches"] >= 2
+    for k in (0, 7, 23):
+        assert np.array_equal(alone[k], _oracle(qs[k], small_db, synth.BLOSUM62, 10, 2))
+
+
+def test_server_memory_admission(small_db, small_handle):
+    # a budget smaller than one query's needs refuses it with SW_ENOMEM; others pass
+    q = synth.served_queries(1, seed=32, median=100, lo=50, hi=150)[0]
+    with swmi.SwServer(small_handle, synth.BLOSUM62, 10, 2, slots=1, max_batch=2,
+                       mem_budget_bytes=1024) as sv:
+        t = sv.submit(q)
+        with pytest.raises(swmi.SwError) as e:
+            sv.wait(t)
+        assert e.value.code == swmi.SW_ENOMEM
+        assert sv.stats()["refused"] == 1
