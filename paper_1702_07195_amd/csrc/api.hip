@@ -336,7 +336,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
   p.grid_long = (int)std::min<int64_t>((int64_t)wide.size() + ((int64_t)narrow.size() + kIntraWaves - 1) / kIntraWaves,
                                        4LL * db->num_cu);
-  p.grid_re = (db->n_short > 0 && nq > 0) ? db->num_cu : 0;
+  // the recompute list is usually empty; a quarter of the CUs is plenty when it is not
+  p.grid_re = (db->n_short > 0 && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
   const int grid32 = p.grid_long + p.grid_re;
 
   // workspace sizes
