@@ -46,8 +46,12 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "inter16_full_scale_traffic.json")
 
 
 def kernel_hash() -> str:
+    """Hash of the source the inter-task kernel is built from (shared helpers, profile and
+    packing kernels and k_inter16: everything before the intra-task section)."""
     with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+        src = f.read()
+    cut = src.find(b"// ------------------------------------------------------------------------ intra-task")
+    return hashlib.sha256(src[:cut if cut >= 0 else len(src)]).hexdigest()[:16]
 
 
 def load_traffic():
@@ -164,8 +168,17 @@ def run_searches(args, w, db, queries):
     per_query = {str(len(q)): round(len(q) * D / per_q[k] / 1e9, 1)
                  for k, q in enumerate(queries)}
     scores = [o.cpu().numpy() for o in outs]
+    # sorting stage: the 100 best hits of the last query, checked against a host sort
+    h.topk(outs[-1], 100)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    idx, sc = h.topk(outs[-1], 100)
+    topk_ms = (time.perf_counter() - t) * 1e3
+    order = np.lexsort((np.arange(db.n_seqs), -scores[-1].astype(np.int64)))[:len(idx)]
+    topk = {"k": 100, "ms": round(topk_ms, 3),
+            "exact": bool(np.array_equal(idx, order) and np.array_equal(sc, scores[-1][order]))}
     h.free()
-    return elapsed, timing, per_query, scores
+    return elapsed, timing, per_query, scores, topk
 
 
 def bench_search(args, w, label):
@@ -174,7 +187,7 @@ def bench_search(args, w, label):
     db = w.make_db()
     queries = w.make_queries()
     D = int(db.offsets[-1])
-    elapsed, timing, per_query, scores = run_searches(args, w, db, queries)
+    elapsed, timing, per_query, scores, topk = run_searches(args, w, db, queries)
     cells_per_step = sum(len(q) for q in queries) * D
     gcups = cells_per_step * args.steps / elapsed / 1e9
     n16, ms16 = timing[swmi.SW_KERNEL_INTER16]
@@ -195,6 +208,7 @@ def bench_search(args, w, label):
               "gap_open": w.gap_open, "gap_extend": w.gap_extend}
     result = base_result(args, gcups, elapsed, "i16+i32", config)
     result["per_query_gcups"] = per_query
+    result["topk"] = topk
     result["roofline"] = roof
     result["kernel_ms_per_step"] = {
         "k_inter16": round(ms16 / args.steps, 3),

@@ -189,6 +189,26 @@ int sw_server_stats(sw_server *server, int64_t *launches, int64_t *max_in_flight
                     int64_t *refused);
 void sw_server_free(sw_server *server);
 
+/*
+ * sw_topk -- sorting stage (Section 4, step 3: scores sorted in descending order),
+ * restricted to the k best hits: selects, on the device, the min(k, n_seqs) highest
+ * scores of a search and returns them sorted by score descending, ties by database index
+ * ascending.
+ *
+ *   scores_dev  device, int32[sw_db_size(db)]: scores in the caller's order (for example
+ *               the output of sw_search_async; the call orders itself after earlier work
+ *               on hip_stream).
+ *   k           1..4096.
+ *   hit_index, hit_score   host, int32[k]: database index and score of each hit.
+ *   n_hits      host: number of hits written (min(k, n_seqs)).
+ *   hip_stream  a hipStream_t (NULL = default stream); the call blocks until done.
+ *
+ * Calls on one database handle are serialised.  Errors: SW_ENODB, SW_EINVAL (k out of
+ * range or NULL output), SW_ENOMEM, SW_EDEVICE.
+ */
+int sw_topk(const sw_db *db, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
+            int32_t *hit_score, int32_t *n_hits, void *hip_stream);
+
 /* Static message for an error code. */
 const char *sw_strerror(int code);
 
@@ -225,7 +245,10 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *   SW_KNOB_MEM_CAP_MB     refuse workspaces beyond this many MiB (0 = no cap);
  *   SW_KNOB_ROUTE_LEN      database groups whose longest sequence exceeds this go to the
  *                          intra-task kernel for the search (0 = automatic: about twice
- *                          the residues per inter-task lane).
+ *                          the residues per inter-task lane);
+ *   SW_KNOB_WIDE_LEN       intra-task pairs at least this long (with two or more query
+ *                          bands) are swept by a whole workgroup, shorter ones by one
+ *                          wave (0 = automatic: 1152).
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -233,6 +256,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_GRID_WAVES     4
 #define SW_KNOB_MEM_CAP_MB     5
 #define SW_KNOB_ROUTE_LEN      6
+#define SW_KNOB_WIDE_LEN       7
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

@@ -30,6 +30,7 @@ std::atomic<int64_t> g_knob_strip_rows{0};
 std::atomic<int64_t> g_knob_grid_waves{0};
 std::atomic<int64_t> g_knob_mem_cap_mb{0};
 std::atomic<int64_t> g_knob_route_len{0};
+std::atomic<int64_t> g_knob_wide_len{0};
 
 struct HipFail {
   hipError_t err;
@@ -104,6 +105,8 @@ struct sw_db {
   std::mutex mu;
   std::vector<Workspace *> pool;
   std::atomic<bool> timing{false};
+  std::mutex topk_mu;
+  DevBuf topk_scratch;  // TopkState, 256 counters, kTopkMax keys, 2 x kTopkMax results
   struct TimedLaunch {
     int kind;
     hipEvent_t e0, e1;
@@ -311,7 +314,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     it.out = orig;
     it.query = (int32_t)q;
     const double cost = (double)len * (double)lens[q];
-    const bool is_wide = len >= 64 * 6 * kIntraLag && p.qd[q].nbands >= 2;
+    const int64_t wide_len = g_knob_wide_len.load() > 0 ? g_knob_wide_len.load()
+                                                        : (int64_t)64 * 6 * kIntraLag;
+    const bool is_wide = len >= wide_len && p.qd[q].nbands >= 2;
     (is_wide ? wide : narrow).emplace_back(cost, it);
   };
   for (int64_t q = 0; q < nq; ++q) {
@@ -518,6 +523,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
     case SW_KNOB_GRID_WAVES: if (value < 0 || value > 64) return SW_EINVAL; g_knob_grid_waves = value; return SW_OK;
     case SW_KNOB_MEM_CAP_MB: if (value < 0) return SW_EINVAL; g_knob_mem_cap_mb = value; return SW_OK;
     case SW_KNOB_ROUTE_LEN: if (value < 0) return SW_EINVAL; g_knob_route_len = value; return SW_OK;
+    case SW_KNOB_WIDE_LEN: if (value < 0) return SW_EINVAL; g_knob_wide_len = value; return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -530,6 +536,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_GRID_WAVES: return g_knob_grid_waves.load();
     case SW_KNOB_MEM_CAP_MB: return g_knob_mem_cap_mb.load();
     case SW_KNOB_ROUTE_LEN: return g_knob_route_len.load();
+    case SW_KNOB_WIDE_LEN: return g_knob_wide_len.load();
     default: return SW_EINVAL;
   }
 }
@@ -673,6 +680,7 @@ SW_API void sw_db_free(sw_db *db) {
     (void)hipEventDestroy(e.e1);
   }
   db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+  db->topk_scratch.release();
   delete db;
 }
 
@@ -1201,4 +1209,45 @@ SW_API void sw_server_free(sw_server *sv) {
   }
   for (auto &kv : sv->requests) delete kv.second;
   delete sv;
+}
+
+// ------------------------------------------------------------------------ sorting stage
+SW_API int sw_topk(const sw_db *cdb, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
+                   int32_t *hit_score, int32_t *n_hits, void *hip_stream) {
+  if (!cdb) return SW_ENODB;
+  if (k < 1 || k > kTopkMax || !n_hits || !hit_index || !hit_score) return SW_EINVAL;
+  sw_db *db = const_cast<sw_db *>(cdb);
+  const int64_t n = db->n_seqs;
+  if (n > 0 && !scores_dev) return SW_EINVAL;
+  const int32_t kk = (int32_t)std::min<int64_t>(k, n);
+  *n_hits = 0;
+  if (kk == 0) return SW_OK;
+  std::lock_guard<std::mutex> lk(db->topk_mu);
+  try {
+    hip_check(hipSetDevice(db->device));
+    const size_t off_hist = 64, off_list = off_hist + 256 * 4, off_idx = off_list + kTopkMax * 8,
+                 off_sc = off_idx + kTopkMax * 4, total = off_sc + kTopkMax * 4;
+    grow(db->topk_scratch, total);
+    uint8_t *base = (uint8_t *)db->topk_scratch.ptr;
+    TopkArgs a;
+    a.scores = scores_dev;
+    a.n = n;
+    a.k = kk;
+    a.state = (TopkState *)base;
+    a.hist = (uint32_t *)(base + off_hist);
+    a.list = (uint64_t *)(base + off_list);
+    a.hit_index = (int32_t *)(base + off_idx);
+    a.hit_score = (int32_t *)(base + off_sc);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hip_check(launch_topk(a, s));
+    hip_check(hipMemcpyAsync(hit_index, a.hit_index, (size_t)kk * 4, hipMemcpyDeviceToHost, s));
+    hip_check(hipMemcpyAsync(hit_score, a.hit_score, (size_t)kk * 4, hipMemcpyDeviceToHost, s));
+    hip_check(hipStreamSynchronize(s));
+  } catch (const HipFail &f) {
+    return map_hip(f.err);
+  } catch (const std::bad_alloc &) {
+    return SW_ENOMEM;
+  }
+  *n_hits = kk;
+  return SW_OK;
 }

@@ -118,7 +118,27 @@ struct PackArgs {
   uint8_t *packed;
 };
 
+// Top-k selection state (device memory); prefix/remaining start at 0/k, count at 0.
+struct TopkState {
+  uint64_t prefix;     // high digits of the k-th largest key found so far
+  uint32_t remaining;  // rank of the k-th key within the keys matching the prefix
+  uint32_t count;      // keys collected
+};
+constexpr int kTopkMax = 4096;
+
+struct TopkArgs {
+  const int32_t *scores;  // n scores in the caller's order
+  int64_t n;
+  int32_t k;              // 1..min(n, kTopkMax)
+  TopkState *state;
+  uint32_t *hist;         // 256 counters, zero on entry
+  uint64_t *list;         // k keys
+  int32_t *hit_index;     // k results (device)
+  int32_t *hit_score;
+};
+
 // Launchers (kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_topk(const TopkArgs &a, hipStream_t s);
 hipError_t launch_profile(const ProfileArgs &a, hipStream_t s);
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s);

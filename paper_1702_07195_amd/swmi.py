@@ -26,13 +26,14 @@ SW_KNOB_STRIP_ROWS = 3
 SW_KNOB_GRID_WAVES = 4
 SW_KNOB_MEM_CAP_MB = 5
 SW_KNOB_ROUTE_LEN = 6
+SW_KNOB_WIDE_LEN = 7
 
 # Every entry point declared in include/swmi.h.
 SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_async",
            "sw_search_batch", "sw_strerror", "sw_timing_enable", "sw_timing_read",
            "sw_timing_read_kernel", "sw_set_knob", "sw_get_knob", "sw_plan_create",
            "sw_plan_launch", "sw_plan_free", "sw_server_create", "sw_server_submit",
-           "sw_server_wait", "sw_server_stats", "sw_server_free")
+           "sw_server_wait", "sw_server_stats", "sw_server_free", "sw_topk")
 
 SW_KERNEL_INTER16 = 0
 SW_KERNEL_INTRA_LONG = 1
@@ -111,6 +112,8 @@ def lib():
         L.sw_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p]
         L.sw_server_free.restype = None
         L.sw_server_free.argtypes = [_vp]
+        L.sw_topk.restype = ctypes.c_int
+        L.sw_topk.argtypes = [_vp, _vp, ctypes.c_int32, _i32p, _i32p, _i32p, _vp]
         L.sw_set_knob.restype = ctypes.c_int
         L.sw_set_knob.argtypes = [ctypes.c_int32, ctypes.c_int64]
         L.sw_get_knob.restype = ctypes.c_int64
@@ -251,6 +254,19 @@ class SwDb:
                                   ctypes.byref(handle))
         _check(rc, "sw_plan_create")
         return SwPlan(handle, self, scores_dev)
+
+    def topk(self, scores_dev, k: int, stream=None):
+        """The k best hits of a search: (database indices, scores), score descending,
+        ties by index ascending; ``scores_dev`` is the int32 device tensor of scores."""
+        idx = np.zeros(k, dtype=np.int32)
+        sc = np.zeros(k, dtype=np.int32)
+        nh = ctypes.c_int32(0)
+        sptr = 0 if stream is None else int(stream.cuda_stream)
+        rc = lib().sw_topk(self.handle, _vp(scores_dev.data_ptr()), int(k),
+                           idx.ctypes.data_as(_i32p), sc.ctypes.data_as(_i32p),
+                           ctypes.byref(nh), _vp(sptr))
+        _check(rc, "sw_topk")
+        return idx[:nh.value], sc[:nh.value]
 
     def timing_enable(self, on: bool = True):
         _check(lib().sw_timing_enable(self.handle, 1 if on else 0), "sw_timing_enable")

@@ -281,3 +281,53 @@ def test_server_memory_admission(small_db, small_handle):
             sv.wait(t)
         assert e.value.code == swmi.SW_ENOMEM
         assert sv.stats()["refused"] == 1
+
+
+def _expected_hits(scores, k):
+    order = np.lexsort((np.arange(len(scores)), -scores.astype(np.int64)))
+    return order[:k], scores[order[:k]]
+
+
+@pytest.mark.parametrize("k", [1, 7, 100, 699, 700, 4096])
+def test_topk_matches_oracle_order(small_db, small_handle, k):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(51))
+    q = synth.residues(rng, 90)
+    want_scores = _oracle(q, small_db, synth.BLOSUM62, 10, 2)
+    out = torch.zeros(small_db.n_seqs, dtype=torch.int32, device="cuda")
+    small_handle.search_async(q, synth.BLOSUM62, 10, 2, out)
+    _say(f"topk k={k}")
+    idx, sc = small_handle.topk(out, k)
+    wi, ws = _expected_hits(want_scores, min(k, small_db.n_seqs))
+    assert np.array_equal(idx, wi) and np.array_equal(sc, ws)
+
+
+def test_topk_ties_and_zero_scores():
+    import torch
+    seqs = [synth.encode("WWWW")] * 50 + [synth.encode("AAAA")] * 30 + [np.zeros(0, np.uint8)] * 20
+    order = np.random.Generator(np.random.PCG64(52)).permutation(len(seqs))
+    db = synth.db_from_seqs([seqs[i] for i in order])
+    q = synth.encode("WWWWCC")
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        out = torch.zeros(db.n_seqs, dtype=torch.int32, device="cuda")
+        h.search_async(q, synth.BLOSUM62, 10, 2, out)
+        for k in (1, 49, 50, 51, 85, 100, 200):
+            idx, sc = h.topk(out, k)
+            wi, ws = _expected_hits(out.cpu().numpy(), min(k, db.n_seqs))
+            assert np.array_equal(idx, wi) and np.array_equal(sc, ws), k
+        with pytest.raises(swmi.SwError):
+            h.topk(out, 4097)
+
+
+def test_search_of_fasta_database(tmp_path):
+    from paper_1702_07195_amd import fasta
+    rng = np.random.Generator(np.random.PCG64(62))
+    db = synth.db_from_lengths(rng, synth.lognormal_lengths(rng, 300, 150, 0.8, 1, 900))
+    fasta.write_fasta(str(tmp_path / "d.fa"), [f"s{k}" for k in range(db.n_seqs)], db)
+    _, db2 = fasta.read_fasta(str(tmp_path / "d.fa"))
+    fasta.save_binary(str(tmp_path / "d.swdb"), db2)
+    db3, alpha = fasta.load_binary(str(tmp_path / "d.swdb"))
+    q = synth.residues(rng, 222)
+    with swmi.sw_db_load(db3.residues, db3.offsets, alpha) as h:
+        got = h.search(q, synth.BLOSUM62, 10, 2)
+    assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
