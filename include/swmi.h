@@ -248,7 +248,9 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          the residues per inter-task lane);
  *   SW_KNOB_WIDE_LEN       intra-task pairs at least this long (with two or more query
  *                          bands) are swept by a whole workgroup, shorter ones by one
- *                          wave (0 = automatic: 1152).
+ *                          wave (0 = automatic: 1152);
+ *   SW_KNOB_MAX_SEGMENTS   most workgroups one intra-task pair may be split across
+ *                          (0 = automatic, 1 = never split).
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -257,6 +259,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_MEM_CAP_MB     5
 #define SW_KNOB_ROUTE_LEN      6
 #define SW_KNOB_WIDE_LEN       7
+#define SW_KNOB_MAX_SEGMENTS   8
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

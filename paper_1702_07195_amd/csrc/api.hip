@@ -3,6 +3,7 @@
 // workspaces, and the launch sequence of one search.
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -31,6 +32,7 @@ std::atomic<int64_t> g_knob_grid_waves{0};
 std::atomic<int64_t> g_knob_mem_cap_mb{0};
 std::atomic<int64_t> g_knob_route_len{0};
 std::atomic<int64_t> g_knob_wide_len{0};
+std::atomic<int64_t> g_knob_max_segments{0};
 
 struct HipFail {
   hipError_t err;
@@ -71,11 +73,12 @@ struct Workspace {
   bool timed[3] = {false, false, false};
   bool busy = false;
   DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp32, ctr, flagged, longitems, bnd16,
-      bnd32, scores;
+      bnd32, xbnd, xprog, scores;
   HostBuf staging;
   size_t total_bytes() const {
     return queries.bytes + qoff.bytes + qdesc.bytes + qorder.bytes + matrix.bytes + qp16.bytes + qp32.bytes +
-           ctr.bytes + flagged.bytes + longitems.bytes + bnd16.bytes + bnd32.bytes + scores.bytes;
+           ctr.bytes + flagged.bytes + longitems.bytes + bnd16.bytes + bnd32.bytes + xbnd.bytes +
+           xprog.bytes + scores.bytes;
   }
 };
 
@@ -142,7 +145,8 @@ void destroy_workspace(Workspace *w) {
   if (w->own) (void)hipStreamSynchronize(w->own);
   if (w->aux) (void)hipStreamSynchronize(w->aux);
   for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->qorder, &w->matrix, &w->qp16, &w->qp32, &w->ctr,
-                    &w->flagged, &w->longitems, &w->bnd16, &w->bnd32, &w->scores})
+                    &w->flagged, &w->longitems, &w->bnd16, &w->bnd32, &w->xbnd, &w->xprog,
+                    &w->scores})
     b->release();
   w->staging.release();
   for (hipEvent_t e : {w->done, w->fork, w->join, w->t0[0], w->t1[0], w->t0[1], w->t1[1],
@@ -241,6 +245,8 @@ int choose_T(const std::vector<int64_t> &lens) {
 
 struct Plan {
   int T = 32;
+  int64_t xbnd_elems = 0;  // int2 elements of the boundary rows between pair segments
+  int32_t nprog = 0;       // progress counters of those boundaries
   int32_t ngroups_inter = 0;
   int32_t n_wide = 0;
   int grid16 = 0;
@@ -313,6 +319,12 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     it.len = len;
     it.out = orig;
     it.query = (int32_t)q;
+    it.band0 = 0;
+    it.band1 = p.qd[q].nbands;
+    it.xin = it.xout = -1;
+    it.prog_in = it.prog_out = -1;
+    it.segment = 0;
+    it.nsegments = 1;
     const double cost = (double)len * (double)lens[q];
     const int64_t wide_len = g_knob_wide_len.load() > 0 ? g_knob_wide_len.load()
                                                         : (int64_t)64 * 6 * kIntraLag;
@@ -333,13 +345,50 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   };
   std::stable_sort(wide.begin(), wide.end(), by_cost);
   std::stable_sort(narrow.begin(), narrow.end(), by_cost);
-  p.n_wide = (int32_t)wide.size();
-  for (auto &x : wide) p.longitems.push_back(x.second);
+  // A wide pair whose cells exceed one compute unit's share of this search's intra-task
+  // work would finish after everything else, so it is split into S segments of
+  // consecutive bands (S = its cells over that share, at most one segment per
+  // kIntraWaves bands), each its own work item on its own workgroup; segments of a pair
+  // are consecutive in the list, so segment j is always claimed after segment j - 1 (the
+  // only one it waits for).  Splitting costs pipeline fill, so smaller pairs stay whole.
+  double intra_cells = 0;
+  for (auto &x : wide) intra_cells += x.first;
+  for (auto &x : narrow) intra_cells += x.first;
+  const double cu_share = intra_cells / std::max(1, db->num_cu);
+  for (auto &x : wide) {
+    const PairItem &it = x.second;
+    const int32_t nb = it.band1;
+    const int32_t max_seg = std::max<int32_t>(1, (nb + kIntraWaves - 1) / kIntraWaves);
+    const int32_t want = cu_share > 0 ? (int32_t)std::ceil(x.first / cu_share) : 1;
+    const int64_t cap = g_knob_max_segments.load();
+    int32_t S = std::max<int32_t>(1, std::min(max_seg, want));
+    if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
+    const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
+    for (int32_t j = 0; j < S; ++j) {
+      PairItem sg = it;
+      sg.band0 = (int32_t)((int64_t)nb * j / S);
+      sg.band1 = (int32_t)((int64_t)nb * (j + 1) / S);
+      sg.segment = j;
+      sg.nsegments = S;
+      if (j > 0) {
+        sg.xin = p.xbnd_elems - npad;
+        sg.prog_in = p.nprog - 1;
+      }
+      if (j + 1 < S) {
+        sg.xout = p.xbnd_elems;
+        sg.prog_out = p.nprog;
+        p.xbnd_elems += npad;
+        p.nprog += 1;
+      }
+      p.longitems.push_back(sg);
+    }
+  }
+  p.n_wide = (int32_t)p.longitems.size();
   for (auto &x : narrow) p.longitems.push_back(x.second);
 
   const int64_t nitems16 = (int64_t)ninter * nq;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
-  p.grid_long = (int)std::min<int64_t>((int64_t)wide.size() + ((int64_t)narrow.size() + kIntraWaves - 1) / kIntraWaves,
+  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + ((int64_t)narrow.size() + kIntraWaves - 1) / kIntraWaves,
                                        4LL * db->num_cu);
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not
   p.grid_re = (db->n_short > 0 && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
@@ -356,7 +405,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     size_t need = (size_t)qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
                   (size_t)p.qp16_elems * 2 + (size_t)p.qp32_elems * 2 + sizeof(Counters) +
                   need_flagged * sizeof(PairItem) + p.longitems.size() * sizeof(PairItem) +
-                  (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8;
+                  (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8 +
+                  (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
     if (cap_mb > 0 && (int64_t)(std::max(need, w->total_bytes()) >> 20) > cap_mb)
       throw HipFail{hipErrorOutOfMemory};
   }
@@ -372,6 +422,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   grow(w->longitems, std::max<size_t>(1, p.longitems.size()) * sizeof(PairItem));
   grow(w->bnd16, std::max<size_t>(1, (size_t)p.grid16 * bnd16_slot) * 4);
   grow(w->bnd32, std::max<size_t>(1, (size_t)grid32 * bnd32_slot) * 8);
+  grow(w->xbnd, (size_t)std::max<int64_t>(1, p.xbnd_elems) * 8);
+  // per segment boundary: progress, finished flag (both cleared per search), maximum
+  grow(w->xprog, (size_t)std::max<int32_t>(1, p.nprog) * 12);
 
   // stage small inputs through pinned memory (reused only after `done`)
   const size_t off_qoff = ((size_t)qbytes + 63) & ~size_t(63);
@@ -410,6 +463,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   pa.qp16 = (int16_t *)w->qp16.ptr;
   pa.qp32 = (int16_t *)w->qp32.ptr;
   pa.ctr = ctr;
+  pa.zero = (int32_t *)w->xprog.ptr;
+  pa.nzero = 2 * (int64_t)std::max<int32_t>(1, p.nprog);
   if (nq > 0) hip_check(launch_profile(pa, s));
 
   // long sequences: intra-task kernel on the auxiliary stream, concurrent with the sweep
@@ -432,6 +487,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.bnd = (int2 *)w->bnd32.ptr;
     ia.bnd_slot_elems = (int64_t)bnd32_slot;
     ia.bnd_stride = bnd32_stride;
+    ia.xbnd = (int2 *)w->xbnd.ptr;
+    ia.xprog = (int32_t *)w->xprog.ptr;
+    ia.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
+    ia.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
+    ia.error = &ctr->error;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
     hip_check(launch_intra32(ia, kIntraR, kIntraWaves, p.grid_long, w->aux));
@@ -487,6 +547,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.bnd = (int2 *)w->bnd32.ptr + (size_t)p.grid_long * bnd32_slot;
     ra.bnd_slot_elems = (int64_t)bnd32_slot;
     ra.bnd_stride = bnd32_stride;
+    ra.xbnd = (int2 *)w->xbnd.ptr;
+    ra.xprog = (int32_t *)w->xprog.ptr;
+    ra.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
+    ra.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
+    ra.error = &ctr->error;
     if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
     hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
     if (timed && p.grid_re > 0) {
@@ -524,6 +589,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
     case SW_KNOB_MEM_CAP_MB: if (value < 0) return SW_EINVAL; g_knob_mem_cap_mb = value; return SW_OK;
     case SW_KNOB_ROUTE_LEN: if (value < 0) return SW_EINVAL; g_knob_route_len = value; return SW_OK;
     case SW_KNOB_WIDE_LEN: if (value < 0) return SW_EINVAL; g_knob_wide_len = value; return SW_OK;
+    case SW_KNOB_MAX_SEGMENTS: if (value < 0) return SW_EINVAL; g_knob_max_segments = value; return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -537,6 +603,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_MEM_CAP_MB: return g_knob_mem_cap_mb.load();
     case SW_KNOB_ROUTE_LEN: return g_knob_route_len.load();
     case SW_KNOB_WIDE_LEN: return g_knob_wide_len.load();
+    case SW_KNOB_MAX_SEGMENTS: return g_knob_max_segments.load();
     default: return SW_EINVAL;
   }
 }
@@ -727,7 +794,12 @@ int run_search(const sw_db *cdb, const uint8_t *queries, const int64_t *qoff, in
     if (host_out) {
       if (nscores > 0)
         hip_check(hipMemcpyAsync(host_out, scores, nscores * 4, hipMemcpyDeviceToHost, s));
+      int32_t err = 0;
+      if (nscores > 0 && w->ctr.ptr)
+        hip_check(hipMemcpyAsync(&err, &((Counters *)w->ctr.ptr)->error, 4,
+                                 hipMemcpyDeviceToHost, s));
       hip_check(hipStreamSynchronize(s));
+      if (err) throw HipFail{hipErrorLaunchTimeOut};
     }
     hand_over_timing(db, w);
     release(db, w);

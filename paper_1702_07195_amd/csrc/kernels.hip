@@ -53,6 +53,10 @@ __device__ __forceinline__ int32_t subu(int32_t a, int32_t b) {
 __global__ void k_profile(ProfileArgs a) {
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < sizeof(Counters) / 4)
     reinterpret_cast<int32_t *>(a.ctr)[threadIdx.x] = 0;
+  if (blockIdx.y == 0)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.nzero;
+         e += (int64_t)gridDim.x * blockDim.x)
+      a.zero[e] = 0;
   const int q = blockIdx.y;
   const QueryDesc d = a.queries[q];
   const uint8_t *qs = a.query + a.qoff[q];
@@ -315,6 +319,12 @@ void k_inter16(InterArgs a) {
         it.len = a.lens[p];
         it.out = orig;
         it.query = qi;
+        it.band0 = 0;
+        it.band1 = qd.nbands;
+        it.xin = it.xout = -1;
+        it.prog_in = it.prog_out = -1;
+        it.segment = 0;
+        it.nsegments = 1;
         a.flagged[k] = it;
       } else {
         a.scores[qd.out + orig] = sc;
@@ -385,7 +395,8 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
                               int w, int2 *ring) {
   const int lane = threadIdx.x & 63;
   const int n = pi.len;
-  const int nb = qd.nbands;
+  const int b_lo = pi.band0;
+  const int nb = pi.band1 - pi.band0;  // bands of this segment
   int32_t vmax = 0;
   if (n <= 0 || nb <= 0) return 0;
   const int nc = (n + 63 + 63) / 64;  // chunks covering n + 63 steps
@@ -395,7 +406,7 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
   const uint8_t *resbase = a.packed + pi.base;
   const int cs = pi.cstride;
 
-  int b = w;  // band this wave works on
+  int bl = w;  // band of this segment that this wave works on
   int32_t Hs[R], Es[R];
   int32_t hbot = 0, fbot = 0, hdiag = 0, code = kPadCode;
   int2 tq = make_int2(0, 0);  // band-top (H, F) for columns 64k + lane
@@ -404,13 +415,39 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
   for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
 
   for (int rd = 0; rd < rounds; ++rd) {
-    if (b < nb) {
-      const int st = (b / NW) * nce + kIntraLag * (b % NW);
+    if (bl < nb) {
+      const int st = (bl / NW) * nce + kIntraLag * (bl % NW);
       if (rd >= st && rd < st + nc) {
         const int k = rd - st;
-        const int2 *top = ring + (int64_t)((b + NW) % (NW + 1)) * a.bnd_stride;
-        int2 *bot = ring + (int64_t)(b % (NW + 1)) * a.bnd_stride;
-        const bool has_top = b > 0, has_bot = b < nb - 1;
+        const int b = b_lo + bl;  // query band
+        // the first band of a later segment reads the previous segment's bottom row,
+        // the last band of an earlier segment writes its own for the next segment
+        const bool ext_top = bl == 0 && pi.xin >= 0;
+        const bool ext_bot = bl == nb - 1 && pi.xout >= 0;
+        const int2 *top = ext_top ? a.xbnd + pi.xin
+                                  : ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride;
+        int2 *bot = ext_bot ? a.xbnd + pi.xout : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
+        const bool has_top = bl > 0 || ext_top;
+        const bool has_bot = bl < nb - 1 || ext_bot;
+        if (ext_top) {
+          // wait until the columns this chunk and the next read are published
+          const int need = min(n, 64 * (k + 2));
+          // (bounded: after kSpinLimit polls, or once any wait has given up, the flag is
+          // set and the kernel runs to its end with whatever the buffer holds)
+          // (polled relaxed, then one acquire fence: an acquire load per poll would
+          // invalidate the cache on every iteration)
+          int polls = 0;
+          while (__hip_atomic_load(a.xprog + pi.prog_in, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            __builtin_amdgcn_s_sleep(4);
+            if (++polls > kSpinLimit) {
+              __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
         if (k == 0) {
 #pragma unroll
           for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
@@ -475,9 +512,16 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
           fbot = f;
           if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
         }
+        if (ext_bot) {
+          // columns 0 .. 64k of the bottom row are written (all of them after the last
+          // chunk); every lane stores the same count with release order
+          const int done = k == nc - 1 ? n : min(n, 64 * k + 1);
+          __hip_atomic_store(a.xprog + pi.prog_out, done, __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        }
         tq = tq_next;
         rq = rq_next;
-        if (k == nc - 1) b += NW;
+        if (k == nc - 1) bl += NW;
       }
     }
     if (NW > 1) __syncthreads();
@@ -516,7 +560,30 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
     if (threadIdx.x == 0) {
       int m = 0;
       for (int i = 0; i < W; ++i) m = max(m, s_max[i]);
-      a.scores[qd.out + pi.out] = m;
+      // Segments of a split pair chain their maxima: each waits for the previous
+      // segment's "finished" flag, takes the maximum so far, and passes it on; the last
+      // segment writes the score.  Waits point only to earlier segments.
+      if (pi.segment > 0) {
+        int polls = 0;
+        while (__hip_atomic_load(a.xfin + pi.prog_in, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+          __builtin_amdgcn_s_sleep(4);
+          if (++polls > kSpinLimit) {
+            __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        m = max(m, __hip_atomic_load(a.xmax + pi.prog_in, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT));
+      }
+      if (pi.segment + 1 < pi.nsegments) {
+        __hip_atomic_store(a.xmax + pi.prog_out, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.xfin + pi.prog_out, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        a.scores[qd.out + pi.out] = m;
+      }
     }
   }
 

@@ -27,14 +27,23 @@ struct GroupDesc {
   int32_t maxlen;
 };
 
-// One (query, database sequence) pair for the int32 intra-task kernel.  Residue of
-// column c sits at packed[base + (c >> 2) * cstride + (c & 3)].
+// One (query, database sequence) pair -- or one segment of its query bands -- for the
+// int32 intra-task kernel.  Residue of column c sits at
+// packed[base + (c >> 2) * cstride + (c & 3)].  A long pair may be split into segments
+// of consecutive query bands [band0, band1) that run on different workgroups: segment
+// j reads the bottom row of segment j - 1 from xbnd[xin ..] once the progress counter
+// xprog[prog_in] says it is there, and publishes its own bottom row to xbnd[xout ..] and
+// xprog[prog_out]; -1 marks "no neighbour".
 struct PairItem {
   int64_t base;
   int32_t cstride;  // 256 for a sequence inside a group, 4 for a contiguous one
   int32_t len;
   int32_t out;      // index into the score array (caller's database order)
   int32_t query;    // query index (batched search), 0 otherwise
+  int32_t band0, band1;
+  int64_t xin, xout;
+  int32_t prog_in, prog_out;
+  int32_t segment, nsegments;
 };
 
 // Per-query data used by both kernels.
@@ -56,7 +65,8 @@ struct Counters {
   int32_t recompute_next; // next wide intra-task item (recompute list)
   int32_t intra_narrow;   // next narrow intra-task item (long list)
   int32_t recompute_narrow;  // next narrow intra-task item (recompute list)
-  int32_t pad[2];
+  int32_t error;          // set if a bounded wait between segments ran out
+  int32_t pad;
 };
 
 struct InterArgs {
@@ -94,6 +104,11 @@ struct IntraArgs {
   int2 *bnd;                 // band boundary scratch, one slot per persistent workgroup
   int64_t bnd_slot_elems;    // int2 elements per slot (>= 2 * waves * bnd_stride)
   int32_t bnd_stride;        // int2 elements per band buffer (>= max len + 128)
+  int2 *xbnd;                // boundary rows between segments of split pairs
+  int32_t *xprog;            // columns published per segment boundary
+  int32_t *xfin;             // 1 once the segment before the boundary has finished
+  int32_t *xmax;             // maximum of H so far, passed along the segments of a pair
+  int32_t *error;            // Counters::error
 };
 
 struct ProfileArgs {
@@ -107,6 +122,8 @@ struct ProfileArgs {
   int16_t *qp16;
   int16_t *qp32;
   Counters *ctr;
+  int32_t *zero;             // an int32 array cleared with the counters (segment progress)
+  int64_t nzero;
 };
 
 struct PackArgs {
@@ -151,5 +168,6 @@ int inter16_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
 constexpr int kIntraWaves = 8;
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
+constexpr int kSpinLimit = 1 << 24;  // polls before a wait between segments gives up
 
 }  // namespace swmi

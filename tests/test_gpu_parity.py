@@ -331,3 +331,23 @@ def test_search_of_fasta_database(tmp_path):
     with swmi.sw_db_load(db3.residues, db3.offsets, alpha) as h:
         got = h.search(q, synth.BLOSUM62, 10, 2)
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
+
+
+@pytest.mark.parametrize("m", [9000, 17000])
+def test_split_pairs_across_workgroups(m):
+    # Queries with more query bands than a workgroup has waves: wide pairs are split
+    # into segments on different workgroups that hand the boundary row over through
+    # global memory; every sequence is routed to the intra-task kernel.
+    rng = np.random.Generator(np.random.PCG64(70 + m))
+    lengths = np.concatenate([rng.integers(1200, 3000, 6), rng.integers(1, 900, 40)])
+    db = synth.db_from_lengths(rng, lengths)
+    q = synth.residues(rng, m)
+    old = swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN)
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+    try:
+        _say(f"split pairs m={m}")
+        with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+            got = h.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
+    assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
