@@ -72,11 +72,11 @@ struct Workspace {
   hipEvent_t t0[3] = {}, t1[3] = {};  // kernel timing: inter-task, long intra, recompute
   bool timed[3] = {false, false, false};
   bool busy = false;
-  DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp32, ctr, flagged, longitems, bnd16,
+  DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp8, ctr, flagged, longitems, bnd16,
       bnd32, xbnd, xprog, scores;
   HostBuf staging;
   size_t total_bytes() const {
-    return queries.bytes + qoff.bytes + qdesc.bytes + qorder.bytes + matrix.bytes + qp16.bytes + qp32.bytes +
+    return queries.bytes + qoff.bytes + qdesc.bytes + qorder.bytes + matrix.bytes + qp16.bytes + qp8.bytes +
            ctr.bytes + flagged.bytes + longitems.bytes + bnd16.bytes + bnd32.bytes + xbnd.bytes +
            xprog.bytes + scores.bytes;
   }
@@ -144,7 +144,7 @@ void grow_host(HostBuf &b, size_t bytes) {
 void destroy_workspace(Workspace *w) {
   if (w->own) (void)hipStreamSynchronize(w->own);
   if (w->aux) (void)hipStreamSynchronize(w->aux);
-  for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->qorder, &w->matrix, &w->qp16, &w->qp32, &w->ctr,
+  for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->qorder, &w->matrix, &w->qp16, &w->qp8, &w->ctr,
                     &w->flagged, &w->longitems, &w->bnd16, &w->bnd32, &w->xbnd, &w->xprog,
                     &w->scores})
     b->release();
@@ -254,7 +254,7 @@ struct Plan {
   int grid_re = 0;
   std::vector<QueryDesc> qd;
   std::vector<PairItem> longitems;
-  int64_t qp16_elems = 0, qp32_elems = 0;
+  int64_t qp16_elems = 0, qp8_elems = 0;
 };
 
 // Enqueue one (possibly batched) search on `s`.  Queries are host memory; scores go to
@@ -280,12 +280,12 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     d.m = (int32_t)lens[q];
     d.nstrips = (int32_t)((lens[q] + 2 * p.T - 1) / (2 * p.T));
     d.nbands = (int32_t)((lens[q] + band - 1) / band);
-    d.mpad32 = d.nbands * band;
+    d.mrows = d.nbands * band;
     d.qp16 = p.qp16_elems;
-    d.qp32 = p.qp32_elems;
+    d.qp8 = p.qp8_elems;
     d.out = q * db->n_seqs;
     p.qp16_elems += (int64_t)d.nstrips * kCodes * 2 * p.T;
-    p.qp32_elems += (int64_t)kCodes * d.mpad32;
+    p.qp8_elems += (int64_t)kCodes * d.mrows;
   }
   // launch geometry of the inter-task kernel
   int per_cu = (int)g_knob_grid_waves.load();
@@ -345,24 +345,34 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   };
   std::stable_sort(wide.begin(), wide.end(), by_cost);
   std::stable_sort(narrow.begin(), narrow.end(), by_cost);
-  // A wide pair whose cells exceed one compute unit's share of this search's intra-task
-  // work would finish after everything else, so it is split into S segments of
-  // consecutive bands (S = its cells over that share, at most one segment per
-  // kIntraWaves bands), each its own work item on its own workgroup; segments of a pair
-  // are consecutive in the list, so segment j is always claimed after segment j - 1 (the
-  // only one it waits for).  Splitting costs pipeline fill, so smaller pairs stay whole.
+  // Critical path of the longest pairs.  A workgroup sweeps its bands in rounds of
+  // kIntraWaves, so a pair of nb bands takes about ceil(nb / kIntraWaves) sweeps of its
+  // columns; cut into segments of at most kIntraWaves consecutive bands on workgroups of
+  // their own, the bands form one pipeline (nc + kIntraLag * (nb - 1) chunks), and with at
+  // most 4 bands per segment each band's wave has a SIMD to itself.  A pair is split as
+  // little as keeps its estimated time within the estimated time of the whole intra-task
+  // search; segments of a pair are consecutive in the list, so segment j is always
+  // claimed after segment j - 1 (the only one it waits for).
+  //   (one step of a wave: about 0.5 us with two waves per SIMD, 0.25 us alone; the
+  //   kernel sustains about 2.5e12 cells/s over the whole chip: MI355X measurements)
   double intra_cells = 0;
   for (auto &x : wide) intra_cells += x.first;
   for (auto &x : narrow) intra_cells += x.first;
-  const double cu_share = intra_cells / std::max(1, db->num_cu);
+  const double t_search = intra_cells / 2.5e12 * (256.0 / std::max(1, db->num_cu));
+  const int64_t cap = g_knob_max_segments.load();
   for (auto &x : wide) {
     const PairItem &it = x.second;
     const int32_t nb = it.band1;
-    const int32_t max_seg = std::max<int32_t>(1, (nb + kIntraWaves - 1) / kIntraWaves);
-    const int32_t want = cu_share > 0 ? (int32_t)std::ceil(x.first / cu_share) : 1;
-    const int64_t cap = g_knob_max_segments.load();
-    int32_t S = std::max<int32_t>(1, std::min(max_seg, want));
+    const int64_t nc = ((int64_t)it.len + 126) / 64;
+    const int64_t nce = std::max<int64_t>(nc, (int64_t)kIntraLag * kIntraWaves);
+    const int64_t lastb = nb - 1;
+    const double whole = (double)((lastb / kIntraWaves) * nce + kIntraLag * (lastb % kIntraWaves) + nc);
+    const double piped = (double)(nc + (int64_t)kIntraLag * lastb);
+    const int32_t s8 = (nb + kIntraWaves - 1) / kIntraWaves, s4 = (nb + 3) / 4;
+    int32_t S = 1;
+    if (whole * 64 * 0.5e-6 > t_search) S = piped * 64 * 0.5e-6 <= t_search ? s8 : s4;
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
+    S = std::max<int32_t>(1, std::min(S, nb));
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
     for (int32_t j = 0; j < S; ++j) {
       PairItem sg = it;
@@ -388,8 +398,12 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
 
   const int64_t nitems16 = (int64_t)ninter * nq;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
+  // One persistent workgroup (kIntraWaves waves) per compute unit: the kernel's
+  // per-step profile gathers touch one cache line per lane, and a second resident
+  // workgroup per CU measured slower and erratic on MI355X (86 ms vs 103-115 ms for a
+  // 35000-residue query over the long-sequence mix), not faster.
   p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + ((int64_t)narrow.size() + kIntraWaves - 1) / kIntraWaves,
-                                       4LL * db->num_cu);
+                                       (int64_t)db->num_cu);
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not
   p.grid_re = (db->n_short > 0 && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
   const int grid32 = p.grid_long + p.grid_re;
@@ -403,7 +417,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const int64_t cap_mb = g_knob_mem_cap_mb.load();
   {
     size_t need = (size_t)qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
-                  (size_t)p.qp16_elems * 2 + (size_t)p.qp32_elems * 2 + sizeof(Counters) +
+                  (size_t)p.qp16_elems * 2 + (size_t)p.qp8_elems + sizeof(Counters) +
                   need_flagged * sizeof(PairItem) + p.longitems.size() * sizeof(PairItem) +
                   (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8 +
                   (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
@@ -416,7 +430,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   grow(w->qorder, std::max<size_t>(1, nq) * sizeof(int32_t));
   grow(w->matrix, (size_t)A * A * 4);
   grow(w->qp16, (size_t)std::max<int64_t>(8, p.qp16_elems) * 2);
-  grow(w->qp32, (size_t)std::max<int64_t>(8, p.qp32_elems) * 2);
+  grow(w->qp8, (size_t)std::max<int64_t>(16, p.qp8_elems));
   grow(w->ctr, sizeof(Counters));
   grow(w->flagged, need_flagged * sizeof(PairItem));
   grow(w->longitems, std::max<size_t>(1, p.longitems.size()) * sizeof(PairItem));
@@ -461,7 +475,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   pa.alphabet = A;
   pa.T = p.T;
   pa.qp16 = (int16_t *)w->qp16.ptr;
-  pa.qp32 = (int16_t *)w->qp32.ptr;
+  pa.qp8 = (int8_t *)w->qp8.ptr;
   pa.ctr = ctr;
   pa.zero = (int32_t *)w->xprog.ptr;
   pa.nzero = 2 * (int64_t)std::max<int32_t>(1, p.nprog);
@@ -480,7 +494,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.next_narrow = &ctr->intra_narrow;
     ia.n_wide = p.n_wide;
     ia.queries = (const QueryDesc *)w->qdesc.ptr;
-    ia.qp32 = (const int16_t *)w->qp32.ptr;
+    ia.qp8 = (const int8_t *)w->qp8.ptr;
     ia.goe = gap_open + gap_extend;
     ia.ge = gap_extend;
     ia.scores = scores_dev;
@@ -540,7 +554,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.next_narrow = &ctr->recompute_narrow;
     ra.n_wide = 0;
     ra.queries = (const QueryDesc *)w->qdesc.ptr;
-    ra.qp32 = (const int16_t *)w->qp32.ptr;
+    ra.qp8 = (const int8_t *)w->qp8.ptr;
     ra.goe = gap_open + gap_extend;
     ra.ge = gap_extend;
     ra.scores = scores_dev;

@@ -47,7 +47,8 @@ __device__ __forceinline__ int32_t subu(int32_t a, int32_t b) {
 
 // ------------------------------------------------------------------------ profiles
 // Inter-task profile of query q: [nstrips][32 codes][2T rows] int16, so one strip's
-// slice is a contiguous block.  Intra-task profile: [32 codes][mpad32 rows] int16.
+// slice is a contiguous block.  Intra-task profile: [32 codes][mrows rows] int8 (every
+// matrix entry and kPadScore fit: the boundary rejects |entries| > 127).
 // Rows past the query end and codes outside the alphabet (including the padding code)
 // score kPadScore.
 __global__ void k_profile(ProfileArgs a) {
@@ -71,13 +72,13 @@ __global__ void k_profile(ProfileArgs a) {
     if (i < d.m && code < a.alphabet) v = a.matrix[qs[i] * a.alphabet + code];
     a.qp16[d.qp16 + e] = (int16_t)v;
   }
-  const int64_t n32 = (int64_t)kCodes * d.mpad32;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n32; e += stride) {
-    const int64_t i = e % d.mpad32;
-    const int code = (int)(e / d.mpad32);
+  const int64_t n8 = (int64_t)kCodes * d.mrows;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n8; e += stride) {
+    const int64_t i = e % d.mrows;
+    const int code = (int)(e / d.mrows);
     int v = kPadScore;
     if (i < d.m && code < a.alphabet) v = a.matrix[qs[i] * a.alphabet + code];
-    a.qp32[d.qp32 + e] = (int16_t)v;
+    a.qp8[d.qp8 + e] = (int8_t)v;
   }
 }
 
@@ -461,56 +462,59 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
             ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
         // this lane's R profile rows of band b; code c's rows start c * pstride bytes on
         const uint8_t *prof = reinterpret_cast<const uint8_t *>(
-            a.qp32 + qd.qp32 + (int64_t)b * 64 * R + lane * R);
-        const uint32_t pstride = (uint32_t)qd.mpad32 * 2u;
+            a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
+        const uint32_t pstride = (uint32_t)qd.mrows;
 
         // The code a lane needs at step s + 1 is its left neighbour's code at step s, so
-        // the profile rows of the next step are loaded one step ahead.
+        // the profile rows of the next step are loaded one step ahead, into the other of
+        // two buffers (steps go in pairs, so no buffer is ever copied).  Each row's
+        // diagonal sum H(i-1, j-1) + SM is formed before the row above is overwritten,
+        // which lets H stay in place from step to step.
         int code_next = wave_shr1(code, __builtin_amdgcn_readlane(rq, 0));
-        uint4 Pn[R / 8];
+        uint4 PA[R / 16], PB[R / 16];
 #pragma unroll
-        for (int r8 = 0; r8 < R; r8 += 8)
-          Pn[r8 >> 3] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code_next * pstride +
-                                                          2 * r8);
-        for (int i = 0; i < 64; ++i) {
+        for (int r16 = 0; r16 < R; r16 += 16)
+          PA[r16 >> 4] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code_next * pstride +
+                                                           r16);
+        auto step = [&](const int i, const uint4 (&P)[R / 16], uint4 (&Pnext)[R / 16]) {
           const int s = 64 * k + i;
           code = code_next;
-          uint4 P[R / 8];
-#pragma unroll
-          for (int r8 = 0; r8 < R; r8 += 8) P[r8 >> 3] = Pn[r8 >> 3];
           // prefetch for step s + 1 (the first column of the next chunk comes from rq_next)
           const int cin = i < 63 ? __builtin_amdgcn_readlane(rq, i + 1)
                                  : __builtin_amdgcn_readfirstlane(rq_next);
           code_next = wave_shr1(code, cin);
 #pragma unroll
-          for (int r8 = 0; r8 < R; r8 += 8)
-            Pn[r8 >> 3] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code_next * pstride +
-                                                            2 * r8);
+          for (int r16 = 0; r16 < R; r16 += 16)
+            Pnext[r16 >> 4] = *reinterpret_cast<const uint4 *>(
+                prof + (uint32_t)code_next * pstride + r16);
           const int hup = wave_shr1(hbot, __builtin_amdgcn_readlane(tq.x, i));
           int f = wave_shr1(fbot, __builtin_amdgcn_readlane(tq.y, i));
-          int hd = hdiag;
+          auto sm = [&](int r) {  // row r's score, sign-extended from its byte
+            const uint32_t v = r % 16 < 8 ? (r % 16 < 4 ? P[r / 16].x : P[r / 16].y)
+                                          : (r % 16 < 12 ? P[r / 16].z : P[r / 16].w);
+            return (int32_t)(int8_t)(v >> (8 * (r & 3)));
+          };
+          int x = hdiag + sm(0);
           hdiag = hup;
           int h = 0;
 #pragma unroll
-          for (int r8 = 0; r8 < R; r8 += 8) {
-            const uint32_t pv[4] = {P[r8 >> 3].x, P[r8 >> 3].y, P[r8 >> 3].z, P[r8 >> 3].w};
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int r = r8 + q;
-              const int sm = (q & 1) ? ((int32_t)pv[q >> 1] >> 16)
-                                     : (int32_t)(int16_t)(pv[q >> 1] & 0xffffu);
-              h = max(max(hd + sm, Es[r]), f);          // Eq. 1 (E, F clamped >= 0)
-              vmax = max(vmax, h);
-              const int t = subu(h, a.goe);
-              Es[r] = max(subu(Es[r], a.ge), t);        // Eq. 2
-              f = max(subu(f, a.ge), t);                // Eq. 3
-              hd = Hs[r];
-              Hs[r] = h;
-            }
+          for (int r = 0; r < R; ++r) {
+            const int xn = r + 1 < R ? Hs[r] + sm(r + 1) : 0;
+            h = max(max(x, Es[r]), f);                  // Eq. 1 (E, F clamped >= 0)
+            vmax = max(vmax, h);
+            const int t = subu(h, a.goe);
+            Es[r] = max(subu(Es[r], a.ge), t);          // Eq. 2
+            f = max(subu(f, a.ge), t);                  // Eq. 3
+            Hs[r] = h;
+            x = xn;
           }
           hbot = h;
           fbot = f;
           if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
+        };
+        for (int i = 0; i < 64; i += 2) {
+          step(i, PA, PB);
+          step(i + 1, PB, PA);
         }
         if (ext_bot) {
           // columns 0 .. 64k of the bottom row are written (all of them after the last

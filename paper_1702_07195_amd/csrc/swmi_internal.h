@@ -49,10 +49,10 @@ struct PairItem {
 // Per-query data used by both kernels.
 struct QueryDesc {
   int64_t qp16;      // element offset of this query's strip profile in the int16 arena
-  int64_t qp32;      // element offset of this query's [32][mpad32] profile in the arena
+  int64_t qp8;       // byte offset of this query's [32][mrows] int8 profile in the arena
   int32_t m;         // query length
   int32_t nstrips;   // inter-task strips (2*T rows each)
-  int32_t mpad32;    // rows of the intra-task profile (multiple of 64 * R)
+  int32_t mrows;     // rows of the intra-task profile (multiple of 64 * R)
   int32_t nbands;    // intra-task bands of 64 * R rows
   int64_t out;       // element offset of this query's scores in the output array
 };
@@ -98,7 +98,7 @@ struct IntraArgs {
   int32_t *next_narrow;      // work counter of the narrow items
   int32_t n_wide;            // items [0, n_wide) take a whole workgroup each
   const QueryDesc *queries;
-  const int16_t *qp32;
+  const int8_t *qp8;
   int32_t goe, ge;
   int32_t *scores;
   int2 *bnd;                 // band boundary scratch, one slot per persistent workgroup
@@ -120,7 +120,7 @@ struct ProfileArgs {
   int32_t alphabet;
   int32_t T;                 // inter-task half-strip rows
   int16_t *qp16;
-  int16_t *qp32;
+  int8_t *qp8;
   Counters *ctr;
   int32_t *zero;             // an int32 array cleared with the counters (segment progress)
   int64_t nzero;

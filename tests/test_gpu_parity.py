@@ -333,21 +333,24 @@ def test_search_of_fasta_database(tmp_path):
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
 
 
-@pytest.mark.parametrize("m", [9000, 17000])
-def test_split_pairs_across_workgroups(m):
+@pytest.mark.parametrize("m,cap", [(9000, 0), (17000, 0), (17000, 2), (17000, 1)])
+def test_split_pairs_across_workgroups(m, cap):
     # Queries with more query bands than a workgroup has waves: wide pairs are split
     # into segments on different workgroups that hand the boundary row over through
-    # global memory; every sequence is routed to the intra-task kernel.
+    # global memory (cap: most segments per pair, 0 = automatic, 1 = none); every
+    # sequence is routed to the intra-task kernel.
     rng = np.random.Generator(np.random.PCG64(70 + m))
     lengths = np.concatenate([rng.integers(1200, 3000, 6), rng.integers(1, 900, 40)])
     db = synth.db_from_lengths(rng, lengths)
     q = synth.residues(rng, m)
-    old = swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN)
+    old = (swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN), swmi.get_knob(swmi.SW_KNOB_MAX_SEGMENTS))
     swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+    swmi.set_knob(swmi.SW_KNOB_MAX_SEGMENTS, cap)
     try:
-        _say(f"split pairs m={m}")
+        _say(f"split pairs m={m} cap={cap}")
         with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
             got = h.search(q, synth.BLOSUM62, 10, 2)
     finally:
-        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
+        swmi.set_knob(swmi.SW_KNOB_MAX_SEGMENTS, old[1])
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
