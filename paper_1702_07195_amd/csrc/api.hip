@@ -350,9 +350,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   // columns; cut into segments of at most kIntraWaves consecutive bands on workgroups of
   // their own, the bands form one pipeline (nc + kIntraLag * (nb - 1) chunks), and with at
   // most 4 bands per segment each band's wave has a SIMD to itself.  A pair is split as
-  // little as keeps its estimated time within the estimated time of the whole intra-task
-  // search; segments of a pair are consecutive in the list, so segment j is always
-  // claimed after segment j - 1 (the only one it waits for).
+  // little as keeps its estimated time within half the estimated time of the whole
+  // intra-task search (a pair may be claimed only after other work has run); 4-band
+  // segments, which leave half a compute unit idle, only when even the full pipeline
+  // would outlast the whole search.  Segments of a pair are consecutive in the list, so
+  // segment j is always claimed after segment j - 1 (the only one it waits for).
   //   (one step of a wave: about 0.5 us with two waves per SIMD, 0.25 us alone; the
   //   kernel sustains about 2.5e12 cells/s over the whole chip: MI355X measurements)
   double intra_cells = 0;
@@ -370,7 +372,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     const double piped = (double)(nc + (int64_t)kIntraLag * lastb);
     const int32_t s8 = (nb + kIntraWaves - 1) / kIntraWaves, s4 = (nb + 3) / 4;
     int32_t S = 1;
-    if (whole * 64 * 0.5e-6 > t_search) S = piped * 64 * 0.5e-6 <= t_search ? s8 : s4;
+    if (whole * 64 * 0.5e-6 > 0.5 * t_search) S = piped * 64 * 0.5e-6 <= t_search ? s8 : s4;
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
     S = std::max<int32_t>(1, std::min(S, nb));
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;

@@ -389,6 +389,110 @@ __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
   return __builtin_amdgcn_update_dpp(lane0_value, src, 0x138, 0xf, 0xf, false);
 }
 
+// What one lane carries while its wave sweeps a band: its R rows of H and E, the bottom
+// row's H and F (passed one lane down after every step), the H that becomes the next
+// step's diagonal for its first row, the band-top values and residues of the current
+// 64-column chunk (lane l holds column 64k + l), and the profile rows of the next
+// kIntraBuf steps, already requested (cfar is the residue code of the last of them).
+template <int R>
+struct BandLane {
+  int32_t H[R], E[R];
+  int32_t hbot, fbot, hdiag, cfar;
+  int2 tq;
+  int rq;
+  uint4 P[kIntraBuf][R / 16];
+};
+
+// Profile rows (int8) of one lane: `prof` points at its R rows for code 0; code c's rows
+// are c * pstride bytes further.
+template <int R>
+__device__ __forceinline__ void load_rows(uint4 (&dst)[R / 16], const uint8_t *prof,
+                                          uint32_t pstride, int code) {
+#pragma unroll
+  for (int r16 = 0; r16 < R; r16 += 16)
+    dst[r16 >> 4] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code * pstride + r16);
+}
+
+// Start a band: zero state, load the first chunk's band-top values and residues, and
+// request the profile rows of steps 0 .. kIntraBuf - 2.  The code lane l needs at step s
+// is that of column s - l: its left neighbour's code of step s - 1 (lane 0 takes column
+// s's residue), so codes run ahead as a chain of wave shifts.
+template <int R>
+__device__ __forceinline__ void band_start(BandLane<R> &L, int lane, int n, const int2 *top,
+                                           bool has_top, const uint8_t *resbase, int cs,
+                                           const uint8_t *prof, uint32_t pstride) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) { L.H[r] = 0; L.E[r] = 0; }
+  L.hbot = 0; L.fbot = 0; L.hdiag = 0; L.cfar = kPadCode;
+  L.tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
+  L.rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
+#pragma unroll
+  for (int t = 0; t + 1 < kIntraBuf; ++t) {
+    L.cfar = wave_shr1(L.cfar, __builtin_amdgcn_readlane(L.rq, t));
+    load_rows<R>(L.P[t], prof, pstride, L.cfar);
+  }
+}
+
+// Chunk k (steps 64k .. 64k + 63) of a band sweep.  Raises vmax to the largest H
+// computed.  Step s computes with the rows in buffer s % kIntraBuf and requests those of
+// step s + kIntraBuf - 1 into the buffer step s - 1 used, so each request has
+// kIntraBuf - 1 steps to arrive; steps go in groups of kIntraBuf, so no buffer is ever
+// copied.  Each row's diagonal sum H(i-1, j-1) + SM is formed before the row above is
+// overwritten, which lets H stay in place from step to step.
+template <int R>
+__device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const IntraArgs &a,
+                                           int lane, int k, int n, const int2 *top,
+                                           bool has_top, int2 *bot, bool has_bot,
+                                           const uint8_t *resbase, int cs,
+                                           const uint8_t *prof, uint32_t pstride) {
+  constexpr int D = kIntraBuf - 1;  // prefetch distance in steps
+  static_assert(64 % kIntraBuf == 0, "a chunk must hold whole groups of steps");
+  const int col_next = 64 * (k + 1) + lane;
+  const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
+  const int rq_next = col_next < n
+      ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
+
+  auto step = [&](const int i, const uint4 (&P)[R / 16], uint4 (&Pfar)[R / 16]) {
+    const int s = 64 * k + i;
+    // request the rows of step s + D (its column residue is in this chunk or the next)
+    const int cin = i + D < 64 ? __builtin_amdgcn_readlane(L.rq, i + D)
+                               : __builtin_amdgcn_readlane(rq_next, i + D - 64);
+    L.cfar = wave_shr1(L.cfar, cin);
+    load_rows<R>(Pfar, prof, pstride, L.cfar);
+    const int hup = wave_shr1(L.hbot, __builtin_amdgcn_readlane(L.tq.x, i));
+    int f = wave_shr1(L.fbot, __builtin_amdgcn_readlane(L.tq.y, i));
+    auto sm = [&](int r) {  // row r's score, sign-extended from its byte
+      const uint32_t v = r % 16 < 8 ? (r % 16 < 4 ? P[r / 16].x : P[r / 16].y)
+                                    : (r % 16 < 12 ? P[r / 16].z : P[r / 16].w);
+      return (int32_t)(int8_t)(v >> (8 * (r & 3)));
+    };
+    int x = L.hdiag + sm(0);
+    L.hdiag = hup;
+    int h = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int xn = r + 1 < R ? L.H[r] + sm(r + 1) : 0;
+      h = max(max(x, L.E[r]), f);                   // Eq. 1 (E, F clamped >= 0)
+      vmax = max(vmax, h);
+      const int t = subu(h, a.goe);
+      L.E[r] = max(subu(L.E[r], a.ge), t);          // Eq. 2
+      f = max(subu(f, a.ge), t);                    // Eq. 3
+      L.H[r] = h;
+      x = xn;
+    }
+    L.hbot = h;
+    L.fbot = f;
+    if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
+  };
+  for (int i = 0; i < 64; i += kIntraBuf) {
+#pragma unroll
+    for (int u = 0; u < kIntraBuf; ++u)
+      step(i + u, L.P[u], L.P[(u + kIntraBuf - 1) % kIntraBuf]);
+  }
+  L.tq = tq_next;
+  L.rq = rq_next;
+}
+
 // Returns this lane's running maximum of H over the cells it computed.  `ring` holds
 // NW + 1 band-boundary buffers of a.bnd_stride (H, F) pairs.
 template <int R, int NW>
@@ -406,14 +510,10 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
   const int rounds = (lastb / NW) * nce + kIntraLag * (lastb % NW) + nc;
   const uint8_t *resbase = a.packed + pi.base;
   const int cs = pi.cstride;
+  const uint32_t pstride = (uint32_t)qd.mrows;
 
   int bl = w;  // band of this segment that this wave works on
-  int32_t Hs[R], Es[R];
-  int32_t hbot = 0, fbot = 0, hdiag = 0, code = kPadCode;
-  int2 tq = make_int2(0, 0);  // band-top (H, F) for columns 64k + lane
-  int rq = kPadCode;          // residue of column 64k + lane
-#pragma unroll
-  for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
+  BandLane<R> L;
 
   for (int rd = 0; rd < rounds; ++rd) {
     if (bl < nb) {
@@ -449,73 +549,12 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
           }
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        if (k == 0) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) { Hs[r] = 0; Es[r] = 0; }
-          hbot = 0; fbot = 0; hdiag = 0; code = kPadCode;
-          tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
-          rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
-        }
-        const int col_next = 64 * (k + 1) + lane;
-        const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
-        const int rq_next = col_next < n
-            ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
-        // this lane's R profile rows of band b; code c's rows start c * pstride bytes on
+        // this lane's R profile rows of band b
         const uint8_t *prof = reinterpret_cast<const uint8_t *>(
             a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
-        const uint32_t pstride = (uint32_t)qd.mrows;
-
-        // The code a lane needs at step s + 1 is its left neighbour's code at step s, so
-        // the profile rows of the next step are loaded one step ahead, into the other of
-        // two buffers (steps go in pairs, so no buffer is ever copied).  Each row's
-        // diagonal sum H(i-1, j-1) + SM is formed before the row above is overwritten,
-        // which lets H stay in place from step to step.
-        int code_next = wave_shr1(code, __builtin_amdgcn_readlane(rq, 0));
-        uint4 PA[R / 16], PB[R / 16];
-#pragma unroll
-        for (int r16 = 0; r16 < R; r16 += 16)
-          PA[r16 >> 4] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code_next * pstride +
-                                                           r16);
-        auto step = [&](const int i, const uint4 (&P)[R / 16], uint4 (&Pnext)[R / 16]) {
-          const int s = 64 * k + i;
-          code = code_next;
-          // prefetch for step s + 1 (the first column of the next chunk comes from rq_next)
-          const int cin = i < 63 ? __builtin_amdgcn_readlane(rq, i + 1)
-                                 : __builtin_amdgcn_readfirstlane(rq_next);
-          code_next = wave_shr1(code, cin);
-#pragma unroll
-          for (int r16 = 0; r16 < R; r16 += 16)
-            Pnext[r16 >> 4] = *reinterpret_cast<const uint4 *>(
-                prof + (uint32_t)code_next * pstride + r16);
-          const int hup = wave_shr1(hbot, __builtin_amdgcn_readlane(tq.x, i));
-          int f = wave_shr1(fbot, __builtin_amdgcn_readlane(tq.y, i));
-          auto sm = [&](int r) {  // row r's score, sign-extended from its byte
-            const uint32_t v = r % 16 < 8 ? (r % 16 < 4 ? P[r / 16].x : P[r / 16].y)
-                                          : (r % 16 < 12 ? P[r / 16].z : P[r / 16].w);
-            return (int32_t)(int8_t)(v >> (8 * (r & 3)));
-          };
-          int x = hdiag + sm(0);
-          hdiag = hup;
-          int h = 0;
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int xn = r + 1 < R ? Hs[r] + sm(r + 1) : 0;
-            h = max(max(x, Es[r]), f);                  // Eq. 1 (E, F clamped >= 0)
-            vmax = max(vmax, h);
-            const int t = subu(h, a.goe);
-            Es[r] = max(subu(Es[r], a.ge), t);          // Eq. 2
-            f = max(subu(f, a.ge), t);                  // Eq. 3
-            Hs[r] = h;
-            x = xn;
-          }
-          hbot = h;
-          fbot = f;
-          if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
-        };
-        for (int i = 0; i < 64; i += 2) {
-          step(i, PA, PB);
-          step(i + 1, PB, PA);
-        }
+        if (k == 0) band_start(L, lane, n, top, has_top, resbase, cs, prof, pstride);
+        band_chunk(L, vmax, a, lane, k, n, top, has_top, bot, has_bot, resbase, cs, prof,
+                   pstride);
         if (ext_bot) {
           // columns 0 .. 64k of the bottom row are written (all of them after the last
           // chunk); every lane stores the same count with release order
@@ -523,8 +562,6 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
           __hip_atomic_store(a.xprog + pi.prog_out, done, __ATOMIC_RELEASE,
                              __HIP_MEMORY_SCOPE_AGENT);
         }
-        tq = tq_next;
-        rq = rq_next;
         if (k == nc - 1) bl += NW;
       }
     }
@@ -591,12 +628,12 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
     }
   }
 
+  int2 *ring = slot + (int64_t)w * 2 * a.bnd_stride;  // two band buffers per wave
   // Narrow phase.  The waves run independently, so the claim cannot go through LDS and a
   // barrier.  It must not sit in a lane-0-only branch either: the compiler may then split
   // the wave across the loop back-edge and let lanes 1..63 re-read a stale item forever.
   // Every lane therefore executes the atomic (adding 1 from lane 0, 0 elsewhere; lane 0
   // gets the old value), and every lane stores the same reduced score.
-  int2 *ring = slot + (int64_t)w * 2 * a.bnd_stride;  // two band buffers per wave
   for (;;) {
     const int claimed = atomicAdd(a.next_narrow, lane == 0 ? 1 : 0);
     const int it = __builtin_amdgcn_readfirstlane(claimed) + n_wide;

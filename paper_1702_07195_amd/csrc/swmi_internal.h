@@ -166,6 +166,7 @@ hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStr
 bool inter16_supported(int T);
 int inter16_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
+constexpr int kIntraBuf = 4;     // profile-row buffers per lane (prefetch distance + 1)
 constexpr int kIntraWaves = 8;
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
 constexpr int kSpinLimit = 1 << 24;  // polls before a wait between segments gives up
