@@ -76,7 +76,8 @@ def cpu_baseline(db, queries, sm, go, ge, gpu_scores, budget_cells: float):
     per_seq = float(sum(len(q) for q in queries)) * float(max(lengths.mean(), 1.0))
     n = int(max(16, min(len(order), budget_cells / max(per_seq, 1.0))))
     idx = order[np.linspace(0, len(order) - 1, n).astype(np.int64)]
-    threads = os.cpu_count() or 1
+    # the host share of one GPU is 16 cores, whatever the machine reports
+    threads = max(1, min(os.cpu_count() or 1, 16))
     cells = 0
     t0 = time.perf_counter()
     exact = True
@@ -357,6 +358,31 @@ def bench_served(args):
     return result
 
 
+def calibrate():
+    """Sustained cell rates of the three integer tiers, without memory traffic."""
+    import ctypes
+
+    import torch  # noqa: F401  (one HIP runtime per process: torch's)
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1702_07195_amd", "libswmi_calib.so"))
+    f = lib.swcal_cellmix
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    f.restype = ctypes.c_int
+    out = {}
+    for kind, name in ((0, "int16x2 packed"), (1, "int32"), (2, "int8x4 SWAR")):
+        rows = {}
+        for waves in (4, 8, 12, 16):
+            ms, cells = ctypes.c_double(), ctypes.c_double()
+            rc = f(kind, waves, 4096 if kind != 2 else 1024, ctypes.byref(ms), ctypes.byref(cells))
+            if rc != 0:
+                raise RuntimeError(f"swcal_cellmix({kind}, {waves}) returned {rc}")
+            rows[str(waves)] = round(cells.value / ms.value / 1e6, 1)
+        out[name] = {"gcups_equiv_by_waves_per_cu": rows, "best": max(rows.values())}
+    return {"calibration": "register-only DP cell mix, 16 rows x 2 chains per lane",
+            "unit": "GCUPS-equivalent", "tiers": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,11 +405,17 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates the "
                          "HBM byte counters of a profiler run)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="time register-only copies of the DP cell at int16 x 2, int32 and "
+                         "SWAR int8 x 4 (libswmi_calib.so) and exit")
     args = ap.parse_args()
+    if args.calibrate:
+        print(json.dumps(calibrate()), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the database would be sharded across GPUs as described in DESIGN.md",
-              file=sys.stderr)
+              "across GPUs the database would be sharded by sequence groups, each GPU "
+              "searching its shard and the scores gathered", file=sys.stderr)
         sys.exit(2)
 
     from paper_1702_07195_amd import synth

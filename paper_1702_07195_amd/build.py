@@ -1,8 +1,9 @@
-"""Build step for the HIP library ``libswmi.so`` (gfx950), run by ``__graft_entry__.build``.
+"""Build step for the HIP libraries (gfx950), run by ``__graft_entry__.build``.
 
-Compiles every ``csrc/*.hip`` source with hipcc into one shared library that exports the
-C ABI of ``include/swmi.h``.  The library is written next to this file so that it
-travels with the source tree.
+Compiles the ``csrc/*.hip`` sources with hipcc into ``libswmi.so``, which exports the C
+ABI of ``include/swmi.h``, and ``csrc/calib.hip`` alone into ``libswmi_calib.so`` (the
+VALU calibration of ``include/swmi_calib.h``).  The libraries are written next to this
+file so that they travel with the source tree.
 """
 from __future__ import annotations
 
@@ -13,6 +14,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libswmi.so")
+CALIB_LIB = os.path.join(HERE, "libswmi_calib.so")
+CALIB_SRC = os.path.join(HERE, "csrc", "calib.hip")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -27,14 +30,23 @@ FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
+    return sorted(s for s in glob.glob(os.path.join(HERE, "csrc", "*.hip")) if s != CALIB_SRC)
+
+
+def _link(objs, lib, verbose):
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, capture_output=not verbose)
+    os.replace(tmp, lib)
 
 
 def build(verbose: bool = False, extra=None) -> str:
     objs = []
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    for src in sources():
+    for src in sources() + [CALIB_SRC]:
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         cmd = [HIPCC, *FLAGS, *(extra or []), "-c", src, "-o", obj]
         if verbose:
@@ -43,12 +55,8 @@ def build(verbose: bool = False, extra=None) -> str:
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
         objs.append(obj)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, capture_output=not verbose)
-    os.replace(tmp, LIB)
+    _link(objs[:-1], LIB, verbose)
+    _link(objs[-1:], CALIB_LIB, verbose)
     return LIB
 
 

@@ -89,3 +89,23 @@ def test_knobs_validate_and_round_trip():
     swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, old)
     with pytest.raises(swmi.SwError):
         swmi.set_knob(99, 1)
+
+
+def test_calibration_library_exports_its_header():
+    import torch  # noqa: F401  (the HIP runtime torch ships is the one loaded first)
+
+    header = os.path.join(ROOT, "include", "swmi_calib.h")
+    text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(swcal_[a-z_]+)\s*\(", text)))
+    assert names == ["swcal_cellmix"]
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_1702_07195_amd", "libswmi_calib.so"))
+    for name in names:
+        assert hasattr(lib, name), name
+    f = lib.swcal_cellmix
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    ms, cells = ctypes.c_double(), ctypes.c_double()
+    # argument checks run before any device call
+    assert f(3, 8, 16, ctypes.byref(ms), ctypes.byref(cells)) == -1
+    assert f(0, 0, 16, ctypes.byref(ms), ctypes.byref(cells)) == -1
+    assert f(0, 8, 16, None, ctypes.byref(cells)) == -1
