@@ -250,7 +250,9 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          bands) are swept by a whole workgroup, shorter ones by one
  *                          wave (0 = automatic: 1152);
  *   SW_KNOB_MAX_SEGMENTS   most workgroups one intra-task pair may be split across
- *                          (0 = automatic, 1 = never split).
+ *                          (0 = automatic, 1 = never split);
+ *   SW_KNOB_INTRA_ROWS     query rows per lane of the intra-task kernel: 4, 8 or 16
+ *                          (bands of 256, 512 or 1024 rows; 0 = chosen per search).
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -260,6 +262,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_ROUTE_LEN      6
 #define SW_KNOB_WIDE_LEN       7
 #define SW_KNOB_MAX_SEGMENTS   8
+#define SW_KNOB_INTRA_ROWS     9
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

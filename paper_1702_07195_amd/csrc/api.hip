@@ -33,6 +33,7 @@ std::atomic<int64_t> g_knob_mem_cap_mb{0};
 std::atomic<int64_t> g_knob_route_len{0};
 std::atomic<int64_t> g_knob_wide_len{0};
 std::atomic<int64_t> g_knob_max_segments{0};
+std::atomic<int64_t> g_knob_intra_rows{0};
 
 struct HipFail {
   hipError_t err;
@@ -224,6 +225,27 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
 // Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
 // by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
 // at three waves per SIMD and was fastest on the full-scale search).
+// Rows per lane of the intra-task kernel for one search.  Its band is 64R query rows,
+// so a short query leaves most lanes of a large band on padding rows, while a lane's
+// per-step overhead (residue and boundary shifts, the profile request) is paid once per
+// R rows: a step issues about 7.5 R + 14 instructions.  Pick the R in {4, 8, 16} that
+// minimises the sum over the queries of bands(R) * (7.5 R + 14).
+int choose_R(const std::vector<int64_t> &lens) {
+  const int64_t forced = g_knob_intra_rows.load();
+  if (forced == 4 || forced == 8 || forced == 16) return (int)forced;
+  int best = kIntraR;
+  double best_cost = 1e300;
+  for (int R : {16, 8, 4}) {
+    double cost = 0;
+    for (int64_t m : lens) cost += (double)((m + 64 * R - 1) / (64 * R)) * (7.5 * R + 14.0);
+    if (cost < best_cost * 0.999) {
+      best_cost = cost;
+      best = R;
+    }
+  }
+  return best;
+}
+
 int choose_T(const std::vector<int64_t> &lens) {
   const int64_t forced = g_knob_strip_rows.load();
   if (forced > 0 && inter16_supported((int)forced)) return (int)forced;
@@ -245,6 +267,8 @@ int choose_T(const std::vector<int64_t> &lens) {
 
 struct Plan {
   int T = 32;
+  int R = kIntraR;               // rows per lane of the long-pair intra-task launch
+  std::vector<int32_t> nbandsR;  // query bands of 64R rows
   int64_t xbnd_elems = 0;  // int2 elements of the boundary rows between pair segments
   int32_t nprog = 0;       // progress counters of those boundaries
   int32_t ngroups_inter = 0;
@@ -273,6 +297,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   std::stable_sort(qorder.begin(), qorder.end(),
                    [&](int32_t x, int32_t y) { return lens[x] > lens[y]; });
   p.T = choose_T(lens);
+  p.R = choose_R(lens);
+  p.nbandsR.resize((size_t)nq);
+  for (int64_t q = 0; q < nq; ++q)
+    p.nbandsR[q] = (int32_t)((lens[q] + 64 * p.R - 1) / (64 * p.R));
   const int band = 64 * kIntraR;
   p.qd.resize((size_t)nq);
   for (int64_t q = 0; q < nq; ++q) {
@@ -320,7 +348,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     it.out = orig;
     it.query = (int32_t)q;
     it.band0 = 0;
-    it.band1 = p.qd[q].nbands;
+    it.band1 = p.nbandsR[q];
     it.xin = it.xout = -1;
     it.prog_in = it.prog_out = -1;
     it.segment = 0;
@@ -328,7 +356,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     const double cost = (double)len * (double)lens[q];
     const int64_t wide_len = g_knob_wide_len.load() > 0 ? g_knob_wide_len.load()
                                                         : (int64_t)64 * 6 * kIntraLag;
-    const bool is_wide = len >= wide_len && p.qd[q].nbands >= 2;
+    const bool is_wide = len >= wide_len && p.nbandsR[q] >= 2;
     (is_wide ? wide : narrow).emplace_back(cost, it);
   };
   for (int64_t q = 0; q < nq; ++q) {
@@ -355,12 +383,16 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   // segments, which leave half a compute unit idle, only when even the full pipeline
   // would outlast the whole search.  Segments of a pair are consecutive in the list, so
   // segment j is always claimed after segment j - 1 (the only one it waits for).
-  //   (one step of a wave: about 0.5 us with two waves per SIMD, 0.25 us alone; the
-  //   kernel sustains about 2.5e12 cells/s over the whole chip: MI355X measurements)
+  //   (one step of a wave with R = 16: about 0.5 us with two waves per SIMD, 0.25 us
+  //   alone; the kernel then sustains about 2.5e12 cells/s over the whole chip: MI355X
+  //   measurements; both scale with the instructions per step, 7.5 R + 14)
   double intra_cells = 0;
   for (auto &x : wide) intra_cells += x.first;
   for (auto &x : narrow) intra_cells += x.first;
-  const double t_search = intra_cells / 2.5e12 * (256.0 / std::max(1, db->num_cu));
+  const double step_scale = (7.5 * p.R + 14.0) / (7.5 * 16 + 14.0);
+  const double t_search = intra_cells / (2.5e12 * (16.0 / p.R) / step_scale) *
+                          (256.0 / std::max(1, db->num_cu));
+  const double t_step = 0.5e-6 * step_scale;
   const int64_t cap = g_knob_max_segments.load();
   for (auto &x : wide) {
     const PairItem &it = x.second;
@@ -372,7 +404,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     const double piped = (double)(nc + (int64_t)kIntraLag * lastb);
     const int32_t s8 = (nb + kIntraWaves - 1) / kIntraWaves, s4 = (nb + 3) / 4;
     int32_t S = 1;
-    if (whole * 64 * 0.5e-6 > 0.5 * t_search) S = piped * 64 * 0.5e-6 <= t_search ? s8 : s4;
+    if (whole * 64 * t_step > 0.5 * t_search) S = piped * 64 * t_step <= t_search ? s8 : s4;
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
     S = std::max<int32_t>(1, std::min(S, nb));
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
@@ -510,7 +542,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.error = &ctr->error;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
-    hip_check(launch_intra32(ia, kIntraR, kIntraWaves, p.grid_long, w->aux));
+    hip_check(launch_intra32(ia, p.R, kIntraWaves, p.grid_long, w->aux));
     if (timed) {
       hip_check(hipEventRecord(w->t1[1], w->aux));
       w->timed[1] = true;
@@ -606,6 +638,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
     case SW_KNOB_ROUTE_LEN: if (value < 0) return SW_EINVAL; g_knob_route_len = value; return SW_OK;
     case SW_KNOB_WIDE_LEN: if (value < 0) return SW_EINVAL; g_knob_wide_len = value; return SW_OK;
     case SW_KNOB_MAX_SEGMENTS: if (value < 0) return SW_EINVAL; g_knob_max_segments = value; return SW_OK;
+    case SW_KNOB_INTRA_ROWS:
+      if (value != 0 && value != 4 && value != 8 && value != 16) return SW_EINVAL;
+      g_knob_intra_rows = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -620,6 +656,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_ROUTE_LEN: return g_knob_route_len.load();
     case SW_KNOB_WIDE_LEN: return g_knob_wide_len.load();
     case SW_KNOB_MAX_SEGMENTS: return g_knob_max_segments.load();
+    case SW_KNOB_INTRA_ROWS: return g_knob_intra_rows.load();
     default: return SW_EINVAL;
   }
 }

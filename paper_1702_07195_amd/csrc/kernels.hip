@@ -394,23 +394,39 @@ __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
 // step's diagonal for its first row, the band-top values and residues of the current
 // 64-column chunk (lane l holds column 64k + l), and the profile rows of the next
 // kIntraBuf steps, already requested (cfar is the residue code of the last of them).
+// One lane's R int8 profile rows for one code (R = 4, 8 or 16: one 4-, 8- or 16-byte
+// load).
+template <int R> struct RowBuf;
+template <> struct RowBuf<4> {
+  uint32_t v;
+  __device__ uint32_t word(int) const { return v; }
+};
+template <> struct RowBuf<8> {
+  uint2 v;
+  __device__ uint32_t word(int i) const { return i == 0 ? v.x : v.y; }
+};
+template <> struct RowBuf<16> {
+  uint4 v;
+  __device__ uint32_t word(int i) const {
+    return i < 2 ? (i == 0 ? v.x : v.y) : (i == 2 ? v.z : v.w);
+  }
+};
+
 template <int R>
 struct BandLane {
   int32_t H[R], E[R];
   int32_t hbot, fbot, hdiag, cfar;
   int2 tq;
   int rq;
-  uint4 P[kIntraBuf][R / 16];
+  RowBuf<R> P[kIntraBuf];
 };
 
 // Profile rows (int8) of one lane: `prof` points at its R rows for code 0; code c's rows
 // are c * pstride bytes further.
 template <int R>
-__device__ __forceinline__ void load_rows(uint4 (&dst)[R / 16], const uint8_t *prof,
-                                          uint32_t pstride, int code) {
-#pragma unroll
-  for (int r16 = 0; r16 < R; r16 += 16)
-    dst[r16 >> 4] = *reinterpret_cast<const uint4 *>(prof + (uint32_t)code * pstride + r16);
+__device__ __forceinline__ void load_rows(RowBuf<R> &dst, const uint8_t *prof, uint32_t pstride,
+                                          int code) {
+  dst.v = *reinterpret_cast<const decltype(dst.v) *>(prof + (uint32_t)code * pstride);
 }
 
 // Start a band: zero state, load the first chunk's band-top values and residues, and
@@ -429,7 +445,7 @@ __device__ __forceinline__ void band_start(BandLane<R> &L, int lane, int n, cons
 #pragma unroll
   for (int t = 0; t + 1 < kIntraBuf; ++t) {
     L.cfar = wave_shr1(L.cfar, __builtin_amdgcn_readlane(L.rq, t));
-    load_rows<R>(L.P[t], prof, pstride, L.cfar);
+    load_rows(L.P[t], prof, pstride, L.cfar);
   }
 }
 
@@ -452,19 +468,17 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
   const int rq_next = col_next < n
       ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
 
-  auto step = [&](const int i, const uint4 (&P)[R / 16], uint4 (&Pfar)[R / 16]) {
+  auto step = [&](const int i, const RowBuf<R> &P, RowBuf<R> &Pfar) {
     const int s = 64 * k + i;
     // request the rows of step s + D (its column residue is in this chunk or the next)
     const int cin = i + D < 64 ? __builtin_amdgcn_readlane(L.rq, i + D)
                                : __builtin_amdgcn_readlane(rq_next, i + D - 64);
     L.cfar = wave_shr1(L.cfar, cin);
-    load_rows<R>(Pfar, prof, pstride, L.cfar);
+    load_rows(Pfar, prof, pstride, L.cfar);
     const int hup = wave_shr1(L.hbot, __builtin_amdgcn_readlane(L.tq.x, i));
     int f = wave_shr1(L.fbot, __builtin_amdgcn_readlane(L.tq.y, i));
     auto sm = [&](int r) {  // row r's score, sign-extended from its byte
-      const uint32_t v = r % 16 < 8 ? (r % 16 < 4 ? P[r / 16].x : P[r / 16].y)
-                                    : (r % 16 < 12 ? P[r / 16].z : P[r / 16].w);
-      return (int32_t)(int8_t)(v >> (8 * (r & 3)));
+      return (int32_t)(int8_t)(P.word(r >> 2) >> (8 * (r & 3)));
     };
     int x = L.hdiag + sm(0);
     L.hdiag = hup;
@@ -648,9 +662,21 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
 
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
   if (grid == 0) return hipSuccess;
-  if (R != kIntraR || waves != kIntraWaves) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_intra32<kIntraR, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0,
-                     s, a);
+  if (waves != kIntraWaves) return hipErrorInvalidValue;
+  switch (R) {
+    case 4:
+      hipLaunchKernelGGL((k_intra32<4, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_intra32<8, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_intra32<16, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s,
+                         a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

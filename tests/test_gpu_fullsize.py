@@ -99,3 +99,24 @@ def test_batched_config_sampled():
     for k in (0, 17, 63):
         want = oracle.search(qs[k], db.residues, db.offsets, sm, 11, 1, index=idx)
         assert np.array_equal(got[k][idx], want), k
+
+
+def test_long_mix_longest_pairs():
+    # The longest sequence of the mix against both queries: these pairs are split across
+    # workgroups (4-band segments for the 5478-residue query, 8-band segments for the
+    # 35000-residue one), so this checks the split path at the full workload size.
+    from concurrent.futures import ThreadPoolExecutor
+
+    w = synth.LONG_MIX
+    db = w.make_db()
+    queries = w.make_queries()
+    longest = int(np.argmax(db.lengths))
+    _say(f"long-mix longest pair: n={int(db.lengths[longest])}")
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        got = [int(h.search(q, w.matrix_values, w.gap_open, w.gap_extend)[longest])
+               for q in queries]
+    # one oracle call per query, in parallel (each scores one pair on one host thread)
+    with ThreadPoolExecutor(max_workers=len(queries)) as ex:
+        want = list(ex.map(lambda q: int(oracle.score(q, db.seq(longest), w.matrix_values,
+                                                      w.gap_open, w.gap_extend)), queries))
+    assert got == want

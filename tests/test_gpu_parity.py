@@ -354,3 +354,31 @@ def test_split_pairs_across_workgroups(m, cap):
         swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
         swmi.set_knob(swmi.SW_KNOB_MAX_SEGMENTS, old[1])
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
+
+
+@pytest.fixture(scope="module")
+def mixed_db():
+    # lengths from empty to 3000 (narrow pairs below 1152, wide pairs above)
+    rng = np.random.Generator(np.random.PCG64(4242))
+    lengths = np.concatenate([rng.integers(0, 1152, 90), rng.integers(1152, 3000, 12)])
+    return synth.db_from_lengths(rng, lengths)
+
+
+@pytest.mark.parametrize("R", [4, 8, 16])
+@pytest.mark.parametrize("m", [70, 300, 1500, 3000])
+def test_intra_rows_per_lane(mixed_db, R, m):
+    # The intra-task kernel with bands of 64R rows (R query rows per lane), every
+    # sequence routed to it; with small databases the longest pairs are also split.
+    rng = np.random.Generator(np.random.PCG64(900 + m))
+    q = synth.residues(rng, m)
+    old = (swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN), swmi.get_knob(swmi.SW_KNOB_INTRA_ROWS))
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, R)
+    try:
+        _say(f"intra rows per lane R={R} m={m}")
+        with swmi.sw_db_load(mixed_db.residues, mixed_db.offsets, ALPHA) as h:
+            got = h.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
+        swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, old[1])
+    assert np.array_equal(got, _oracle(q, mixed_db, synth.BLOSUM62, 10, 2))
