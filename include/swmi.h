@@ -163,7 +163,11 @@ void sw_plan_free(sw_plan *plan);
  * (at most `max_batch`, 1..4096, and, if `mem_budget_bytes` > 0, only while the device
  * bytes of all batches in flight stay within the budget) as one batched search, so
  * requests that arrive while others are on the GPU join the next launch and run next to
- * them on the device.  A query that alone exceeds the budget completes with SW_ENOMEM.
+ * them on the device.  A batch stops growing once its inter-task work items (database
+ * groups x queries) fill every wave slot of the device four times over, and no further
+ * batch is launched while the batches in flight do: on a large database each query then
+ * runs alone at full speed, on a small one several share a launch.  A query that alone
+ * exceeds the budget completes with SW_ENOMEM.
  * All searches use `matrix`, `gap_open` and `gap_extend` (validated as for sw_search).
  * The database must outlive the server.
  *

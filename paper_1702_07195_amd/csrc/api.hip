@@ -1071,6 +1071,7 @@ struct ServerSlot {
   hipEvent_t finished = nullptr;
   bool busy = false;
   size_t mem = 0;                       // admitted bytes of the batch in flight
+  int64_t items = 0;                    // inter-task work items of the batch
   std::vector<ServerRequest *> batch;
   DevBuf scores;
   HostBuf host_scores;
@@ -1088,6 +1089,7 @@ struct sw_server {
   int32_t gap_open = 0, gap_extend = 0;
   int32_t max_batch = 1;
   int64_t mem_budget = 0;
+  int64_t fill_items = 0;  // inter-task work items that keep every wave slot busy
   std::vector<ServerSlot> slots;
   std::mutex mu;
   std::condition_variable cv;     // wakes the worker
@@ -1136,21 +1138,28 @@ void server_loop(sw_server *sv) {
     // retire finished batches
     int in_flight = 0;
     size_t mem_in_flight = 0;
+    int64_t items_in_flight = 0;
     for (ServerSlot &sl : sv->slots) {
       if (sl.busy && hipEventQuery(sl.finished) == hipSuccess) server_finish_slot(sv, sl);
       if (sl.busy) {
         ++in_flight;
         mem_in_flight += sl.mem;
+        items_in_flight += sl.items;
       }
     }
     if (sv->stop && sv->queue.empty() && in_flight == 0) break;
-    // admit queued requests into a free slot
+    // Admit queued requests into a free slot, but only while the batches in flight leave
+    // wave slots idle, and stop growing a batch once it alone fills them: on a large
+    // database one query already fills the GPU, and a second batch running beside it
+    // only halves the speed of both; on a small one several queries share a launch.
     ServerSlot *free_slot = nullptr;
     for (ServerSlot &sl : sv->slots)
       if (!sl.busy) { free_slot = &sl; break; }
-    if (free_slot && !sv->queue.empty()) {
+    const int64_t per_query = std::max<int64_t>(1, sv->db->ngroups);
+    if (free_slot && !sv->queue.empty() && items_in_flight < sv->fill_items) {
       std::vector<ServerRequest *> batch;
-      while (!sv->queue.empty() && (int)batch.size() < sv->max_batch) {
+      while (!sv->queue.empty() && (int)batch.size() < sv->max_batch &&
+             (int64_t)batch.size() * per_query < sv->fill_items) {
         batch.push_back(sv->queue.front());
         if (sv->mem_budget > 0 && (int64_t)(mem_in_flight + batch_bytes(sv->db, batch)) > sv->mem_budget) {
           batch.pop_back();
@@ -1208,6 +1217,7 @@ void server_loop(sw_server *sv) {
           sl.batch = std::move(batch);
           sl.busy = true;
           sl.mem = batch_bytes(sv->db, sl.batch);
+          sl.items = (int64_t)sl.batch.size() * per_query;
           ++sv->launches;
           sv->max_in_flight = std::max<int64_t>(sv->max_in_flight, in_flight + 1);
         }
@@ -1239,6 +1249,10 @@ SW_API int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open,
   sv->gap_open = gap_open;
   sv->gap_extend = gap_extend;
   sv->max_batch = max_batch;
+  {
+    const int per_cu = std::max(1, inter16_max_blocks_per_cu(24));
+    sv->fill_items = 4LL * per_cu * std::max(1, db->num_cu);
+  }
   sv->mem_budget = mem_budget_bytes;
   sv->slots.resize((size_t)slots);
   try {

@@ -382,3 +382,26 @@ def test_intra_rows_per_lane(mixed_db, R, m):
         swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
         swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, old[1])
     assert np.array_equal(got, _oracle(q, mixed_db, synth.BLOSUM62, 10, 2))
+
+
+def test_server_runs_one_query_per_launch_when_it_fills_the_device():
+    # 1,000,000 sequences are 15,625 groups of 64: one query's work items fill every
+    # wave slot (256 CUs x 12 waves) more than four times over, so the server neither
+    # batches nor overlaps launches.
+    rng = np.random.Generator(np.random.PCG64(61))
+    db = synth.db_from_lengths(rng, synth.lognormal_lengths(rng, 1_000_000, 30, 0.5, 5, 100))
+    qs = [synth.residues(rng, m) for m in (40, 75, 60, 90, 55, 70)]
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        alone = [h.search(q, synth.BLOSUM62, 10, 2) for q in qs]
+        _say("server on a device-filling database")
+        with swmi.SwServer(h, synth.BLOSUM62, 10, 2, slots=2, max_batch=4) as sv:
+            tickets = [sv.submit(q) for q in qs]
+            results = [sv.wait(t) for t in tickets]
+            st = sv.stats()
+    assert st["launches"] == len(qs)
+    assert st["max_in_flight"] == 1
+    for k, (scores, _, _) in enumerate(results):
+        assert np.array_equal(scores, alone[k]), k
+    idx = np.linspace(0, db.n_seqs - 1, 40).astype(np.int64)
+    want = oracle.search(qs[0], db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
+    assert np.array_equal(alone[0][idx], want)
