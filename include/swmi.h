@@ -256,7 +256,11 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *   SW_KNOB_MAX_SEGMENTS   most workgroups one intra-task pair may be split across
  *                          (0 = automatic, 1 = never split);
  *   SW_KNOB_INTRA_ROWS     query rows per lane of the intra-task kernel: 4, 8 or 16
- *                          (bands of 256, 512 or 1024 rows; 0 = chosen per search).
+ *                          (bands of 256, 512 or 1024 rows; 0 = chosen per search);
+ *   SW_KNOB_INTRA_PAIRS    1 (default): when a search has many narrow intra-task pairs,
+ *                          short ones run two per wave in packed int16 (saturated halves
+ *                          recomputed in int32); 0: every intra-task pair runs alone in
+ *                          int32; 2: every unsplit pair is paired (for tests).
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -267,6 +271,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_WIDE_LEN       7
 #define SW_KNOB_MAX_SEGMENTS   8
 #define SW_KNOB_INTRA_ROWS     9
+#define SW_KNOB_INTRA_PAIRS    10
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

@@ -34,6 +34,7 @@ std::atomic<int64_t> g_knob_route_len{0};
 std::atomic<int64_t> g_knob_wide_len{0};
 std::atomic<int64_t> g_knob_max_segments{0};
 std::atomic<int64_t> g_knob_intra_rows{0};
+std::atomic<int64_t> g_knob_intra_pairs{1};
 
 struct HipFail {
   hipError_t err;
@@ -73,13 +74,13 @@ struct Workspace {
   hipEvent_t t0[3] = {}, t1[3] = {};  // kernel timing: inter-task, long intra, recompute
   bool timed[3] = {false, false, false};
   bool busy = false;
-  DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp8, ctr, flagged, longitems, bnd16,
-      bnd32, xbnd, xprog, scores;
+  DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp8, ctr, flagged, longitems, second,
+      bnd16, bnd32, xbnd, xprog, scores;
   HostBuf staging;
   size_t total_bytes() const {
     return queries.bytes + qoff.bytes + qdesc.bytes + qorder.bytes + matrix.bytes + qp16.bytes + qp8.bytes +
-           ctr.bytes + flagged.bytes + longitems.bytes + bnd16.bytes + bnd32.bytes + xbnd.bytes +
-           xprog.bytes + scores.bytes;
+           ctr.bytes + flagged.bytes + longitems.bytes + second.bytes + bnd16.bytes + bnd32.bytes +
+           xbnd.bytes + xprog.bytes + scores.bytes;
   }
 };
 
@@ -146,8 +147,8 @@ void destroy_workspace(Workspace *w) {
   if (w->own) (void)hipStreamSynchronize(w->own);
   if (w->aux) (void)hipStreamSynchronize(w->aux);
   for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->qorder, &w->matrix, &w->qp16, &w->qp8, &w->ctr,
-                    &w->flagged, &w->longitems, &w->bnd16, &w->bnd32, &w->xbnd, &w->xprog,
-                    &w->scores})
+                    &w->flagged, &w->longitems, &w->second, &w->bnd16, &w->bnd32, &w->xbnd,
+                    &w->xprog, &w->scores})
     b->release();
   w->staging.release();
   for (hipEvent_t e : {w->done, w->fork, w->join, w->t0[0], w->t1[0], w->t0[1], w->t1[1],
@@ -166,7 +167,8 @@ Workspace *acquire(sw_db *db) {
       return w;
     }
   }
-  // at most 8 workspaces; beyond that wait for the oldest idle one
+  // up to 8 workspaces are created on demand; beyond that a call waits for an idle one
+  // to finish (a new one is still created if all 8 are held by concurrent calls)
   if (db->pool.size() >= 8) {
     for (Workspace *w : db->pool) {
       if (!w->busy) {
@@ -222,9 +224,6 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
   return SW_OK;
 }
 
-// Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
-// by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
-// at three waves per SIMD and was fastest on the full-scale search).
 // Rows per lane of the intra-task kernel for one search.  Its band is 64R query rows,
 // so a short query leaves most lanes of a large band on padding rows, while a lane's
 // per-step overhead (residue and boundary shifts, the profile request) is paid once per
@@ -246,6 +245,9 @@ int choose_R(const std::vector<int64_t> &lens) {
   return best;
 }
 
+// Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
+// by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
+// at three waves per SIMD and was fastest on the full-scale search).
 int choose_T(const std::vector<int64_t> &lens) {
   const int64_t forced = g_knob_strip_rows.load();
   if (forced > 0 && inter16_supported((int)forced)) return (int)forced;
@@ -278,6 +280,7 @@ struct Plan {
   int grid_re = 0;
   std::vector<QueryDesc> qd;
   std::vector<PairItem> longitems;
+  std::vector<PairItem> second;  // per long item: its second pair (two-pair items) or len -1
   int64_t qp16_elems = 0, qp8_elems = 0;
 };
 
@@ -394,6 +397,37 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
                           (256.0 / std::max(1, db->num_cu));
   const double t_step = 0.5e-6 * step_scale;
   const int64_t cap = g_knob_max_segments.load();
+  // Narrow pairs of the same query can run two per wave as one packed int16 item
+  // (consecutive in cost order, so of similar length).  Such an item does two pairs'
+  // cells per step at about 1.45 times the single step's time, which pays when the
+  // search is throughput-bound and hurts the critical path when it is not, so pairing
+  // is used only when there are at least two narrow items per wave slot, and only for
+  // items whose paired time stays under a quarter of the estimated search time.  Wide
+  // pairs stay single, in int32.  (Knob value 2 pairs every unsplit pair, wide ones
+  // included: a test setting.)
+  const int64_t pair_mode = g_knob_intra_pairs.load();
+  const bool pair_all = pair_mode == 2;
+  const bool pairs16 = pair_all ||
+                       (pair_mode == 1 &&
+                        narrow.size() >= 2 * (size_t)std::max(1, db->num_cu) * kIntraWaves);
+  PairItem none;
+  std::memset(&none, 0, sizeof(none));
+  none.len = -1;
+  none.out = -1;
+  std::vector<int64_t> pending((size_t)nq, -1);  // index in longitems of an unpaired item
+  auto emit = [&](const PairItem &it, bool pairable) {
+    if (pairs16 && pairable) {
+      int64_t &pend = pending[(size_t)it.query];
+      if (pend >= 0) {
+        p.second[(size_t)pend] = it;
+        pend = -1;
+        return;
+      }
+      pend = (int64_t)p.longitems.size();
+    }
+    p.longitems.push_back(it);
+    p.second.push_back(none);
+  };
   for (auto &x : wide) {
     const PairItem &it = x.second;
     const int32_t nb = it.band1;
@@ -407,6 +441,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     if (whole * 64 * t_step > 0.5 * t_search) S = piped * 64 * t_step <= t_search ? s8 : s4;
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
     S = std::max<int32_t>(1, std::min(S, nb));
+    if (S == 1) {
+      emit(it, pair_all);
+      continue;
+    }
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
     for (int32_t j = 0; j < S; ++j) {
       PairItem sg = it;
@@ -425,10 +463,16 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
         p.nprog += 1;
       }
       p.longitems.push_back(sg);
+      p.second.push_back(none);
     }
   }
   p.n_wide = (int32_t)p.longitems.size();
-  for (auto &x : narrow) p.longitems.push_back(x.second);
+  std::fill(pending.begin(), pending.end(), -1);  // wide and narrow items are not mixed
+  for (auto &x : narrow) {
+    const PairItem &it = x.second;
+    const double single = (double)it.band1 * (double)((it.len + 126) / 64) * 64 * t_step;
+    emit(it, pair_all || 1.45 * single <= 0.25 * t_search);
+  }
 
   const int64_t nitems16 = (int64_t)ninter * nq;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
@@ -436,7 +480,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   // per-step profile gathers touch one cache line per lane, and a second resident
   // workgroup per CU measured slower and erratic on MI355X (86 ms vs 103-115 ms for a
   // 35000-residue query over the long-sequence mix), not faster.
-  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + ((int64_t)narrow.size() + kIntraWaves - 1) / kIntraWaves,
+  const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
+  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + kIntraWaves - 1) / kIntraWaves,
                                        (int64_t)db->num_cu);
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not
   p.grid_re = (db->n_short > 0 && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
@@ -447,12 +492,13 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const size_t bnd16_slot = (size_t)db->max_ncols * 64;  // dwords
   const int bnd32_stride = ((db->max_len + 128 + 63) / 64) * 64;
   const size_t bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * bnd32_stride;
-  const size_t need_flagged = (size_t)std::max<int64_t>(1, db->n_short * nq);
+  // saturated pairs: any database sequence, from either kernel
+  const size_t need_flagged = (size_t)std::max<int64_t>(1, db->n_seqs * nq);
   const int64_t cap_mb = g_knob_mem_cap_mb.load();
   {
     size_t need = (size_t)qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
                   (size_t)p.qp16_elems * 2 + (size_t)p.qp8_elems + sizeof(Counters) +
-                  need_flagged * sizeof(PairItem) + p.longitems.size() * sizeof(PairItem) +
+                  need_flagged * sizeof(PairItem) + 2 * p.longitems.size() * sizeof(PairItem) +
                   (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8 +
                   (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
     if (cap_mb > 0 && (int64_t)(std::max(need, w->total_bytes()) >> 20) > cap_mb)
@@ -468,6 +514,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   grow(w->ctr, sizeof(Counters));
   grow(w->flagged, need_flagged * sizeof(PairItem));
   grow(w->longitems, std::max<size_t>(1, p.longitems.size()) * sizeof(PairItem));
+  grow(w->second, std::max<size_t>(1, p.second.size()) * sizeof(PairItem));
   grow(w->bnd16, std::max<size_t>(1, (size_t)p.grid16 * bnd16_slot) * 4);
   grow(w->bnd32, std::max<size_t>(1, (size_t)grid32 * bnd32_slot) * 8);
   grow(w->xbnd, (size_t)std::max<int64_t>(1, p.xbnd_elems) * 8);
@@ -480,7 +527,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const size_t off_mx = off_qd + ((nq * sizeof(QueryDesc) + 63) & ~size_t(63));
   const size_t off_qo = off_mx + (((size_t)A * A * 4 + 63) & ~size_t(63));
   const size_t off_li = off_qo + ((nq * sizeof(int32_t) + 63) & ~size_t(63));
-  const size_t stage_bytes = off_li + p.longitems.size() * sizeof(PairItem) + 64;
+  const size_t off_se = off_li + ((p.longitems.size() * sizeof(PairItem) + 63) & ~size_t(63));
+  const size_t stage_bytes = off_se + p.second.size() * sizeof(PairItem) + 64;
   grow_host(w->staging, stage_bytes);
   uint8_t *st = (uint8_t *)w->staging.ptr;
   if (qbytes) std::memcpy(st, queries, (size_t)qbytes);
@@ -488,16 +536,21 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   if (nq) std::memcpy(st + off_qd, p.qd.data(), nq * sizeof(QueryDesc));
   std::memcpy(st + off_mx, matrix, (size_t)A * A * 4);
   if (nq) std::memcpy(st + off_qo, qorder.data(), nq * sizeof(int32_t));
-  if (!p.longitems.empty())
+  if (!p.longitems.empty()) {
     std::memcpy(st + off_li, p.longitems.data(), p.longitems.size() * sizeof(PairItem));
+    std::memcpy(st + off_se, p.second.data(), p.second.size() * sizeof(PairItem));
+  }
   if (qbytes) hip_check(hipMemcpyAsync(w->queries.ptr, st, (size_t)qbytes, hipMemcpyHostToDevice, s));
   hip_check(hipMemcpyAsync(w->qoff.ptr, st + off_qoff, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, s));
   if (nq) hip_check(hipMemcpyAsync(w->qdesc.ptr, st + off_qd, nq * sizeof(QueryDesc), hipMemcpyHostToDevice, s));
   hip_check(hipMemcpyAsync(w->matrix.ptr, st + off_mx, (size_t)A * A * 4, hipMemcpyHostToDevice, s));
   if (nq) hip_check(hipMemcpyAsync(w->qorder.ptr, st + off_qo, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  if (!p.longitems.empty())
+  if (!p.longitems.empty()) {
     hip_check(hipMemcpyAsync(w->longitems.ptr, st + off_li, p.longitems.size() * sizeof(PairItem),
                              hipMemcpyHostToDevice, s));
+    hip_check(hipMemcpyAsync(w->second.ptr, st + off_se, p.second.size() * sizeof(PairItem),
+                             hipMemcpyHostToDevice, s));
+  }
 
   Counters *ctr = (Counters *)w->ctr.ptr;
   ProfileArgs pa;
@@ -540,6 +593,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
     ia.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
     ia.error = &ctr->error;
+    ia.second = (const PairItem *)w->second.ptr;
+    ia.flagged = (PairItem *)w->flagged.ptr;
+    ia.flag_count = &ctr->flagged;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
     hip_check(launch_intra32(ia, p.R, kIntraWaves, p.grid_long, w->aux));
@@ -577,8 +633,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       hip_check(hipEventRecord(w->t1[0], s));
       w->timed[0] = true;
     }
-    // exact int32 recompute of the saturated alignments (count read on the device);
-    // it uses the boundary slots after the long-sequence kernel's, so both may overlap
+    // exact int32 recompute of the saturated alignments of both kernels (count read on
+    // the device), after the long-pair kernel; it uses the boundary slots after that
+    // kernel's
+    if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
     IntraArgs ra;
     ra.packed = (const uint8_t *)db->packed.ptr;
     ra.items = (const PairItem *)w->flagged.ptr;
@@ -600,6 +658,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
     ra.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
     ra.error = &ctr->error;
+    ra.second = nullptr;
+    ra.flagged = nullptr;
+    ra.flag_count = nullptr;
     if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
     hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
     if (timed && p.grid_re > 0) {
@@ -642,6 +703,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       if (value != 0 && value != 4 && value != 8 && value != 16) return SW_EINVAL;
       g_knob_intra_rows = value;
       return SW_OK;
+    case SW_KNOB_INTRA_PAIRS: if (value < 0 || value > 2) return SW_EINVAL; g_knob_intra_pairs = value; return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -657,6 +719,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_WIDE_LEN: return g_knob_wide_len.load();
     case SW_KNOB_MAX_SEGMENTS: return g_knob_max_segments.load();
     case SW_KNOB_INTRA_ROWS: return g_knob_intra_rows.load();
+    case SW_KNOB_INTRA_PAIRS: return g_knob_intra_pairs.load();
     default: return SW_EINVAL;
   }
 }

@@ -507,6 +507,186 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
   L.rq = rq_next;
 }
 
+// ---- Two pairs per wave in packed int16 (Section 4.2: narrow range first).  The low
+// half of every register belongs to sequence A, the high half to sequence B; both run
+// against the same query rows, so one packed instruction advances two cells.  Values
+// stay in [0, 32767] exactly as in the inter-task kernel (saturating add, E and F
+// clamped at zero by unsigned saturating subtraction), a half whose maximum reaches
+// 32767 is recomputed in int32, and every other half is exact.
+template <int R>
+struct BandLane16 {
+  uint32_t H[R], E[R];
+  uint32_t hbot, fbot, hdiag;
+  int cfarA, cfarB;
+  int2 tq;  // band-top (H, F), both halves packed
+  int rqA, rqB;
+  RowBuf<R> PA[kIntraBuf], PB[kIntraBuf];
+};
+
+// Row r's scores for A (low half) and B (high half), sign-extended from their int8
+// bytes by one byte permute: the permute can copy a sign only from bytes 1 and 3 of
+// each word, so rows at even byte positions are first moved up by a byte.
+template <int R>
+__device__ __forceinline__ uint32_t pair_score(const RowBuf<R> &A, const RowBuf<R> &B, int r) {
+  const int j = r & 3;
+  uint32_t a = A.word(r >> 2), b = B.word(r >> 2);
+  if ((j & 1) == 0) { a <<= 8; b <<= 8; }
+  const uint32_t k = (uint32_t)(j | 1);  // byte of A (1 or 3); B's is k + 4
+  const uint32_t sel = k | ((k == 1 ? 8u : 9u) << 8) | ((k + 4) << 16) | ((k == 1 ? 10u : 11u) << 24);
+  return __builtin_amdgcn_perm(b, a, sel);
+}
+
+template <int R>
+__device__ __forceinline__ void band_start16(BandLane16<R> &L, int lane, int nA, int nB,
+                                             const int2 *top, bool has_top,
+                                             const uint8_t *resA, int csA, const uint8_t *resB,
+                                             int csB, const uint8_t *prof, uint32_t pstride) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) { L.H[r] = 0; L.E[r] = 0; }
+  L.hbot = 0; L.fbot = 0; L.hdiag = 0; L.cfarA = kPadCode; L.cfarB = kPadCode;
+  L.tq = (has_top && lane < nA) ? top[lane] : make_int2(0, 0);
+  L.rqA = lane < nA ? resA[(lane >> 2) * (int64_t)csA + (lane & 3)] : kPadCode;
+  L.rqB = lane < nB ? resB[(lane >> 2) * (int64_t)csB + (lane & 3)] : kPadCode;
+#pragma unroll
+  for (int t = 0; t + 1 < kIntraBuf; ++t) {
+    L.cfarA = wave_shr1(L.cfarA, __builtin_amdgcn_readlane(L.rqA, t));
+    L.cfarB = wave_shr1(L.cfarB, __builtin_amdgcn_readlane(L.rqB, t));
+    load_rows(L.PA[t], prof, pstride, L.cfarA);
+    load_rows(L.PB[t], prof, pstride, L.cfarB);
+  }
+}
+
+// Chunk k of a band sweep for both pairs (nA >= nB; B's columns past nB carry the
+// padding code).  Same schedule as band_chunk.
+template <int R>
+__device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, uint32_t goe2,
+                                             uint32_t ge2, int lane, int k, int nA, int nB,
+                                             const int2 *top, bool has_top, int2 *bot,
+                                             bool has_bot, const uint8_t *resA, int csA,
+                                             const uint8_t *resB, int csB,
+                                             const uint8_t *prof, uint32_t pstride) {
+  constexpr int D = kIntraBuf - 1;
+  const int col_next = 64 * (k + 1) + lane;
+  const int2 tq_next = (has_top && col_next < nA) ? top[col_next] : make_int2(0, 0);
+  const int rqA_next = col_next < nA
+      ? (int)resA[(col_next >> 2) * (int64_t)csA + (col_next & 3)] : kPadCode;
+  const int rqB_next = col_next < nB
+      ? (int)resB[(col_next >> 2) * (int64_t)csB + (col_next & 3)] : kPadCode;
+
+  auto step = [&](const int i, const RowBuf<R> &PA, const RowBuf<R> &PB, RowBuf<R> &PAfar,
+                  RowBuf<R> &PBfar) {
+    const int s = 64 * k + i;
+    const int cinA = i + D < 64 ? __builtin_amdgcn_readlane(L.rqA, i + D)
+                                : __builtin_amdgcn_readlane(rqA_next, i + D - 64);
+    const int cinB = i + D < 64 ? __builtin_amdgcn_readlane(L.rqB, i + D)
+                                : __builtin_amdgcn_readlane(rqB_next, i + D - 64);
+    L.cfarA = wave_shr1(L.cfarA, cinA);
+    L.cfarB = wave_shr1(L.cfarB, cinB);
+    load_rows(PAfar, prof, pstride, L.cfarA);
+    load_rows(PBfar, prof, pstride, L.cfarB);
+    const uint32_t hup = (uint32_t)wave_shr1((int)L.hbot, __builtin_amdgcn_readlane(L.tq.x, i));
+    uint32_t f = (uint32_t)wave_shr1((int)L.fbot, __builtin_amdgcn_readlane(L.tq.y, i));
+    uint32_t x = pk_adds(L.hdiag, pair_score<R>(PA, PB, 0));
+    L.hdiag = hup;
+    uint32_t h = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t xn = r + 1 < R ? pk_adds(L.H[r], pair_score<R>(PA, PB, r + 1)) : 0u;
+      h = pk_max(pk_max(x, L.E[r]), f);             // Eq. 1 (E, F clamped >= 0)
+      vmax = pk_max(vmax, h);
+      const uint32_t t = pk_subu(h, goe2);
+      L.E[r] = pk_max(pk_subu(L.E[r], ge2), t);     // Eq. 2
+      f = pk_max(pk_subu(f, ge2), t);               // Eq. 3
+      L.H[r] = h;
+      x = xn;
+    }
+    L.hbot = h;
+    L.fbot = f;
+    if (has_bot && lane == 63 && s >= 63 && s - 63 < nA)
+      bot[s - 63] = make_int2((int)h, (int)f);
+  };
+  for (int i = 0; i < 64; i += kIntraBuf) {
+#pragma unroll
+    for (int u = 0; u < kIntraBuf; ++u)
+      step(i + u, L.PA[u], L.PB[u], L.PA[(u + kIntraBuf - 1) % kIntraBuf],
+           L.PB[(u + kIntraBuf - 1) % kIntraBuf]);
+  }
+  L.tq = tq_next;
+  L.rqA = rqA_next;
+  L.rqB = rqB_next;
+}
+
+// Both pairs of a two-pair item swept by NW waves (the band pipeline of intra_pair; such
+// items are never split).  Returns this lane's packed running maximum.
+template <int R, int NW>
+__device__ uint32_t intra_pair16(const IntraArgs &a, const PairItem &pa, const PairItem &pb,
+                                 const QueryDesc &qd, int w, int2 *ring) {
+  const int lane = threadIdx.x & 63;
+  const int nA = pa.len, nB = pb.len;  // nA >= nB
+  const int nb = pa.band1 - pa.band0;
+  uint32_t vmax = 0;
+  if (nA <= 0 || nb <= 0) return 0;
+  const int nc = (nA + 63 + 63) / 64;
+  const int nce = nc > kIntraLag * NW ? nc : kIntraLag * NW;
+  const int lastb = nb - 1;
+  const int rounds = (lastb / NW) * nce + kIntraLag * (lastb % NW) + nc;
+  const uint8_t *resA = a.packed + pa.base, *resB = a.packed + pb.base;
+  const int csA = pa.cstride, csB = pb.cstride;
+  const uint32_t pstride = (uint32_t)qd.mrows;
+  const uint32_t goe2 = (uint32_t)a.goe * 0x10001u, ge2 = (uint32_t)a.ge * 0x10001u;
+
+  int bl = w;
+  BandLane16<R> L;
+  for (int rd = 0; rd < rounds; ++rd) {
+    if (bl < nb) {
+      const int st = (bl / NW) * nce + kIntraLag * (bl % NW);
+      if (rd >= st && rd < st + nc) {
+        const int k = rd - st;
+        const int b = pa.band0 + bl;
+        const int2 *top = ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride;
+        int2 *bot = ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
+        const bool has_top = bl > 0, has_bot = bl < nb - 1;
+        const uint8_t *prof = reinterpret_cast<const uint8_t *>(
+            a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
+        if (k == 0)
+          band_start16(L, lane, nA, nB, top, has_top, resA, csA, resB, csB, prof, pstride);
+        band_chunk16(L, vmax, goe2, ge2, lane, k, nA, nB, top, has_top, bot, has_bot, resA,
+                     csA, resB, csB, prof, pstride);
+        if (k == nc - 1) bl += NW;
+      }
+    }
+    if (NW > 1) __syncthreads();
+  }
+  return vmax;
+}
+
+// Score of one half of a two-pair item: written, or (if it may have saturated) the pair
+// is appended to the int32 recompute list.  Called by all lanes of a wave with the same
+// score (lane 0 claims the list slot, every lane stores the same item) or by lane 0 of a
+// workgroup alone.
+__device__ __forceinline__ void finish_half(const IntraArgs &a, const PairItem &p,
+                                            const QueryDesc &qd, int score) {
+  const int lane = threadIdx.x & 63;
+  if (score >= kSat16) {
+    PairItem it = p;
+    it.band0 = 0;
+    it.band1 = qd.nbands;  // the recompute runs with 16 rows per lane
+    it.xin = it.xout = -1;
+    it.prog_in = it.prog_out = -1;
+    it.segment = 0;
+    it.nsegments = 1;
+    const int k = __builtin_amdgcn_readfirstlane(atomicAdd(a.flag_count, lane == 0 ? 1 : 0));
+    a.flagged[k] = it;
+  } else {
+    a.scores[qd.out + p.out] = score;
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_pk_max(uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v = pk_max(v, (uint32_t)__shfl_xor((int)v, off));
+  return v;
+}
+
 // Returns this lane's running maximum of H over the cells it computed.  `ring` holds
 // NW + 1 band-boundary buffers of a.bnd_stride (H, F) pairs.
 template <int R, int NW>
@@ -586,7 +766,9 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
 
 // Items [0, n_wide) are swept by a whole workgroup each ("wide"); items [n_wide, count)
 // by a single wave each ("narrow").  Each workgroup first takes wide items, then its waves
-// take narrow items independently.
+// take narrow items independently.  If a.second is given, an item whose second entry has
+// a length >= 0 is a two-pair item (int16, recompute on saturation); the others run in
+// int32.
 template <int R, int W>
 __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
   __shared__ int s_item;
@@ -608,6 +790,19 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
     if (it < 0) break;
     const PairItem pi = a.items[it];
     const QueryDesc qd = a.queries[pi.query];
+    if (a.second && a.second[it].len >= 0) {
+      const PairItem pb = a.second[it];
+      const uint32_t v = wave_pk_max(intra_pair16<R, W>(a, pi, pb, qd, w, slot));
+      if (lane == 0) s_max[w] = (int32_t)v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t m = 0;
+        for (int i = 0; i < W; ++i) m = pk_max(m, (uint32_t)s_max[i]);
+        finish_half(a, pi, qd, (int)(int16_t)(m & 0xffffu));
+        finish_half(a, pb, qd, (int)(int16_t)(m >> 16));
+      }
+      continue;
+    }
     int32_t vmax = intra_pair<R, W>(a, pi, qd, w, slot);
     for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
     if (lane == 0) s_max[w] = vmax;
@@ -654,6 +849,13 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
     if (it >= count) break;
     const PairItem pi = a.items[it];
     const QueryDesc qd = a.queries[pi.query];
+    if (a.second && a.second[it].len >= 0) {
+      const PairItem pb = a.second[it];
+      const uint32_t v = wave_pk_max(intra_pair16<R, 1>(a, pi, pb, qd, 0, ring));
+      finish_half(a, pi, qd, (int)(int16_t)(v & 0xffffu));
+      finish_half(a, pb, qd, (int)(int16_t)(v >> 16));
+      continue;
+    }
     int32_t vmax = intra_pair<R, 1>(a, pi, qd, 0, ring);
     for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
     a.scores[qd.out + pi.out] = vmax;

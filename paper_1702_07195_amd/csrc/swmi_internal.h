@@ -109,6 +109,10 @@ struct IntraArgs {
   int32_t *xfin;             // 1 once the segment before the boundary has finished
   int32_t *xmax;             // maximum of H so far, passed along the segments of a pair
   int32_t *error;            // Counters::error
+  const PairItem *second;    // per item: the second pair of a two-pair item (len >= 0),
+                             // or len < 0; NULL when every item is a single pair
+  PairItem *flagged;         // recompute list for two-pair halves that may have saturated
+  int32_t *flag_count;       // Counters::flagged
 };
 
 struct ProfileArgs {

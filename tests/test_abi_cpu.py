@@ -122,3 +122,17 @@ def test_intra_rows_knob_takes_only_band_shapes():
             assert swmi.get_knob(swmi.SW_KNOB_INTRA_ROWS) == good
     finally:
         swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, old)
+
+
+def test_intra_pairs_knob_values():
+    old = swmi.get_knob(swmi.SW_KNOB_INTRA_PAIRS)
+    assert old == 1
+    try:
+        for bad in (-1, 3):
+            with pytest.raises(swmi.SwError):
+                swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, bad)
+        for good in (0, 2, 1):
+            swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, good)
+            assert swmi.get_knob(swmi.SW_KNOB_INTRA_PAIRS) == good
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, old)

@@ -405,3 +405,54 @@ def test_server_runs_one_query_per_launch_when_it_fills_the_device():
     idx = np.linspace(0, db.n_seqs - 1, 40).astype(np.int64)
     want = oracle.search(qs[0], db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
     assert np.array_equal(alone[0][idx], want)
+
+
+@pytest.mark.parametrize("R", [0, 4, 16])
+def test_paired_intra_items_with_saturation(R):
+    # Two pairs per wave in packed int16 (wide and narrow items, every unsplit pair
+    # paired): halves whose maximum reaches 32767 are recomputed in int32, the other half
+    # of the same item keeps its int16 score.  SM(a, a) = 127: a^258 scores 32766 (exact),
+    # a^259 32893 (saturates).
+    sm = np.array([[127, -3], [-3, 127]], dtype=np.int32)
+    rng = np.random.Generator(np.random.PCG64(77 + R))
+    seqs = [np.zeros(257, np.uint8), np.zeros(258, np.uint8), np.zeros(259, np.uint8),
+            np.zeros(1500, np.uint8)]
+    seqs += [rng.integers(0, 2, size=int(n)).astype(np.uint8) for n in rng.integers(1, 1100, 41)]
+    seqs += [rng.integers(0, 2, size=int(n)).astype(np.uint8) for n in rng.integers(1200, 2600, 9)]
+    db = synth.db_from_seqs(seqs)
+    q = np.zeros(1300, np.uint8)
+    q[::97] = 1
+    old = [swmi.get_knob(k) for k in (swmi.SW_KNOB_ROUTE_LEN, swmi.SW_KNOB_INTRA_PAIRS,
+                                      swmi.SW_KNOB_INTRA_ROWS)]
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, 2)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, R)
+    try:
+        _say(f"paired intra items R={R}")
+        with swmi.sw_db_load(db.residues, db.offsets, 2) as h:
+            got = h.search(q, sm, 10, 2)
+    finally:
+        for k, v in zip((swmi.SW_KNOB_ROUTE_LEN, swmi.SW_KNOB_INTRA_PAIRS,
+                         swmi.SW_KNOB_INTRA_ROWS), old):
+            swmi.set_knob(k, v)
+    want = _oracle(q, db, sm, 10, 2)
+    assert want[1] < 32767 <= want[2]
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("m", [200, 2100])
+def test_paired_intra_items_blosum(small_db, small_handle, m):
+    # every unsplit intra-task pair paired, on the small database (empty sequences
+    # included, an odd number of items per kind)
+    rng = np.random.Generator(np.random.PCG64(5000 + m))
+    q = synth.residues(rng, m)
+    old = (swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN), swmi.get_knob(swmi.SW_KNOB_INTRA_PAIRS))
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, 2)
+    try:
+        _say(f"paired intra items m={m}")
+        got = small_handle.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
+        swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, old[1])
+    assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
