@@ -407,9 +407,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   // included: a test setting.)
   const int64_t pair_mode = g_knob_intra_pairs.load();
   const bool pair_all = pair_mode == 2;
-  const bool pairs16 = pair_all ||
-                       (pair_mode == 1 &&
-                        narrow.size() >= 2 * (size_t)std::max(1, db->num_cu) * kIntraWaves);
+  const bool pair_narrow = pair_mode == 1 &&
+                           narrow.size() >= 2 * (size_t)std::max(1, db->num_cu) * kIntraWaves;
+  const bool pair_wide = pair_mode == 1 && wide.size() >= 2 * (size_t)std::max(1, db->num_cu);
+  const bool pairs16 = pair_all || pair_narrow || pair_wide;
   PairItem none;
   std::memset(&none, 0, sizeof(none));
   none.len = -1;
@@ -442,7 +443,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
     S = std::max<int32_t>(1, std::min(S, nb));
     if (S == 1) {
-      emit(it, pair_all);
+      emit(it, pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
       continue;
     }
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
@@ -471,7 +472,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   for (auto &x : narrow) {
     const PairItem &it = x.second;
     const double single = (double)it.band1 * (double)((it.len + 126) / 64) * 64 * t_step;
-    emit(it, pair_all || 1.45 * single <= 0.25 * t_search);
+    emit(it, pair_all || (pair_narrow && 1.45 * single <= 0.25 * t_search));
   }
 
   const int64_t nitems16 = (int64_t)ninter * nq;
