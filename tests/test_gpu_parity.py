@@ -456,3 +456,40 @@ def test_paired_intra_items_blosum(small_db, small_handle, m):
         swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
         swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, old[1])
     assert np.array_equal(got, _oracle(q, small_db, synth.BLOSUM62, 10, 2))
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_configurations(case):
+    # Seeded random configurations: alphabet, asymmetric matrix (entries up to the
+    # +-127 bound), gap penalties, query length and database length law, with every
+    # routing and pairing setting drawn at random; scores must equal the oracle's.
+    rng = np.random.Generator(np.random.PCG64(31337 + case))
+    alpha = int(rng.integers(2, 25))
+    bound = int(rng.choice([3, 10, 127]))
+    sm = synth.random_matrix(rng, alpha, -bound, bound)
+    go, ge = int(rng.integers(0, 20)), int(rng.integers(0, 6))
+    m = int(rng.choice([1, 7, 63, 300, 1100, 2500]))
+    n_seqs = int(rng.integers(50, 400))
+    lengths = synth.lognormal_lengths(rng, n_seqs, float(rng.choice([30, 150, 600])), 0.9, 0,
+                                      3000)
+    residues = rng.integers(0, alpha, size=int(lengths.sum()), dtype=np.uint8)
+    offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
+    db = synth.SeqDB(residues, offsets)
+    q = rng.integers(0, alpha, size=m, dtype=np.uint8)
+    knobs = {swmi.SW_KNOB_ROUTE_LEN: int(rng.choice([0, 1, 1 << 30])),
+             swmi.SW_KNOB_INTRA_PAIRS: int(rng.integers(0, 3)),
+             swmi.SW_KNOB_INTRA_ROWS: int(rng.choice([0, 4, 8, 16])),
+             swmi.SW_KNOB_STRIP_ROWS: int(rng.choice([0, 8, 16, 24, 32, 40]))}
+    old = {k: swmi.get_knob(k) for k in knobs}
+    try:
+        for k, v in knobs.items():
+            swmi.set_knob(k, v)
+        _say(f"random case {case}: A={alpha} |SM|<={bound} gaps {go}/{ge} m={m} "
+             f"n={n_seqs} knobs={list(knobs.values())}")
+        with swmi.sw_db_load(db.residues, db.offsets, alpha) as h:
+            got = h.search(q, sm, go, ge)
+    finally:
+        for k, v in old.items():
+            swmi.set_knob(k, v)
+    want = oracle.search(q, db.residues, db.offsets, sm, go, ge)
+    assert np.array_equal(got, want)
