@@ -89,7 +89,9 @@ void sw_db_free(sw_db *db);
  *
  * Blocks until the scores are on the host.  Safe to call concurrently from several
  * host threads on one handle (the database is read-only; each call takes its own
- * device workspace).  Errors: SW_ENODB, SW_EINVAL, SW_ENOMEM, SW_EDEVICE.
+ * device workspace).  Errors: SW_ENODB, SW_EINVAL, SW_ENOMEM, SW_EDEVICE (also when a
+ * bounded wait between the workgroups of a split pair gave up; see
+ * SW_KNOB_SPIN_LIMIT).  After an error the contents of scores_out are unspecified.
  */
 int sw_search(const sw_db *db, const uint8_t *query, int32_t query_len,
               const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
@@ -106,7 +108,9 @@ int sw_search(const sw_db *db, const uint8_t *query, int32_t query_len,
  *   hip_stream  a hipStream_t (NULL = the default stream).
  *
  * Returns once the work is enqueued.  The device workspace of the call is recycled
- * only after the stream has passed it.  Errors as for sw_search.
+ * only after the stream has passed it.  Errors as for sw_search, except that a bounded
+ * wait that gives up on the device cannot be reported by an asynchronous call (its
+ * default limit, 2^24 polls, is seconds beyond any legitimate wait).
  */
 int sw_search_async(const sw_db *db, const uint8_t *query, int32_t query_len,
                     const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
@@ -260,7 +264,12 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *   SW_KNOB_INTRA_PAIRS    1 (default): when a search has many narrow intra-task pairs,
  *                          short ones run two per wave in packed int16 (saturated halves
  *                          recomputed in int32); 0: every intra-task pair runs alone in
- *                          int32; 2: every unsplit pair is paired (for tests).
+ *                          int32; 2: every unsplit pair is paired (for tests);
+ *   SW_KNOB_SPIN_LIMIT     polls after which a workgroup waiting for the previous
+ *                          segment of a split intra-task pair gives up (1..2^24; 0 =
+ *                          2^24).  A wait that gives up marks the search failed (a
+ *                          blocking search returns SW_EDEVICE) and every kernel still
+ *                          runs to its end; tiny values exist to test that path.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -272,6 +281,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_MAX_SEGMENTS   8
 #define SW_KNOB_INTRA_ROWS     9
 #define SW_KNOB_INTRA_PAIRS    10
+#define SW_KNOB_SPIN_LIMIT     11
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

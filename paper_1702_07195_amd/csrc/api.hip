@@ -35,6 +35,7 @@ std::atomic<int64_t> g_knob_wide_len{0};
 std::atomic<int64_t> g_knob_max_segments{0};
 std::atomic<int64_t> g_knob_intra_rows{0};
 std::atomic<int64_t> g_knob_intra_pairs{1};
+std::atomic<int64_t> g_knob_spin_limit{0};
 
 struct HipFail {
   hipError_t err;
@@ -597,6 +598,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.second = (const PairItem *)w->second.ptr;
     ia.flagged = (PairItem *)w->flagged.ptr;
     ia.flag_count = &ctr->flagged;
+    ia.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
     hip_check(launch_intra32(ia, p.R, kIntraWaves, p.grid_long, w->aux));
@@ -662,6 +664,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.second = nullptr;
     ra.flagged = nullptr;
     ra.flag_count = nullptr;
+    ra.spin_limit = kSpinLimit;
     if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
     hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
     if (timed && p.grid_re > 0) {
@@ -705,6 +708,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       g_knob_intra_rows = value;
       return SW_OK;
     case SW_KNOB_INTRA_PAIRS: if (value < 0 || value > 2) return SW_EINVAL; g_knob_intra_pairs = value; return SW_OK;
+    case SW_KNOB_SPIN_LIMIT:
+      if (value < 0 || value > kSpinLimit) return SW_EINVAL;
+      g_knob_spin_limit = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -721,6 +728,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_MAX_SEGMENTS: return g_knob_max_segments.load();
     case SW_KNOB_INTRA_ROWS: return g_knob_intra_rows.load();
     case SW_KNOB_INTRA_PAIRS: return g_knob_intra_pairs.load();
+    case SW_KNOB_SPIN_LIMIT: return g_knob_spin_limit.load();
     default: return SW_EINVAL;
   }
 }

@@ -727,7 +727,7 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
         if (ext_top) {
           // wait until the columns this chunk and the next read are published
           const int need = min(n, 64 * (k + 2));
-          // (bounded: after kSpinLimit polls, or once any wait has given up, the flag is
+          // (bounded: after a.spin_limit polls, or once any wait has given up, the flag is
           // set and the kernel runs to its end with whatever the buffer holds)
           // (polled relaxed, then one acquire fence: an acquire load per poll would
           // invalidate the cache on every iteration)
@@ -736,7 +736,7 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
                                    __HIP_MEMORY_SCOPE_AGENT) < need) {
             if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
             __builtin_amdgcn_s_sleep(4);
-            if (++polls > kSpinLimit) {
+            if (++polls > a.spin_limit) {
               __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               break;
             }
@@ -819,7 +819,7 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
                                  __HIP_MEMORY_SCOPE_AGENT) == 0) {
           if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
           __builtin_amdgcn_s_sleep(4);
-          if (++polls > kSpinLimit) {
+          if (++polls > a.spin_limit) {
             __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
           }

@@ -113,6 +113,7 @@ struct IntraArgs {
                              // or len < 0; NULL when every item is a single pair
   PairItem *flagged;         // recompute list for two-pair halves that may have saturated
   int32_t *flag_count;       // Counters::flagged
+  int32_t spin_limit;        // polls before a wait between segments gives up (sets *error)
 };
 
 struct ProfileArgs {
@@ -173,6 +174,6 @@ constexpr int kIntraR = 16;
 constexpr int kIntraBuf = 4;     // profile-row buffers per lane (prefetch distance + 1)
 constexpr int kIntraWaves = 8;
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
-constexpr int kSpinLimit = 1 << 24;  // polls before a wait between segments gives up
+constexpr int kSpinLimit = 1 << 24;  // default polls before a wait between segments gives up
 
 }  // namespace swmi

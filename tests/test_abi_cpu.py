@@ -136,3 +136,15 @@ def test_intra_pairs_knob_values():
             assert swmi.get_knob(swmi.SW_KNOB_INTRA_PAIRS) == good
     finally:
         swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, old)
+
+
+def test_spin_limit_knob_range():
+    old = swmi.get_knob(swmi.SW_KNOB_SPIN_LIMIT)
+    try:
+        for bad in (-1, (1 << 24) + 1):
+            with pytest.raises(swmi.SwError):
+                swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, bad)
+        swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, 1)
+        assert swmi.get_knob(swmi.SW_KNOB_SPIN_LIMIT) == 1
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, old)

@@ -493,3 +493,31 @@ def test_random_configurations(case):
             swmi.set_knob(k, v)
     want = oracle.search(q, db.residues, db.offsets, sm, go, ge)
     assert np.array_equal(got, want)
+
+
+def test_segment_wait_that_gives_up_fails_the_search():
+    # A spin limit of one poll makes the waits between the segments of split pairs give
+    # up: every kernel still runs to its end, the blocking search reports SW_EDEVICE,
+    # and the next search (default limit) is exact again.
+    rng = np.random.Generator(np.random.PCG64(88))
+    lengths = np.concatenate([rng.integers(2000, 3000, 8), rng.integers(1, 900, 20)])
+    db = synth.db_from_lengths(rng, lengths)
+    q = synth.residues(rng, 17000)
+    knobs = (swmi.SW_KNOB_ROUTE_LEN, swmi.SW_KNOB_SPIN_LIMIT, swmi.SW_KNOB_INTRA_PAIRS)
+    old = [swmi.get_knob(k) for k in knobs]
+    try:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+        swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, 0)
+        with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+            swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, 1)
+            _say("search with a one-poll segment wait")
+            with pytest.raises(swmi.SwError) as e:
+                h.search(q, synth.BLOSUM62, 10, 2)
+            assert e.value.code == swmi.SW_EDEVICE
+            swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, 0)
+            _say("search with the default limit")
+            got = h.search(q, synth.BLOSUM62, 10, 2)
+    finally:
+        for k, v in zip(knobs, old):
+            swmi.set_knob(k, v)
+    assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
