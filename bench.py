@@ -399,7 +399,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="full",
                     choices=["full", "plain", "long_mix", "batched", "served"])
     ap.add_argument("--rates", default="2,8,32", help="served: arrival rates per second")

@@ -75,13 +75,15 @@ struct Workspace {
   hipEvent_t t0[3] = {}, t1[3] = {};  // kernel timing: inter-task, long intra, recompute
   bool timed[3] = {false, false, false};
   bool busy = false;
-  DevBuf queries, qoff, qdesc, qorder, matrix, qp16, qp8, ctr, flagged, longitems, second,
-      bnd16, bnd32, xbnd, xprog, scores;
+  uint64_t last_use = 0;  // order in which workspaces were last handed out
+  // `inputs` holds the per-call host data (queries, offsets, query descriptors,
+  // matrix, query order, intra-task items) in the layout of `staging`, so one copy
+  // moves it to the device
+  DevBuf inputs, qp16, qp8, ctr, flagged, bnd16, bnd32, xbnd, xprog, scores;
   HostBuf staging;
   size_t total_bytes() const {
-    return queries.bytes + qoff.bytes + qdesc.bytes + qorder.bytes + matrix.bytes + qp16.bytes + qp8.bytes +
-           ctr.bytes + flagged.bytes + longitems.bytes + second.bytes + bnd16.bytes + bnd32.bytes +
-           xbnd.bytes + xprog.bytes + scores.bytes;
+    return inputs.bytes + qp16.bytes + qp8.bytes + ctr.bytes + flagged.bytes + bnd16.bytes +
+           bnd32.bytes + xbnd.bytes + xprog.bytes + scores.bytes;
   }
 };
 
@@ -110,6 +112,7 @@ struct sw_db {
   int64_t short_residues = 0;       // residues in groups
   std::mutex mu;
   std::vector<Workspace *> pool;
+  uint64_t pool_uses = 0;
   std::atomic<bool> timing{false};
   std::mutex topk_mu;
   DevBuf topk_scratch;  // TopkState, 256 counters, kTopkMax keys, 2 x kTopkMax results
@@ -118,6 +121,7 @@ struct sw_db {
     hipEvent_t e0, e1;
   };
   std::vector<TimedLaunch> timing_events;
+  std::vector<hipEvent_t> spare_events;  // read timing events, reused by later searches
   int64_t timing_launches[3] = {0, 0, 0};
   double timing_ms[3] = {0.0, 0.0, 0.0};
 };
@@ -147,9 +151,8 @@ void grow_host(HostBuf &b, size_t bytes) {
 void destroy_workspace(Workspace *w) {
   if (w->own) (void)hipStreamSynchronize(w->own);
   if (w->aux) (void)hipStreamSynchronize(w->aux);
-  for (DevBuf *b : {&w->queries, &w->qoff, &w->qdesc, &w->qorder, &w->matrix, &w->qp16, &w->qp8, &w->ctr,
-                    &w->flagged, &w->longitems, &w->second, &w->bnd16, &w->bnd32, &w->xbnd,
-                    &w->xprog, &w->scores})
+  for (DevBuf *b : {&w->inputs, &w->qp16, &w->qp8, &w->ctr, &w->flagged, &w->bnd16, &w->bnd32,
+                    &w->xbnd, &w->xprog, &w->scores})
     b->release();
   w->staging.release();
   for (hipEvent_t e : {w->done, w->fork, w->join, w->t0[0], w->t1[0], w->t0[1], w->t1[1],
@@ -165,18 +168,24 @@ Workspace *acquire(sw_db *db) {
   for (Workspace *w : db->pool) {
     if (!w->busy && hipEventQuery(w->done) == hipSuccess) {
       w->busy = true;
+      w->last_use = ++db->pool_uses;
       return w;
     }
   }
-  // up to 8 workspaces are created on demand; beyond that a call waits for an idle one
-  // to finish (a new one is still created if all 8 are held by concurrent calls)
-  if (db->pool.size() >= 8) {
-    for (Workspace *w : db->pool) {
-      if (!w->busy) {
-        hip_check(hipEventSynchronize(w->done));
-        w->busy = true;
-        return w;
-      }
+  // Two workspaces let a host thread enqueue one search while the previous one runs;
+  // beyond that a call waits for the older idle workspace to finish, which keeps the
+  // device fed (the newer search is still queued) and costs less than sizing a new
+  // workspace.  A new one is still created if every workspace is held by a concurrent
+  // call.
+  if (db->pool.size() >= 2) {
+    Workspace *oldest = nullptr;
+    for (Workspace *w : db->pool)
+      if (!w->busy && (!oldest || w->last_use < oldest->last_use)) oldest = w;
+    if (oldest) {
+      hip_check(hipEventSynchronize(oldest->done));
+      oldest->busy = true;
+      oldest->last_use = ++db->pool_uses;
+      return oldest;
     }
   }
   Workspace *w = new Workspace();
@@ -196,6 +205,7 @@ Workspace *acquire(sw_db *db) {
     throw;
   }
   w->busy = true;
+  w->last_use = ++db->pool_uses;
   db->pool.push_back(w);
   return w;
 }
@@ -276,6 +286,7 @@ struct Plan {
   int32_t nprog = 0;       // progress counters of those boundaries
   int32_t ngroups_inter = 0;
   int32_t n_wide = 0;
+  int64_t nduos = 0;  // two-pair items (their halves may be flagged for recompute)
   int grid16 = 0;
   int grid_long = 0;
   int grid_re = 0;
@@ -423,6 +434,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       if (pend >= 0) {
         p.second[(size_t)pend] = it;
         pend = -1;
+        ++p.nduos;
         return;
       }
       pend = (int64_t)p.longitems.size();
@@ -485,8 +497,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
   p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + kIntraWaves - 1) / kIntraWaves,
                                        (int64_t)db->num_cu);
-  // the recompute list is usually empty; a quarter of the CUs is plenty when it is not
-  p.grid_re = (db->n_short > 0 && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
+  // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
+  // and nothing is launched when no kernel can append to it
+  const bool may_flag = (nitems16 > 0 && p.grid16 > 0) || p.nduos > 0;
+  p.grid_re = (may_flag && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
   const int grid32 = p.grid_long + p.grid_re;
 
   // workspace sizes
@@ -506,24 +520,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     if (cap_mb > 0 && (int64_t)(std::max(need, w->total_bytes()) >> 20) > cap_mb)
       throw HipFail{hipErrorOutOfMemory};
   }
-  grow(w->queries, (size_t)qbytes + 64);
-  grow(w->qoff, (size_t)(nq + 1) * 8);
-  grow(w->qdesc, std::max<size_t>(1, nq) * sizeof(QueryDesc));
-  grow(w->qorder, std::max<size_t>(1, nq) * sizeof(int32_t));
-  grow(w->matrix, (size_t)A * A * 4);
-  grow(w->qp16, (size_t)std::max<int64_t>(8, p.qp16_elems) * 2);
-  grow(w->qp8, (size_t)std::max<int64_t>(16, p.qp8_elems));
-  grow(w->ctr, sizeof(Counters));
-  grow(w->flagged, need_flagged * sizeof(PairItem));
-  grow(w->longitems, std::max<size_t>(1, p.longitems.size()) * sizeof(PairItem));
-  grow(w->second, std::max<size_t>(1, p.second.size()) * sizeof(PairItem));
-  grow(w->bnd16, std::max<size_t>(1, (size_t)p.grid16 * bnd16_slot) * 4);
-  grow(w->bnd32, std::max<size_t>(1, (size_t)grid32 * bnd32_slot) * 8);
-  grow(w->xbnd, (size_t)std::max<int64_t>(1, p.xbnd_elems) * 8);
-  // per segment boundary: progress, finished flag (both cleared per search), maximum
-  grow(w->xprog, (size_t)std::max<int32_t>(1, p.nprog) * 12);
-
-  // stage small inputs through pinned memory (reused only after `done`)
+  // small per-call inputs, staged through pinned memory (reused only after `done`) and
+  // copied to the device in one transfer
   const size_t off_qoff = ((size_t)qbytes + 63) & ~size_t(63);
   const size_t off_qd = off_qoff + (((size_t)(nq + 1) * 8 + 63) & ~size_t(63));
   const size_t off_mx = off_qd + ((nq * sizeof(QueryDesc) + 63) & ~size_t(63));
@@ -531,6 +529,17 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const size_t off_li = off_qo + ((nq * sizeof(int32_t) + 63) & ~size_t(63));
   const size_t off_se = off_li + ((p.longitems.size() * sizeof(PairItem) + 63) & ~size_t(63));
   const size_t stage_bytes = off_se + p.second.size() * sizeof(PairItem) + 64;
+  grow(w->inputs, stage_bytes);
+  grow(w->qp16, (size_t)std::max<int64_t>(8, p.qp16_elems) * 2);
+  grow(w->qp8, (size_t)std::max<int64_t>(16, p.qp8_elems));
+  grow(w->ctr, sizeof(Counters));
+  grow(w->flagged, need_flagged * sizeof(PairItem));
+  grow(w->bnd16, std::max<size_t>(1, (size_t)p.grid16 * bnd16_slot) * 4);
+  grow(w->bnd32, std::max<size_t>(1, (size_t)grid32 * bnd32_slot) * 8);
+  grow(w->xbnd, (size_t)std::max<int64_t>(1, p.xbnd_elems) * 8);
+  // per segment boundary: progress, finished flag (both cleared per search), maximum
+  grow(w->xprog, (size_t)std::max<int32_t>(1, p.nprog) * 12);
+
   grow_host(w->staging, stage_bytes);
   uint8_t *st = (uint8_t *)w->staging.ptr;
   if (qbytes) std::memcpy(st, queries, (size_t)qbytes);
@@ -542,25 +551,23 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     std::memcpy(st + off_li, p.longitems.data(), p.longitems.size() * sizeof(PairItem));
     std::memcpy(st + off_se, p.second.data(), p.second.size() * sizeof(PairItem));
   }
-  if (qbytes) hip_check(hipMemcpyAsync(w->queries.ptr, st, (size_t)qbytes, hipMemcpyHostToDevice, s));
-  hip_check(hipMemcpyAsync(w->qoff.ptr, st + off_qoff, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, s));
-  if (nq) hip_check(hipMemcpyAsync(w->qdesc.ptr, st + off_qd, nq * sizeof(QueryDesc), hipMemcpyHostToDevice, s));
-  hip_check(hipMemcpyAsync(w->matrix.ptr, st + off_mx, (size_t)A * A * 4, hipMemcpyHostToDevice, s));
-  if (nq) hip_check(hipMemcpyAsync(w->qorder.ptr, st + off_qo, nq * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  if (!p.longitems.empty()) {
-    hip_check(hipMemcpyAsync(w->longitems.ptr, st + off_li, p.longitems.size() * sizeof(PairItem),
-                             hipMemcpyHostToDevice, s));
-    hip_check(hipMemcpyAsync(w->second.ptr, st + off_se, p.second.size() * sizeof(PairItem),
-                             hipMemcpyHostToDevice, s));
-  }
+  hip_check(hipMemcpyAsync(w->inputs.ptr, st, stage_bytes, hipMemcpyHostToDevice, s));
+  uint8_t *din = (uint8_t *)w->inputs.ptr;
+  const uint8_t *d_queries = din;
+  const int64_t *d_qoff = (const int64_t *)(din + off_qoff);
+  const QueryDesc *d_qdesc = (const QueryDesc *)(din + off_qd);
+  const int32_t *d_matrix = (const int32_t *)(din + off_mx);
+  const int32_t *d_qorder = (const int32_t *)(din + off_qo);
+  const PairItem *d_items = (const PairItem *)(din + off_li);
+  const PairItem *d_second = (const PairItem *)(din + off_se);
 
   Counters *ctr = (Counters *)w->ctr.ptr;
   ProfileArgs pa;
-  pa.query = (const uint8_t *)w->queries.ptr;
-  pa.qoff = (const int64_t *)w->qoff.ptr;
-  pa.queries = (const QueryDesc *)w->qdesc.ptr;
+  pa.query = d_queries;
+  pa.qoff = d_qoff;
+  pa.queries = d_qdesc;
   pa.nqueries = (int32_t)nq;
-  pa.matrix = (const int32_t *)w->matrix.ptr;
+  pa.matrix = d_matrix;
   pa.alphabet = A;
   pa.T = p.T;
   pa.qp16 = (int16_t *)w->qp16.ptr;
@@ -576,13 +583,13 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     hip_check(hipStreamWaitEvent(w->aux, w->fork, 0));
     IntraArgs ia;
     ia.packed = (const uint8_t *)db->packed.ptr;
-    ia.items = (const PairItem *)w->longitems.ptr;
+    ia.items = d_items;
     ia.count_dev = nullptr;
     ia.count = (int32_t)p.longitems.size();
     ia.next = &ctr->intra_next;
     ia.next_narrow = &ctr->intra_narrow;
     ia.n_wide = p.n_wide;
-    ia.queries = (const QueryDesc *)w->qdesc.ptr;
+    ia.queries = d_qdesc;
     ia.qp8 = (const int8_t *)w->qp8.ptr;
     ia.goe = gap_open + gap_extend;
     ia.ge = gap_extend;
@@ -595,7 +602,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
     ia.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
     ia.error = &ctr->error;
-    ia.second = (const PairItem *)w->second.ptr;
+    ia.second = d_second;
     ia.flagged = (PairItem *)w->flagged.ptr;
     ia.flag_count = &ctr->flagged;
     ia.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
@@ -615,8 +622,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.groups = (const GroupDesc *)db->groups.ptr;
     ia.ngroups = p.ngroups_inter;
     ia.nqueries = (int32_t)nq;
-    ia.queries = (const QueryDesc *)w->qdesc.ptr;
-    ia.qorder = (const int32_t *)w->qorder.ptr;
+    ia.queries = d_qdesc;
+    ia.qorder = d_qorder;
     ia.qp16 = (const int16_t *)w->qp16.ptr;
     ia.perm = (const int32_t *)db->perm.ptr;
     ia.lens = (const int32_t *)db->lens.ptr;
@@ -648,7 +655,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.next = &ctr->recompute_next;
     ra.next_narrow = &ctr->recompute_narrow;
     ra.n_wide = 0;
-    ra.queries = (const QueryDesc *)w->qdesc.ptr;
+    ra.queries = d_qdesc;
     ra.qp8 = (const int8_t *)w->qp8.ptr;
     ra.goe = gap_open + gap_extend;
     ra.ge = gap_extend;
@@ -871,6 +878,7 @@ SW_API void sw_db_free(sw_db *db) {
     (void)hipEventDestroy(e.e0);
     (void)hipEventDestroy(e.e1);
   }
+  for (hipEvent_t e : db->spare_events) (void)hipEventDestroy(e);
   db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
   db->topk_scratch.release();
   delete db;
@@ -878,17 +886,29 @@ SW_API void sw_db_free(sw_db *db) {
 
 namespace {
 
-// Hand the workspace's recorded timing events to the database (they are read, and
-// destroyed, by sw_timing_read_kernel) and give the workspace fresh ones.
+// An event for timing: a spare one already read, else a new one (caller holds db->mu).
+hipEvent_t timing_event(sw_db *db) {
+  if (!db->spare_events.empty()) {
+    hipEvent_t e = db->spare_events.back();
+    db->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Hand the workspace's recorded timing events to the database (they are read by
+// sw_timing_read_kernel and then kept as spares) and give the workspace other ones.
 void hand_over_timing(sw_db *db, Workspace *w) {
   std::lock_guard<std::mutex> lk(db->mu);
   for (int k = 0; k < 3; ++k) {
     if (!w->timed[k]) continue;
     w->timed[k] = false;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess) continue;
-    if (hipEventCreate(&b) != hipSuccess) {
-      (void)hipEventDestroy(a);
+    hipEvent_t a = timing_event(db);
+    if (!a) continue;
+    hipEvent_t b = timing_event(db);
+    if (!b) {
+      db->spare_events.push_back(a);
       continue;
     }
     db->timing_events.push_back({k, w->t0[k], w->t1[k]});
@@ -992,7 +1012,7 @@ SW_API int sw_timing_enable(sw_db *db, int32_t enable) {
     db->timing_launches[k] = 0;
     db->timing_ms[k] = 0.0;
   }
-  for (auto &e : db->timing_events) {
+  for (auto &e : db->timing_events) {  // recorded, possibly unfinished: not reused
     (void)hipEventDestroy(e.e0);
     (void)hipEventDestroy(e.e1);
   }
@@ -1012,8 +1032,8 @@ SW_API int sw_timing_read_kernel(const sw_db *cdb, int32_t kernel, int64_t *laun
     if (hipEventElapsedTime(&ms, e.e0, e.e1) != hipSuccess) return SW_EDEVICE;
     db->timing_launches[e.kind] += 1;
     db->timing_ms[e.kind] += ms;
-    (void)hipEventDestroy(e.e0);
-    (void)hipEventDestroy(e.e1);
+    db->spare_events.push_back(e.e0);
+    db->spare_events.push_back(e.e1);
   }
   db->timing_events.clear();
   *launches = db->timing_launches[kernel];
