@@ -17,7 +17,7 @@
  * with H = E = F = 0 on row 0 and column 0, Goe = gap_open + gap_extend and
  * Ge = gap_extend.  The score of the pair is the maximum entry of H (0 if either
  * sequence is empty).  A search scores one query against every database sequence
- * (Section 4, "SW stage"); scores are exact integers.
+ * (Section 4, the alignment stage); scores are exact integers.
  */
 #ifndef SWMI_H
 #define SWMI_H
@@ -47,8 +47,8 @@ extern "C" {
 typedef struct sw_db sw_db;
 
 /*
- * sw_db_load -- pre-processing stage (Section 4, step 1; the grouping of Section 4
- * before "Multiple Parallelism Levels"): sort the sequences by length, split off the
+ * sw_db_load -- pre-processing stage (Section 4, first stage, and its grouping of
+ * sequences by lane count): sort the sequences by length, split off the
  * very long ones, group the rest 64 to a group, pad each group to its longest member
  * with a reserved padding code and copy the packed, interleaved result to HBM, where
  * it stays resident for any number of searches.
@@ -91,7 +91,7 @@ void sw_db_free(sw_db *db);
  * host threads on one handle (the database is read-only; each call takes its own
  * device workspace).  Errors: SW_ENODB, SW_EINVAL, SW_ENOMEM, SW_EDEVICE (also when a
  * bounded wait between the workgroups of a split pair gave up; see
- * SW_KNOB_SPIN_LIMIT).  After an error the contents of scores_out are unspecified.
+ * SW_KNOB_SPIN_LIMIT); scores_out is then left untouched.
  */
 int sw_search(const sw_db *db, const uint8_t *query, int32_t query_len,
               const int32_t *matrix, int32_t gap_open, int32_t gap_extend,

@@ -935,16 +935,21 @@ int run_search(const sw_db *cdb, const uint8_t *queries, const int64_t *qoff, in
     if (nscores > 0) {
       enqueue_search(db, w, queries, qoff, nq, matrix, gap_open, gap_extend, scores, s);
     }
-    hip_check(hipEventRecord(w->done, s));
     if (host_out) {
-      if (nscores > 0)
-        hip_check(hipMemcpyAsync(host_out, scores, nscores * 4, hipMemcpyDeviceToHost, s));
+      // the error flag first, so that a failed search leaves scores_out untouched
       int32_t err = 0;
-      if (nscores > 0 && w->ctr.ptr)
+      if (nscores > 0 && w->ctr.ptr) {
         hip_check(hipMemcpyAsync(&err, &((Counters *)w->ctr.ptr)->error, 4,
                                  hipMemcpyDeviceToHost, s));
-      hip_check(hipStreamSynchronize(s));
+        hip_check(hipStreamSynchronize(s));
+      }
       if (err) throw HipFail{hipErrorLaunchTimeOut};
+      if (nscores > 0)
+        hip_check(hipMemcpyAsync(host_out, scores, nscores * 4, hipMemcpyDeviceToHost, s));
+      hip_check(hipEventRecord(w->done, s));
+      hip_check(hipStreamSynchronize(s));
+    } else {
+      hip_check(hipEventRecord(w->done, s));
     }
     hand_over_timing(db, w);
     release(db, w);

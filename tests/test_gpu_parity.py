@@ -511,9 +511,14 @@ def test_segment_wait_that_gives_up_fails_the_search():
         with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
             swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, 1)
             _say("search with a one-poll segment wait")
-            with pytest.raises(swmi.SwError) as e:
-                h.search(q, synth.BLOSUM62, 10, 2)
-            assert e.value.code == swmi.SW_EDEVICE
+            out = np.full(db.n_seqs, -7, dtype=np.int32)
+            qq = np.ascontiguousarray(q, dtype=np.uint8)
+            sm = np.ascontiguousarray(synth.BLOSUM62, dtype=np.int32)
+            rc = swmi.lib().sw_search(h.handle, qq.ctypes.data_as(swmi._u8p), len(qq),
+                                      sm.ctypes.data_as(swmi._i32p), 10, 2,
+                                      out.ctypes.data_as(swmi._i32p))
+            assert rc == swmi.SW_EDEVICE
+            assert (out == -7).all()  # a failed search leaves the output untouched
             swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, 0)
             _say("search with the default limit")
             got = h.search(q, synth.BLOSUM62, 10, 2)
