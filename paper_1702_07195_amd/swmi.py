@@ -20,6 +20,11 @@ SW_ENOMEM = -2
 SW_EDEVICE = -3
 SW_ENODB = -4
 
+SW_MAX_ALPHABET = 31
+SW_MAX_QUERY_LEN = 1 << 24
+SW_MAX_GOE = 16383
+SW_MAX_ABS_SCORE = 127
+
 SW_KNOB_INTRA_MIN_LEN = 1
 SW_KNOB_RECOMPUTE_ALL = 2
 SW_KNOB_STRIP_ROWS = 3

@@ -148,3 +148,13 @@ def test_spin_limit_knob_range():
         assert swmi.get_knob(swmi.SW_KNOB_SPIN_LIMIT) == 1
     finally:
         swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, old)
+
+
+def test_binding_constants_match_the_header():
+    # every #define of include/swmi.h has the same value in the binding
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(SW_[A-Z0-9_]+)\s+\(?(-?[0-9]+(?:\s*<<\s*[0-9]+)?)\)?", text))
+    assert len(defs) > 20
+    for name, expr in defs.items():
+        assert hasattr(swmi, name), name
+        assert getattr(swmi, name) == eval(expr), name  # literal integers and shifts only

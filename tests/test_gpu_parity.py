@@ -526,3 +526,46 @@ def test_segment_wait_that_gives_up_fails_the_search():
         for k, v in zip(knobs, old):
             swmi.set_knob(k, v)
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
+
+
+def test_maximum_query_length():
+    # The longest query the boundary accepts (2^24 residues) against a few short
+    # sequences, through both kernels (1.1 GB of inter-task profile, 16,384 intra-task
+    # bands split across workgroups); one residue more is rejected.
+    rng = np.random.Generator(np.random.PCG64(2024))
+    m = swmi.SW_MAX_QUERY_LEN
+    q = synth.residues(rng, m)
+    db = synth.db_from_seqs([synth.residues(rng, n) for n in (1, 7, 40)])
+    want = oracle.search(q, db.residues, db.offsets, synth.BLOSUM62, 10, 2)
+    old = swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN)
+    try:
+        with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+            for route in (1 << 30, 1):
+                swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, route)
+                _say(f"maximum query length, route {route}")
+                assert np.array_equal(h.search(q, synth.BLOSUM62, 10, 2), want), route
+            with pytest.raises(swmi.SwError) as e:
+                h.search(np.zeros(m + 1, np.uint8), synth.BLOSUM62, 10, 2)
+            assert e.value.code == swmi.SW_EINVAL
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
+
+
+@pytest.mark.parametrize("route", [0, 1])
+def test_largest_alphabet(route):
+    # 31 codes (the most the boundary accepts; code 31 is the padding code)
+    rng = np.random.Generator(np.random.PCG64(3131 + route))
+    sm = synth.random_matrix(rng, 31, -12, 12)
+    lengths = synth.lognormal_lengths(rng, 300, 200, 0.9, 0, 2500)
+    residues = rng.integers(0, 31, size=int(lengths.sum()), dtype=np.uint8)
+    db = synth.SeqDB(residues, np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64))
+    q = rng.integers(0, 31, size=700, dtype=np.uint8)
+    old = swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN)
+    try:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, route)
+        with swmi.sw_db_load(db.residues, db.offsets, 31) as h:
+            _say(f"alphabet 31, route {route}")
+            got = h.search(q, sm, 7, 3)
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
+    assert np.array_equal(got, oracle.search(q, db.residues, db.offsets, sm, 7, 3))
