@@ -71,7 +71,8 @@ struct HostBuf {
 struct Workspace {
   hipStream_t own = nullptr;    // stream used by the blocking calls
   hipStream_t aux = nullptr;    // second stream for the long-sequence kernel
-  hipEvent_t done = nullptr, fork = nullptr, join = nullptr;
+  hipStream_t crit = nullptr;   // third stream for the critical pairs (finer bands)
+  hipEvent_t done = nullptr, fork = nullptr, join = nullptr, join_crit = nullptr;
   hipEvent_t t0[3] = {}, t1[3] = {};  // kernel timing: inter-task, long intra, recompute
   bool timed[3] = {false, false, false};
   bool busy = false;
@@ -151,16 +152,41 @@ void grow_host(HostBuf &b, size_t bytes) {
 void destroy_workspace(Workspace *w) {
   if (w->own) (void)hipStreamSynchronize(w->own);
   if (w->aux) (void)hipStreamSynchronize(w->aux);
+  if (w->crit) (void)hipStreamSynchronize(w->crit);
   for (DevBuf *b : {&w->inputs, &w->qp16, &w->qp8, &w->ctr, &w->flagged, &w->bnd16, &w->bnd32,
                     &w->xbnd, &w->xprog, &w->scores})
     b->release();
   w->staging.release();
-  for (hipEvent_t e : {w->done, w->fork, w->join, w->t0[0], w->t1[0], w->t0[1], w->t1[1],
+  for (hipEvent_t e : {w->done, w->fork, w->join, w->join_crit, w->t0[0], w->t1[0], w->t0[1], w->t1[1],
                        w->t0[2], w->t1[2]})
     if (e) (void)hipEventDestroy(e);
   if (w->own) (void)hipStreamDestroy(w->own);
   if (w->aux) (void)hipStreamDestroy(w->aux);
+  if (w->crit) (void)hipStreamDestroy(w->crit);
   delete w;
+}
+
+// A workspace with its streams and events (buffers grow on first use).
+Workspace *new_workspace() {
+  Workspace *w = new Workspace();
+  try {
+    hip_check(hipStreamCreateWithFlags(&w->own, hipStreamNonBlocking));
+    hip_check(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
+    hip_check(hipStreamCreateWithFlags(&w->crit, hipStreamNonBlocking));
+    hip_check(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
+    hip_check(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
+    hip_check(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
+    hip_check(hipEventCreateWithFlags(&w->join_crit, hipEventDisableTiming));
+    for (int k = 0; k < 3; ++k) {
+      hip_check(hipEventCreate(&w->t0[k]));
+      hip_check(hipEventCreate(&w->t1[k]));
+    }
+    hip_check(hipEventRecord(w->done, w->own));
+  } catch (...) {
+    destroy_workspace(w);
+    throw;
+  }
+  return w;
 }
 
 Workspace *acquire(sw_db *db) {
@@ -188,22 +214,7 @@ Workspace *acquire(sw_db *db) {
       return oldest;
     }
   }
-  Workspace *w = new Workspace();
-  try {
-    hip_check(hipStreamCreateWithFlags(&w->own, hipStreamNonBlocking));
-    hip_check(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
-    hip_check(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
-    hip_check(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-    hip_check(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
-    for (int k = 0; k < 3; ++k) {
-      hip_check(hipEventCreate(&w->t0[k]));
-      hip_check(hipEventCreate(&w->t1[k]));
-    }
-    hip_check(hipEventRecord(w->done, w->own));
-  } catch (...) {
-    destroy_workspace(w);
-    throw;
-  }
+  Workspace *w = new_workspace();
   w->busy = true;
   w->last_use = ++db->pool_uses;
   db->pool.push_back(w);
@@ -293,6 +304,8 @@ struct Plan {
   std::vector<QueryDesc> qd;
   std::vector<PairItem> longitems;
   std::vector<PairItem> second;  // per long item: its second pair (two-pair items) or len -1
+  std::vector<PairItem> crititems;  // segments of critical pairs, in bands of 64 * R_CRIT rows
+  int grid_crit = 0;
   int64_t qp16_elems = 0, qp8_elems = 0;
 };
 
@@ -459,6 +472,39 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       emit(it, pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
       continue;
     }
+    // A pair whose full pipeline would outlast the search sets its critical path; with
+    // bands of 64 * kCritR rows a step takes 7.5 kCritR + 14 instructions instead of
+    // 7.5 R + 14, over more, shorter bands, so such pairs get a launch of their own with
+    // that height (4-band segments, one wave per SIMD) when it shortens their pipeline.
+    if (S == s4 && p.R > kCritR && g_knob_intra_rows.load() == 0 && cap == 0 &&
+        piped * 64 * 0.5 * t_step > 0.5 * t_search) {  // still critical with a SIMD per wave
+      const int32_t nbc = (int32_t)((lens[it.query] + 64 * kCritR - 1) / (64 * kCritR));
+      const double piped_c = (double)(nc + (int64_t)kIntraLag * (nbc - 1));
+      const double step_c = (7.5 * kCritR + 14.0) / (7.5 * p.R + 14.0);
+      if (piped_c * step_c < piped) {
+        const int32_t Sc = (nbc + 3) / 4;
+        const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
+        for (int32_t j = 0; j < Sc; ++j) {
+          PairItem sg = it;
+          sg.band0 = (int32_t)((int64_t)nbc * j / Sc);
+          sg.band1 = (int32_t)((int64_t)nbc * (j + 1) / Sc);
+          sg.segment = j;
+          sg.nsegments = Sc;
+          if (j > 0) {
+            sg.xin = p.xbnd_elems - npad;
+            sg.prog_in = p.nprog - 1;
+          }
+          if (j + 1 < Sc) {
+            sg.xout = p.xbnd_elems;
+            sg.prog_out = p.nprog;
+            p.xbnd_elems += npad;
+            p.nprog += 1;
+          }
+          p.crititems.push_back(sg);
+        }
+        continue;
+      }
+    }
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
     for (int32_t j = 0; j < S; ++j) {
       PairItem sg = it;
@@ -495,13 +541,18 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   // workgroup per CU measured slower and erratic on MI355X (86 ms vs 103-115 ms for a
   // 35000-residue query over the long-sequence mix), not faster.
   const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
+  // The critical pairs' launch (at most half of the CUs) is enqueued first and gets its
+  // CUs first; the main launch still asks for one workgroup per CU, and the ones that
+  // find no free CU start as the critical workgroups finish.
+  p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(),
+                                       std::max(1, db->num_cu / 2));
   p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + kIntraWaves - 1) / kIntraWaves,
                                        (int64_t)db->num_cu);
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
   // and nothing is launched when no kernel can append to it
   const bool may_flag = (nitems16 > 0 && p.grid16 > 0) || p.nduos > 0;
   p.grid_re = (may_flag && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
-  const int grid32 = p.grid_long + p.grid_re;
+  const int grid32 = p.grid_long + p.grid_re + p.grid_crit;
 
   // workspace sizes
   const int64_t qbytes = qoff[nq];
@@ -514,7 +565,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   {
     size_t need = (size_t)qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
                   (size_t)p.qp16_elems * 2 + (size_t)p.qp8_elems + sizeof(Counters) +
-                  need_flagged * sizeof(PairItem) + 2 * p.longitems.size() * sizeof(PairItem) +
+                  need_flagged * sizeof(PairItem) +
+                  (2 * p.longitems.size() + p.crititems.size()) * sizeof(PairItem) +
                   (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8 +
                   (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
     if (cap_mb > 0 && (int64_t)(std::max(need, w->total_bytes()) >> 20) > cap_mb)
@@ -528,7 +580,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const size_t off_qo = off_mx + (((size_t)A * A * 4 + 63) & ~size_t(63));
   const size_t off_li = off_qo + ((nq * sizeof(int32_t) + 63) & ~size_t(63));
   const size_t off_se = off_li + ((p.longitems.size() * sizeof(PairItem) + 63) & ~size_t(63));
-  const size_t stage_bytes = off_se + p.second.size() * sizeof(PairItem) + 64;
+  const size_t off_cr = off_se + ((p.second.size() * sizeof(PairItem) + 63) & ~size_t(63));
+  const size_t stage_bytes = off_cr + p.crititems.size() * sizeof(PairItem) + 64;
   grow(w->inputs, stage_bytes);
   grow(w->qp16, (size_t)std::max<int64_t>(8, p.qp16_elems) * 2);
   grow(w->qp8, (size_t)std::max<int64_t>(16, p.qp8_elems));
@@ -551,6 +604,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     std::memcpy(st + off_li, p.longitems.data(), p.longitems.size() * sizeof(PairItem));
     std::memcpy(st + off_se, p.second.data(), p.second.size() * sizeof(PairItem));
   }
+  if (!p.crititems.empty())
+    std::memcpy(st + off_cr, p.crititems.data(), p.crititems.size() * sizeof(PairItem));
   hip_check(hipMemcpyAsync(w->inputs.ptr, st, stage_bytes, hipMemcpyHostToDevice, s));
   uint8_t *din = (uint8_t *)w->inputs.ptr;
   const uint8_t *d_queries = din;
@@ -560,6 +615,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const int32_t *d_qorder = (const int32_t *)(din + off_qo);
   const PairItem *d_items = (const PairItem *)(din + off_li);
   const PairItem *d_second = (const PairItem *)(din + off_se);
+  const PairItem *d_crit = (const PairItem *)(din + off_cr);
 
   Counters *ctr = (Counters *)w->ctr.ptr;
   ProfileArgs pa;
@@ -577,9 +633,41 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   pa.nzero = 2 * (int64_t)std::max<int32_t>(1, p.nprog);
   if (nq > 0) hip_check(launch_profile(pa, s));
 
+  if (p.grid_long > 0 || p.grid_crit > 0) hip_check(hipEventRecord(w->fork, s));
+  // critical pairs first (their workgroups are dispatched before the main launch's),
+  // on a stream of their own, with finer bands
+  if (p.grid_crit > 0) {
+    hip_check(hipStreamWaitEvent(w->crit, w->fork, 0));
+    IntraArgs ca;
+    ca.packed = (const uint8_t *)db->packed.ptr;
+    ca.items = d_crit;
+    ca.count_dev = nullptr;
+    ca.count = (int32_t)p.crititems.size();
+    ca.next = &ctr->crit_next;
+    ca.next_narrow = &ctr->crit_narrow;
+    ca.n_wide = ca.count;
+    ca.queries = d_qdesc;
+    ca.qp8 = (const int8_t *)w->qp8.ptr;
+    ca.goe = gap_open + gap_extend;
+    ca.ge = gap_extend;
+    ca.scores = scores_dev;
+    ca.bnd = (int2 *)w->bnd32.ptr + (size_t)(p.grid_long + p.grid_re) * bnd32_slot;
+    ca.bnd_slot_elems = (int64_t)bnd32_slot;
+    ca.bnd_stride = bnd32_stride;
+    ca.xbnd = (int2 *)w->xbnd.ptr;
+    ca.xprog = (int32_t *)w->xprog.ptr;
+    ca.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
+    ca.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
+    ca.error = &ctr->error;
+    ca.second = nullptr;
+    ca.flagged = nullptr;
+    ca.flag_count = nullptr;
+    ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
+    hip_check(launch_intra32(ca, kCritR, kIntraWaves, p.grid_crit, w->crit));
+    hip_check(hipEventRecord(w->join_crit, w->crit));
+  }
   // long sequences: intra-task kernel on the auxiliary stream, concurrent with the sweep
   if (p.grid_long > 0) {
-    hip_check(hipEventRecord(w->fork, s));
     hip_check(hipStreamWaitEvent(w->aux, w->fork, 0));
     IntraArgs ia;
     ia.packed = (const uint8_t *)db->packed.ptr;
@@ -647,6 +735,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     // the device), after the long-pair kernel; it uses the boundary slots after that
     // kernel's
     if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
+    if (p.grid_crit > 0) hip_check(hipStreamWaitEvent(s, w->join_crit, 0));
     IntraArgs ra;
     ra.packed = (const uint8_t *)db->packed.ptr;
     ra.items = (const PairItem *)w->flagged.ptr;
@@ -680,6 +769,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     }
   }
   if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
+  if (p.grid_crit > 0) hip_check(hipStreamWaitEvent(s, w->join_crit, 0));
 }
 
 int64_t total_of(const int64_t *offsets, int64_t n) { return offsets[n]; }
@@ -1082,19 +1172,15 @@ SW_API int sw_plan_create(const sw_db *cdb, const uint8_t *queries, const int64_
   hipStream_t cap = nullptr;
   try {
     hip_check(hipSetDevice(db->device));
-    plan->w = new Workspace();
+    plan->w = new_workspace();
     Workspace *w = plan->w;
-    hip_check(hipStreamCreateWithFlags(&w->own, hipStreamNonBlocking));
-    hip_check(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
-    hip_check(hipEventCreateWithFlags(&w->done, hipEventDisableTiming));
-    hip_check(hipEventCreateWithFlags(&w->fork, hipEventDisableTiming));
-    hip_check(hipEventCreateWithFlags(&w->join, hipEventDisableTiming));
     if (db->n_seqs > 0) {
       // eager run: allocates and fills every buffer
       enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
                      scores_dev, w->own, false);
       hip_check(hipStreamSynchronize(w->own));
       hip_check(hipStreamSynchronize(w->aux));
+      hip_check(hipStreamSynchronize(w->crit));
       // capture the same launch sequence
       hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
       hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -1355,12 +1441,7 @@ SW_API int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open,
   try {
     hip_check(hipSetDevice(db->device));
     for (ServerSlot &sl : sv->slots) {
-      sl.w = new Workspace();
-      hip_check(hipStreamCreateWithFlags(&sl.w->own, hipStreamNonBlocking));
-      hip_check(hipStreamCreateWithFlags(&sl.w->aux, hipStreamNonBlocking));
-      hip_check(hipEventCreateWithFlags(&sl.w->done, hipEventDisableTiming));
-      hip_check(hipEventCreateWithFlags(&sl.w->fork, hipEventDisableTiming));
-      hip_check(hipEventCreateWithFlags(&sl.w->join, hipEventDisableTiming));
+      sl.w = new_workspace();
       hip_check(hipEventCreateWithFlags(&sl.finished, hipEventDisableTiming));
     }
   } catch (const HipFail &f) {

@@ -66,6 +66,8 @@ struct Counters {
   int32_t intra_narrow;   // next narrow intra-task item (long list)
   int32_t recompute_narrow;  // next narrow intra-task item (recompute list)
   int32_t error;          // set if a bounded wait between segments ran out
+  int32_t crit_next;      // next wide item of the critical-pair list
+  int32_t crit_narrow;    // (unused: that list has no narrow items)
   int32_t pad;
 };
 
@@ -173,6 +175,7 @@ int inter16_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
 constexpr int kIntraBuf = 4;     // profile-row buffers per lane (prefetch distance + 1)
 constexpr int kIntraWaves = 8;
+constexpr int kCritR = 8;        // rows per lane of the critical-pair launch
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
 constexpr int kSpinLimit = 1 << 24;  // default polls before a wait between segments gives up
 
