@@ -16,8 +16,10 @@
 //               pre-processing: sort by length, group by lane count, pad with dummies).
 //   k_inter16   inter-task DP (Sections 1 and 4.1) in packed int16 with saturation
 //               (Section 4.2): one sequence per lane, two DP cells per 32-bit lane.
-//   k_intra32   intra-task DP (Section 1) for very long sequences and for the exact
-//               recompute of saturated alignments (Section 4.2), int32, anti-diagonal.
+//   k_intra32   intra-task DP (Section 1), anti-diagonal, for very long sequences, for
+//               every pair of a database too small to fill the GPU, and for the exact
+//               recompute of saturated alignments (Section 4.2): int32, or two pairs
+//               per wave in packed int16 with the same saturation rule.
 #include "swmi_internal.h"
 
 namespace swmi {
