@@ -270,6 +270,10 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          2^24).  A wait that gives up marks the search failed (a
  *                          blocking search returns SW_EDEVICE) and every kernel still
  *                          runs to its end; tiny values exist to test that path.
+ *   SW_KNOB_QUERY_PAIRS    1 (default): a search of two or more queries runs the
+ *                          inter-task DP two queries per lane (the queries paired
+ *                          longest first, both in packed int16 at the same database
+ *                          column); 0: one query per lane.  Scores are the same.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -282,6 +286,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_INTRA_ROWS     9
 #define SW_KNOB_INTRA_PAIRS    10
 #define SW_KNOB_SPIN_LIMIT     11
+#define SW_KNOB_QUERY_PAIRS    12
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

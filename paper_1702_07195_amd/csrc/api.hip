@@ -36,6 +36,7 @@ std::atomic<int64_t> g_knob_max_segments{0};
 std::atomic<int64_t> g_knob_intra_rows{0};
 std::atomic<int64_t> g_knob_intra_pairs{1};
 std::atomic<int64_t> g_knob_spin_limit{0};
+std::atomic<int64_t> g_knob_query_pairs{1};
 
 struct HipFail {
   hipError_t err;
@@ -307,6 +308,8 @@ struct Plan {
   std::vector<PairItem> crititems;  // segments of critical pairs, in bands of 64 * R_CRIT rows
   int grid_crit = 0;
   int64_t qp16_elems = 0, qp8_elems = 0;
+  std::vector<QueryPair> pairs;  // two-query inter-task kernel (empty: k_inter16)
+  int64_t qp2_elems = 0;         // dwords of the pair profiles
 };
 
 // Enqueue one (possibly batched) search on `s`.  Queries are host memory; scores go to
@@ -324,7 +327,26 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   std::iota(qorder.begin(), qorder.end(), 0);
   std::stable_sort(qorder.begin(), qorder.end(),
                    [&](int32_t x, int32_t y) { return lens[x] > lens[y]; });
-  p.T = choose_T(lens);
+  // A batched search pairs its queries (longest first) in the two-query inter-task
+  // kernel, whose strips hold T rows of both; the strip height is chosen on the padded
+  // rows of the pairs.
+  const bool q2 = g_knob_query_pairs.load() != 0 && nq >= 2;
+  if (q2) {
+    std::vector<int64_t> pair_rows;
+    for (int64_t k = 0; k < nq; k += 2) {
+      QueryPair qp;
+      qp.qa = qorder[(size_t)k];
+      qp.qb = k + 1 < nq ? qorder[(size_t)k + 1] : -1;
+      qp.qp2 = 0;
+      qp.nstrips = 0;
+      qp.pad = 0;
+      p.pairs.push_back(qp);
+      pair_rows.push_back(2 * lens[(size_t)qp.qa]);  // ceil(2m / 2T) * 2T = 2T ceil(m / T)
+    }
+    p.T = choose_T(pair_rows);
+  } else {
+    p.T = choose_T(lens);
+  }
   p.R = choose_R(lens);
   p.nbandsR.resize((size_t)nq);
   for (int64_t q = 0; q < nq; ++q)
@@ -334,7 +356,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   for (int64_t q = 0; q < nq; ++q) {
     QueryDesc &d = p.qd[q];
     d.m = (int32_t)lens[q];
-    d.nstrips = (int32_t)((lens[q] + 2 * p.T - 1) / (2 * p.T));
+    d.nstrips = q2 ? 0 : (int32_t)((lens[q] + 2 * p.T - 1) / (2 * p.T));
     d.nbands = (int32_t)((lens[q] + band - 1) / band);
     d.mrows = d.nbands * band;
     d.qp16 = p.qp16_elems;
@@ -343,17 +365,29 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     p.qp16_elems += (int64_t)d.nstrips * kCodes * 2 * p.T;
     p.qp8_elems += (int64_t)kCodes * d.mrows;
   }
+  for (QueryPair &qp : p.pairs) {
+    qp.nstrips = (int32_t)((lens[(size_t)qp.qa] + p.T - 1) / p.T);
+    qp.qp2 = p.qp2_elems;
+    p.qp2_elems += (int64_t)qp.nstrips * kCodes * p.T;
+  }
+  const int64_t nunits = q2 ? (int64_t)p.pairs.size() : nq;  // inter-task items per group
   // launch geometry of the inter-task kernel
   int per_cu = (int)g_knob_grid_waves.load();
-  if (per_cu <= 0) per_cu = std::max(1, inter16_max_blocks_per_cu(p.T));
+  if (per_cu <= 0)
+    per_cu = std::max(1, q2 ? inter16q2_max_blocks_per_cu(p.T) : inter16_max_blocks_per_cu(p.T));
   const int64_t lanes = (int64_t)per_cu * db->num_cu * 64;
 
   // Route the longest groups to the intra-task kernel.  One lane runs a whole alignment
   // in the inter-task kernel, so a group of length L costs about L * m on one wave; keep
   // L below twice the average number of residues per lane (weighted by the number of
   // equally long queries), else that wave becomes the critical path.
+  // (paired queries: a lane runs both queries of a pair at once, so a pair counts once)
   int64_t sum_m = 0, max_m = 1;
-  for (int64_t q = 0; q < nq; ++q) { sum_m += lens[q]; max_m = std::max(max_m, lens[q]); }
+  for (int64_t q = 0; q < nq; ++q) max_m = std::max(max_m, lens[q]);
+  if (q2)
+    for (const QueryPair &qp : p.pairs) sum_m += lens[(size_t)qp.qa];
+  else
+    for (int64_t q = 0; q < nq; ++q) sum_m += lens[q];
   const double weight = (double)sum_m / (double)max_m;
   int64_t route = (int64_t)(2.0 * (double)db->short_residues * weight / (double)lanes);
   route = std::max<int64_t>(route, 64);
@@ -534,7 +568,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     emit(it, pair_all || (pair_narrow && 1.45 * single <= 0.25 * t_search));
   }
 
-  const int64_t nitems16 = (int64_t)ninter * nq;
+  const int64_t nitems16 = (int64_t)ninter * nunits;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
   // One persistent workgroup (kIntraWaves waves) per compute unit: the kernel's
   // per-step profile gathers touch one cache line per lane, and a second resident
@@ -556,7 +590,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
 
   // workspace sizes
   const int64_t qbytes = qoff[nq];
-  const size_t bnd16_slot = (size_t)db->max_ncols * 64;  // dwords
+  const size_t bnd16_slot = (size_t)db->max_ncols * 64 * (q2 ? 2 : 1);  // dwords
   const int bnd32_stride = ((db->max_len + 128 + 63) / 64) * 64;
   const size_t bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * bnd32_stride;
   // saturated pairs: any database sequence, from either kernel
@@ -564,7 +598,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const int64_t cap_mb = g_knob_mem_cap_mb.load();
   {
     size_t need = (size_t)qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
-                  (size_t)p.qp16_elems * 2 + (size_t)p.qp8_elems + sizeof(Counters) +
+                  (size_t)p.qp16_elems * 2 + (size_t)p.qp2_elems * 4 + (size_t)p.qp8_elems +
+                  sizeof(Counters) + p.pairs.size() * sizeof(QueryPair) +
                   need_flagged * sizeof(PairItem) +
                   (2 * p.longitems.size() + p.crititems.size()) * sizeof(PairItem) +
                   (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8 +
@@ -581,9 +616,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const size_t off_li = off_qo + ((nq * sizeof(int32_t) + 63) & ~size_t(63));
   const size_t off_se = off_li + ((p.longitems.size() * sizeof(PairItem) + 63) & ~size_t(63));
   const size_t off_cr = off_se + ((p.second.size() * sizeof(PairItem) + 63) & ~size_t(63));
-  const size_t stage_bytes = off_cr + p.crititems.size() * sizeof(PairItem) + 64;
+  const size_t off_pr = off_cr + ((p.crititems.size() * sizeof(PairItem) + 63) & ~size_t(63));
+  const size_t stage_bytes = off_pr + p.pairs.size() * sizeof(QueryPair) + 64;
   grow(w->inputs, stage_bytes);
-  grow(w->qp16, (size_t)std::max<int64_t>(8, p.qp16_elems) * 2);
+  // (the int16 strip profiles of k_inter16, or the pair profiles of the two-query kernel)
+  grow(w->qp16, (size_t)std::max<int64_t>({16, p.qp16_elems * 2, p.qp2_elems * 4}));
   grow(w->qp8, (size_t)std::max<int64_t>(16, p.qp8_elems));
   grow(w->ctr, sizeof(Counters));
   grow(w->flagged, need_flagged * sizeof(PairItem));
@@ -606,6 +643,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   }
   if (!p.crititems.empty())
     std::memcpy(st + off_cr, p.crititems.data(), p.crititems.size() * sizeof(PairItem));
+  if (!p.pairs.empty())
+    std::memcpy(st + off_pr, p.pairs.data(), p.pairs.size() * sizeof(QueryPair));
   hip_check(hipMemcpyAsync(w->inputs.ptr, st, stage_bytes, hipMemcpyHostToDevice, s));
   uint8_t *din = (uint8_t *)w->inputs.ptr;
   const uint8_t *d_queries = din;
@@ -616,6 +655,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const PairItem *d_items = (const PairItem *)(din + off_li);
   const PairItem *d_second = (const PairItem *)(din + off_se);
   const PairItem *d_crit = (const PairItem *)(din + off_cr);
+  const QueryPair *d_pairs = (const QueryPair *)(din + off_pr);
 
   Counters *ctr = (Counters *)w->ctr.ptr;
   ProfileArgs pa;
@@ -632,6 +672,18 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   pa.zero = (int32_t *)w->xprog.ptr;
   pa.nzero = 2 * (int64_t)std::max<int32_t>(1, p.nprog);
   if (nq > 0) hip_check(launch_profile(pa, s));
+  if (q2 && nitems16 > 0) {
+    Profile2Args pb;
+    pb.query = d_queries;
+    pb.qoff = d_qoff;
+    pb.pairs = d_pairs;
+    pb.npairs = (int32_t)p.pairs.size();
+    pb.matrix = d_matrix;
+    pb.alphabet = A;
+    pb.T = p.T;
+    pb.qp2 = (uint32_t *)w->qp16.ptr;
+    hip_check(launch_profile2(pb, s));
+  }
 
   if (p.grid_long > 0 || p.grid_crit > 0) hip_check(hipEventRecord(w->fork, s));
   // critical pairs first (their workgroups are dispatched before the main launch's),
@@ -705,28 +757,51 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   }
 
   if (nq > 0) {
-    InterArgs ia;
-    ia.packed = (const uint8_t *)db->packed.ptr;
-    ia.groups = (const GroupDesc *)db->groups.ptr;
-    ia.ngroups = p.ngroups_inter;
-    ia.nqueries = (int32_t)nq;
-    ia.queries = d_qdesc;
-    ia.qorder = d_qorder;
-    ia.qp16 = (const int16_t *)w->qp16.ptr;
-    ia.perm = (const int32_t *)db->perm.ptr;
-    ia.lens = (const int32_t *)db->lens.ptr;
-    ia.goe = gap_open + gap_extend;
-    ia.ge = gap_extend;
-    ia.scores = scores_dev;
-    ia.flagged = (PairItem *)w->flagged.ptr;
-    ia.ctr = ctr;
-    ia.bnd = (uint32_t *)w->bnd16.ptr;
-    ia.bnd_slot_words = (int64_t)bnd16_slot;
-    ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
-    ia.nitems = (int32_t)nitems16;
     const bool timed = allow_timing && db->timing.load();
     if (timed && p.grid16 > 0) hip_check(hipEventRecord(w->t0[0], s));
-    hip_check(launch_inter16(ia, p.T, p.grid16, s));
+    if (q2) {
+      Inter2Args ia;
+      ia.packed = (const uint8_t *)db->packed.ptr;
+      ia.groups = (const GroupDesc *)db->groups.ptr;
+      ia.ngroups = p.ngroups_inter;
+      ia.npairs = (int32_t)p.pairs.size();
+      ia.pairs = d_pairs;
+      ia.queries = d_qdesc;
+      ia.qp2 = (const uint32_t *)w->qp16.ptr;
+      ia.perm = (const int32_t *)db->perm.ptr;
+      ia.lens = (const int32_t *)db->lens.ptr;
+      ia.goe = gap_open + gap_extend;
+      ia.ge = gap_extend;
+      ia.scores = scores_dev;
+      ia.flagged = (PairItem *)w->flagged.ptr;
+      ia.ctr = ctr;
+      ia.bnd = (uint32_t *)w->bnd16.ptr;
+      ia.bnd_slot_words = (int64_t)bnd16_slot;
+      ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
+      ia.nitems = (int32_t)nitems16;
+      hip_check(launch_inter16q2(ia, p.T, p.grid16, s));
+    } else {
+      InterArgs ia;
+      ia.packed = (const uint8_t *)db->packed.ptr;
+      ia.groups = (const GroupDesc *)db->groups.ptr;
+      ia.ngroups = p.ngroups_inter;
+      ia.nqueries = (int32_t)nq;
+      ia.queries = d_qdesc;
+      ia.qorder = d_qorder;
+      ia.qp16 = (const int16_t *)w->qp16.ptr;
+      ia.perm = (const int32_t *)db->perm.ptr;
+      ia.lens = (const int32_t *)db->lens.ptr;
+      ia.goe = gap_open + gap_extend;
+      ia.ge = gap_extend;
+      ia.scores = scores_dev;
+      ia.flagged = (PairItem *)w->flagged.ptr;
+      ia.ctr = ctr;
+      ia.bnd = (uint32_t *)w->bnd16.ptr;
+      ia.bnd_slot_words = (int64_t)bnd16_slot;
+      ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
+      ia.nitems = (int32_t)nitems16;
+      hip_check(launch_inter16(ia, p.T, p.grid16, s));
+    }
     if (timed && p.grid16 > 0) {
       hip_check(hipEventRecord(w->t1[0], s));
       w->timed[0] = true;
@@ -809,6 +884,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       if (value < 0 || value > kSpinLimit) return SW_EINVAL;
       g_knob_spin_limit = value;
       return SW_OK;
+    case SW_KNOB_QUERY_PAIRS: if (value < 0 || value > 1) return SW_EINVAL; g_knob_query_pairs = value; return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -826,6 +902,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_INTRA_ROWS: return g_knob_intra_rows.load();
     case SW_KNOB_INTRA_PAIRS: return g_knob_intra_pairs.load();
     case SW_KNOB_SPIN_LIMIT: return g_knob_spin_limit.load();
+    case SW_KNOB_QUERY_PAIRS: return g_knob_query_pairs.load();
     default: return SW_EINVAL;
   }
 }

@@ -884,4 +884,228 @@ hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStr
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------ inter-task, two queries
+// Batched searches (several queries against the same database): the inter-task DP of
+// k_inter16 with the two int16 halves of every register given to two different queries
+// aligned against the same sequence, at the same DB column and the same strip row.  Both
+// halves then read the substitution score of the same residue code, so the profile is
+// stored pre-packed, one dword per (code, row) holding the scores of both queries
+// (k_profile2), and a cell pair is nine VALU instructions instead of ten (no byte
+// permute).  The two halves are independent alignments: each strip of T rows starts from
+// the previous strip's bottom row of the same two alignments, kept per wave in a boundary
+// buffer laid out [column][H plane, F plane][64 lanes] dwords (the H pair of the bottom
+// row, and the F pair entering the next strip).  Pairs of queries are formed longest
+// first; an odd query out gets an empty partner whose rows all score kPadScore, which
+// keeps that half at zero.  Saturation is handled per half as in k_inter16.
+
+// Pair profile of query pair p: [nstrips][32 codes][T rows] dwords, low half query qa,
+// high half query qb; rows past a query's end, codes outside the alphabet and the whole
+// high half of a pair without qb score kPadScore.
+__global__ void k_profile2(Profile2Args a) {
+  const QueryPair pr = a.pairs[blockIdx.y];
+  const int64_t n = (int64_t)pr.nstrips * kCodes * a.T;
+  const uint8_t *qa = a.query + a.qoff[pr.qa];
+  const int64_t ma = a.qoff[pr.qa + 1] - a.qoff[pr.qa];
+  const uint8_t *qb = pr.qb >= 0 ? a.query + a.qoff[pr.qb] : nullptr;
+  const int64_t mb = pr.qb >= 0 ? a.qoff[pr.qb + 1] - a.qoff[pr.qb] : 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % a.T);
+    const int code = (int)((e / a.T) % kCodes);
+    const int64_t i = (e / ((int64_t)a.T * kCodes)) * a.T + r;
+    int lo = kPadScore, hi = kPadScore;
+    if (code < a.alphabet) {
+      if (i < ma) lo = a.matrix[qa[i] * a.alphabet + code];
+      if (i < mb) hi = a.matrix[qb[i] * a.alphabet + code];
+    }
+    a.qp2[pr.qp2 + e] = ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
+  }
+}
+
+hipError_t launch_profile2(const Profile2Args &a, hipStream_t s) {
+  if (a.npairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_profile2, dim3(32, a.npairs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Writes the score of one half, or appends the pair to the recompute list when the half
+// may have saturated.
+__device__ __forceinline__ void inter2_finish(const Inter2Args &a, int q, int sc, int p,
+                                              int orig, const GroupDesc &gd, int lane) {
+  const QueryDesc qd = a.queries[q];
+  if (sc >= kSat16 || a.recompute_all) {
+    const int k = atomicAdd(&a.ctr->flagged, 1);
+    PairItem it;
+    it.base = gd.base + 4 * lane;
+    it.cstride = 256;
+    it.len = a.lens[p];
+    it.out = orig;
+    it.query = q;
+    it.band0 = 0;
+    it.band1 = qd.nbands;
+    it.xin = it.xout = -1;
+    it.prog_in = it.prog_out = -1;
+    it.segment = 0;
+    it.nsegments = 1;
+    a.flagged[k] = it;
+  } else {
+    a.scores[qd.out + orig] = sc;
+  }
+}
+
+template <int T, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_inter16q2(Inter2Args a) {
+  static_assert(T % 8 == 0, "strip height must be a multiple of 8");
+  constexpr int RS = 4 * T + 16;  // LDS bytes per code row; RS/16 is odd (fewer conflicts)
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kCodes * RS];
+  const int lane = threadIdx.x;
+  uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
+  const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
+  const uint32_t ge2 = (uint32_t)a.ge * 0x10001u;
+  __shared__ int s_item;
+
+  for (;;) {
+    __syncthreads();
+    if (lane == 0) s_item = atomicAdd(&a.ctr->inter_next, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= a.nitems) break;
+    const int g = a.ngroups - 1 - item / a.npairs;  // longest groups first
+    const QueryPair pr = a.pairs[item % a.npairs];  // pairs are ordered longest first
+    const GroupDesc gd = a.groups[g];
+    const uint32_t *qp = a.qp2 + pr.qp2;
+    const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
+    const int nchunks = gd.ncols >> 2;
+    uint32_t vmaxA = 0, vmaxB = 0;
+
+    for (int s = 0; s < pr.nstrips; ++s) {
+      __syncthreads();
+      {
+        const uint4 *src = reinterpret_cast<const uint4 *>(qp + (int64_t)s * kCodes * T);
+        constexpr int PER_CODE = T / 4;  // 16-byte pieces per code row
+        constexpr int PIECES = kCodes * PER_CODE;
+#pragma unroll
+        for (int c = lane; c < PIECES; c += 64) {
+          const int code = c / PER_CODE, k = c - code * PER_CODE;
+          *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
+        }
+      }
+      __syncthreads();
+
+      const bool first = (s == 0);
+      const bool last = (s == pr.nstrips - 1);
+      uint32_t Hs[T], Es[T];
+#pragma unroll
+      for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
+      uint32_t hprev = 0;  // boundary H pair of the column before the lead
+      uint32_t rw = res[0];
+      uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+      if (!first) {
+        h0 = bnd[0]; h1 = bnd[128]; h2 = bnd[256]; h3 = bnd[384];
+        f0 = bnd[64]; f1 = bnd[192]; f2 = bnd[320]; f3 = bnd[448];
+      }
+
+      for (int c = 0; c < nchunks; ++c) {
+        uint32_t rwn = 0, nh0 = 0, nh1 = 0, nh2 = 0, nh3 = 0, nf0 = 0, nf1 = 0, nf2 = 0, nf3 = 0;
+        if (c + 1 < nchunks) {
+          rwn = res[(int64_t)(c + 1) * 64];
+          if (!first) {
+            const uint32_t *bp = bnd + (int64_t)(c + 1) * 512;
+            nh0 = bp[0]; nh1 = bp[128]; nh2 = bp[256]; nh3 = bp[384];
+            nf0 = bp[64]; nf1 = bp[192]; nf2 = bp[320]; nf3 = bp[448];
+          }
+        }
+        const uint32_t hv[4] = {h0, h1, h2, h3}, fv[4] = {f0, f1, f2, f3};
+#pragma unroll 1
+        for (int p = 0; p < 2; ++p) {
+          const int J = c * 4 + 2 * p;  // lead column; the lag column is J + 1
+          const uint8_t *plA = lds + ((rw >> (16 * p)) & 0xffu) * RS;
+          const uint8_t *plB = lds + ((rw >> (16 * p + 8)) & 0xffu) * RS;
+          // row-0 inputs from the boundary row: diagonal H and the F entering row 0
+          const uint32_t hdA = hprev;
+          uint32_t fa = fv[2 * p];
+          const uint32_t hdB = hv[2 * p];
+          uint32_t fb = fv[2 * p + 1];
+          // The lead runs row r next to the lag's row r - 1, as in k_inter16.
+          uint32_t dA1 = hdB, dA2 = 0;
+          uint32_t smB_prev = 0;
+#pragma unroll
+          for (int r8 = 0; r8 < T; r8 += 8) {
+            const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 4 * r8);
+            const uint4 A2 = *reinterpret_cast<const uint4 *>(plA + 4 * r8 + 16);
+            const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 4 * r8);
+            const uint4 B2 = *reinterpret_cast<const uint4 *>(plB + 4 * r8 + 16);
+            const uint32_t av[8] = {A1.x, A1.y, A1.z, A1.w, A2.x, A2.y, A2.z, A2.w};
+            const uint32_t bw[8] = {B1.x, B1.y, B1.z, B1.w, B2.x, B2.y, B2.z, B2.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int r = r8 + q;
+              const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], av[q], Es[r], fa, vmaxA,
+                                        goe2, ge2);
+              if (r >= 1) Hs[r - 1] = cell16(dA2, smB_prev, Es[r - 1], fb, vmaxB, goe2, ge2);
+              dA2 = dA1;
+              dA1 = h;
+              smB_prev = bw[q];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          const uint32_t ha = dA1;
+          const uint32_t hb = cell16(dA2, smB_prev, Es[T - 1], fb, vmaxB, goe2, ge2);
+          Hs[T - 1] = hb;
+          if (!last) {
+            uint32_t *bp = bnd + (int64_t)J * 128;
+            bp[0] = ha; bp[64] = fa;
+            bp[128] = hb; bp[192] = fb;
+          }
+          hprev = hv[2 * p + 1];
+        }
+        rw = rwn;
+        h0 = nh0; h1 = nh1; h2 = nh2; h3 = nh3;
+        f0 = nf0; f1 = nf1; f2 = nf2; f3 = nf3;
+      }
+    }
+
+    const uint32_t vmax = pk_max(vmaxA, vmaxB);
+    if (lane < gd.count) {
+      const int p = gd.first + lane;
+      const int orig = a.perm[p];
+      inter2_finish(a, pr.qa, (int)(int16_t)(vmax & 0xffffu), p, orig, gd, lane);
+      if (pr.qb >= 0) inter2_finish(a, pr.qb, (int)(int16_t)(vmax >> 16), p, orig, gd, lane);
+    }
+  }
+}
+
+template <int T>
+static hipError_t launch_inter16q2_t(const Inter2Args &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_inter16q2<T, Inter16Occ<T>::wpe>), dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+int inter16q2_max_blocks_per_cu(int T) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (T) {
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<8, Inter16Occ<8>::wpe>, 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<16, Inter16Occ<16>::wpe>, 64, 0); break;
+    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<24, Inter16Occ<24>::wpe>, 64, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<32, Inter16Occ<32>::wpe>, 64, 0); break;
+    case 40: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<40, Inter16Occ<40>::wpe>, 64, 0); break;
+    default: break;
+  }
+  return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s) {
+  if (a.nitems == 0 || grid == 0) return hipSuccess;
+  switch (T) {
+    case 8: return launch_inter16q2_t<8>(a, grid, s);
+    case 16: return launch_inter16q2_t<16>(a, grid, s);
+    case 24: return launch_inter16q2_t<24>(a, grid, s);
+    case 32: return launch_inter16q2_t<32>(a, grid, s);
+    case 40: return launch_inter16q2_t<40>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace swmi

@@ -91,6 +91,34 @@ struct InterArgs {
   int32_t nitems;            // ngroups * nqueries
 };
 
+// Two queries sharing the lanes of the two-query inter-task kernel (batched searches).
+struct QueryPair {
+  int64_t qp2;       // dword offset of the pair profile in the arena
+  int32_t qa, qb;    // query indices; qb = -1 when qa has no partner
+  int32_t nstrips;   // strips of T rows (the longer query decides)
+  int32_t pad;
+};
+
+struct Inter2Args {
+  const uint8_t *packed;
+  const GroupDesc *groups;
+  int32_t ngroups;
+  int32_t npairs;
+  const QueryPair *pairs;    // longest first
+  const QueryDesc *queries;  // per query: score offset and intra-task bands (recompute)
+  const uint32_t *qp2;
+  const int32_t *perm;       // sorted position -> caller's index
+  const int32_t *lens;       // sorted position -> length
+  int32_t goe, ge;
+  int32_t *scores;
+  PairItem *flagged;
+  Counters *ctr;
+  uint32_t *bnd;             // boundary scratch, one slot per persistent wave
+  int64_t bnd_slot_words;    // dwords per slot (>= 128 * widest group's columns)
+  int32_t recompute_all;
+  int32_t nitems;            // ngroups * npairs
+};
+
 struct IntraArgs {
   const uint8_t *packed;
   const PairItem *items;     // static list (long sequences) or recompute list
@@ -133,6 +161,17 @@ struct ProfileArgs {
   int64_t nzero;
 };
 
+struct Profile2Args {
+  const uint8_t *query;      // concatenated queries
+  const int64_t *qoff;       // query offsets (nqueries + 1)
+  const QueryPair *pairs;
+  int32_t npairs;
+  const int32_t *matrix;     // alphabet x alphabet
+  int32_t alphabet;
+  int32_t T;                 // strip rows
+  uint32_t *qp2;
+};
+
 struct PackArgs {
   const uint8_t *raw;        // concatenated residues in caller order
   const int64_t *offsets;    // caller offsets
@@ -166,12 +205,15 @@ hipError_t launch_topk(const TopkArgs &a, hipStream_t s);
 hipError_t launch_profile(const ProfileArgs &a, hipStream_t s);
 hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s);
+hipError_t launch_profile2(const Profile2Args &a, hipStream_t s);
+hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s);
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s);
 
 // Strip heights compiled for the inter-task kernel, and band rows per lane for the
 // intra-task kernel.
 bool inter16_supported(int T);
 int inter16_max_blocks_per_cu(int T);
+int inter16q2_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
 constexpr int kIntraBuf = 4;     // profile-row buffers per lane (prefetch distance + 1)
 constexpr int kIntraWaves = 8;

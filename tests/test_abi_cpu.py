@@ -150,6 +150,20 @@ def test_spin_limit_knob_range():
         swmi.set_knob(swmi.SW_KNOB_SPIN_LIMIT, old)
 
 
+def test_query_pairs_knob_values():
+    old = swmi.get_knob(swmi.SW_KNOB_QUERY_PAIRS)
+    assert old == 1  # on by default
+    try:
+        for bad in (-1, 2):
+            with pytest.raises(swmi.SwError):
+                swmi.set_knob(swmi.SW_KNOB_QUERY_PAIRS, bad)
+        for good in (0, 1):
+            swmi.set_knob(swmi.SW_KNOB_QUERY_PAIRS, good)
+            assert swmi.get_knob(swmi.SW_KNOB_QUERY_PAIRS) == good
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_QUERY_PAIRS, old)
+
+
 def test_binding_constants_match_the_header():
     # every #define of include/swmi.h has the same value in the binding
     text = open(HEADER).read()
