@@ -43,25 +43,32 @@ PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_07195_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "inter16_full_scale_traffic.json")
+TRAFFIC_FILE_Q2 = os.path.join(ROOT, "profiles", "inter16q2_batched_traffic.json")
+_SECTION = b"// ------------------------------------------------------------------------ "
 
 
-def kernel_hash() -> str:
-    """Hash of the source the inter-task kernel is built from (shared helpers, profile and
-    packing kernels and k_inter16: everything before the intra-task section)."""
+def kernel_hash(section: str = "inter") -> str:
+    """Hash of the source an inter-task kernel is built from: for k_inter16 ("inter") the
+    shared helpers, profile and packing kernels and k_inter16 (everything before the
+    intra-task section); for k_inter16q2 ("inter_q2") those plus its own section."""
     with open(KERNEL_SRC, "rb") as f:
         src = f.read()
-    cut = src.find(b"// ------------------------------------------------------------------------ intra-task")
-    return hashlib.sha256(src[:cut if cut >= 0 else len(src)]).hexdigest()[:16]
+    cut = src.find(_SECTION + b"intra-task")
+    head = src[:cut if cut >= 0 else len(src)]
+    if section == "inter":
+        return hashlib.sha256(head).hexdigest()[:16]
+    q2 = src.find(_SECTION + b"inter-task, two queries")
+    return hashlib.sha256(head + (src[q2:] if q2 >= 0 else b"")).hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(path: str = TRAFFIC_FILE, section: str = "inter"):
     """HBM bytes per launch from committed PMC runs, if taken on the current kernel."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_hash():
+    if t.get("kernel_sha") != kernel_hash(section):
         return None
     return t.get("bytes_per_launch")
 
@@ -249,9 +256,17 @@ def bench_batched(args):
     h = swmi.sw_db_load(db.residues, db.offsets, len(synth.ALPHABET))
     out = torch.zeros((len(qs), db.n_seqs), dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream()
-    best, timings = autotune.tune(h, D, qs, synth.BLOSUM62, 10, 2, out,
-                                  use_cache=not args.no_tune_cache,
-                                  log=lambda m: print(m, file=sys.stderr, flush=True))
+    if args.copy_mib > 0:  # a copy of known size, to scale profiler byte counters
+        src = torch.ones(args.copy_mib << 20, dtype=torch.uint8, device="cuda:0")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
+    if args.no_tune:
+        best, timings = autotune.Config(), {}
+    else:
+        best, timings = autotune.tune(h, D, qs, synth.BLOSUM62, 10, 2, out,
+                                      use_cache=not args.no_tune_cache,
+                                      log=lambda m: print(m, file=sys.stderr, flush=True))
     variants = {}
     total_t = 0.0
     graph_scores = None
@@ -289,8 +304,13 @@ def bench_batched(args):
     result = base_result(args, gcups, total_t / 4, "i16+i32", config)
     result["per_variant_gcups"] = variants
     result["autotune_ms"] = timings
-    result["roofline"] = roofline("k_inter16 (eager batch, default configuration)", cells,
-                                  n16, ms16, True, None)
+    # (a batch runs two queries per lane in k_inter16q2 unless SW_KNOB_QUERY_PAIRS is 0;
+    # the algorithmic work per cell is the same 10 int16 operations)
+    q2 = bool(swmi.get_knob(swmi.SW_KNOB_QUERY_PAIRS))
+    kname = "k_inter16q2" if q2 else "k_inter16"
+    result["roofline"] = roofline(f"{kname} (eager batch, default configuration)", cells,
+                                  n16, ms16, True,
+                                  load_traffic(TRAFFIC_FILE_Q2, "inter_q2") if q2 else None)
     result["graph_equals_eager"] = bool(np.array_equal(graph_scores, scores_host))
     if not args.no_cpu:
         base, exact = cpu_baseline(db, qs[:8], sm, 10, 2, list(scores_host[:8]),
@@ -412,6 +432,8 @@ def main():
     ap.add_argument("--cpu-cells", type=float, default=2.5e10,
                     help="oracle sample size in cells (about 10-30 s on the host)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched: skip the autotuner (automatic strip height and grid)")
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="batched: re-run the autotuner instead of reading its cache")
     ap.add_argument("--copy-mib", type=int, default=0,
