@@ -233,19 +233,21 @@ void k_inter16(InterArgs a) {
             n0 = bp[0]; n1 = bp[64]; n2 = bp[128]; n3 = bp[192];
           }
         }
-        const uint32_t bv[4] = {b0, b1, b2, b3};
+        // the pair's codes (J, J + 1) are the low two bytes of cw, those of (J - 2, J - 1)
+        // the low two bytes of pw; boundary words of (J, J + 1) are bJ, bJ1
+        uint32_t cw = rw, pw = rwp >> 16;
+        uint32_t bJ = b0, bJ1 = b1;
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
           const int J = c * 4 + 2 * p;  // lead column (low half); lag is J + 1
-          const uint32_t dJ = (rw >> (16 * p)) & 0xffu;
-          const uint32_t dJ1 = (rw >> (16 * p + 8)) & 0xffu;
-          const uint32_t dJm2 = p == 0 ? (rwp >> 16) & 0xffu : rw & 0xffu;
-          const uint32_t dJm1 = p == 0 ? (rwp >> 24) : (rw >> 8) & 0xffu;
+          const uint32_t dJ = cw & 0xffu;
+          const uint32_t dJ1 = (cw >> 8) & 0xffu;
+          const uint32_t dJm2 = pw & 0xffu;
+          const uint32_t dJm1 = (pw >> 8) & 0xffu;
           const uint8_t *plA = lds + dJ * RS;               // lead low rows, column J
           const uint8_t *phA = lds + dJm2 * RS + 2 * T;     // lead high rows, column J - 2
           const uint8_t *plB = lds + dJ1 * RS;              // lag low rows, column J + 1
           const uint8_t *phB = lds + dJm1 * RS + 2 * T;     // lag high rows, column J - 1
-          const uint32_t bJ = bv[2 * p], bJ1 = bv[2 * p + 1];
           // row-0 inputs: low half from the boundary row, high half from the low rows
           uint32_t hdA = pack_lo(hbnd_prev, hBB);  // H(row-1, col-1)
           uint32_t fa = pack_hl(bJ, fA);           // F entering row 0
@@ -296,6 +298,10 @@ void k_inter16(InterArgs a) {
           hA = ha; fA = fa;
           hB = hb; fB = fb;
           hbnd_prev = bJ1;
+          pw = cw;
+          cw >>= 16;
+          bJ = b2;
+          bJ1 = b3;
         }
         rwp = rw;
         rw = rwn; b0 = n0; b1 = n1; b2 = n2; b3 = n3;
@@ -1016,17 +1022,20 @@ void k_inter16q2(Inter2Args a) {
             nf0 = bp[64]; nf1 = bp[192]; nf2 = bp[320]; nf3 = bp[448];
           }
         }
-        const uint32_t hv[4] = {h0, h1, h2, h3}, fv[4] = {f0, f1, f2, f3};
+        // codes of the pair's columns (J, J + 1) in the low two bytes of cw; boundary
+        // words of those columns in hJ, hJ1 (H pairs) and fJ, fJ1 (F pairs)
+        uint32_t cw = rw;
+        uint32_t hJ = h0, hJ1 = h1, fJ = f0, fJ1 = f1;
 #pragma unroll 1
         for (int p = 0; p < 2; ++p) {
           const int J = c * 4 + 2 * p;  // lead column; the lag column is J + 1
-          const uint8_t *plA = lds + ((rw >> (16 * p)) & 0xffu) * RS;
-          const uint8_t *plB = lds + ((rw >> (16 * p + 8)) & 0xffu) * RS;
+          const uint8_t *plA = lds + (cw & 0xffu) * RS;
+          const uint8_t *plB = lds + ((cw >> 8) & 0xffu) * RS;
           // row-0 inputs from the boundary row: diagonal H and the F entering row 0
           const uint32_t hdA = hprev;
-          uint32_t fa = fv[2 * p];
-          const uint32_t hdB = hv[2 * p];
-          uint32_t fb = fv[2 * p + 1];
+          uint32_t fa = fJ;
+          const uint32_t hdB = hJ;
+          uint32_t fb = fJ1;
           // The lead runs row r next to the lag's row r - 1, as in k_inter16.
           uint32_t dA1 = hdB, dA2 = 0;
           uint32_t smB_prev = 0;
@@ -1058,7 +1067,10 @@ void k_inter16q2(Inter2Args a) {
             bp[0] = ha; bp[64] = fa;
             bp[128] = hb; bp[192] = fb;
           }
-          hprev = hv[2 * p + 1];
+          hprev = hJ1;
+          cw >>= 16;
+          hJ = h2; hJ1 = h3;
+          fJ = f2; fJ1 = f3;
         }
         rw = rwn;
         h0 = nh0; h1 = nh1; h2 = nh2; h3 = nh3;
