@@ -248,7 +248,9 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          kernel (read at sw_db_load; default 8192);
  *   SW_KNOB_RECOMPUTE_ALL  non-zero: recompute every score in int32 (debug; the
  *                          result must not change);
- *   SW_KNOB_STRIP_ROWS     rows per inter-task strip (0 = automatic choice);
+ *   SW_KNOB_STRIP_ROWS     rows per inter-task strip half: 8, 16, 24, 32 or 40, and 28
+ *                          for searches that pair their queries (a height a search's
+ *                          kernel lacks is chosen automatically); 0 = automatic;
  *   SW_KNOB_GRID_WAVES     persistent waves per compute unit (0 = automatic);
  *   SW_KNOB_MEM_CAP_MB     refuse workspaces beyond this many MiB (0 = no cap);
  *   SW_KNOB_ROUTE_LEN      database groups whose longest sequence exceeds this go to the

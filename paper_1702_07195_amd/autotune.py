@@ -21,7 +21,7 @@ import numpy as np
 
 from . import swmi
 
-STRIP_HEIGHTS = (16, 24, 32, 40)
+STRIP_HEIGHTS = (16, 24, 28, 32, 40)  # 28: query-pair searches only
 WAVES_PER_CU = (0, 8, 12, 16)      # 0 = occupancy limit of the kernel
 BIN_WIDTHS = (0, 32, 16)           # 0 = the whole batch in one launch
 

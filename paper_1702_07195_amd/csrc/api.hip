@@ -270,15 +270,22 @@ int choose_R(const std::vector<int64_t> &lens) {
 
 // Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
 // by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
-// at three waves per SIMD and was fastest on the full-scale search).
-int choose_T(const std::vector<int64_t> &lens) {
+// at three waves per SIMD and was fastest on the full-scale search).  The pair kernel
+// (`pairs`) also has T = 28, still at three waves per SIMD and 2% faster on the batched
+// search; its per-strip row count is T, and `lens` then holds twice each pair's rows.
+int choose_T(const std::vector<int64_t> &lens, bool pairs = false) {
   const int64_t forced = g_knob_strip_rows.load();
-  if (forced > 0 && inter16_supported((int)forced)) return (int)forced;
+  if (forced > 0 && (pairs ? inter16q2_supported((int)forced) : inter16_supported((int)forced)))
+    return (int)forced;
   struct Cand { int T; double speed; };
-  const Cand cands[] = {{24, 1.0}, {40, 0.985}, {32, 0.968}, {16, 0.89}};
+  static const Cand single[] = {{24, 1.0}, {40, 0.985}, {32, 0.968}, {16, 0.89}};
+  static const Cand paired[] = {{28, 1.02}, {24, 1.0}, {40, 0.98}, {32, 0.962}, {16, 0.938}};
+  const Cand *cands = pairs ? paired : single;
+  const int ncand = pairs ? 5 : 4;
   int best = 24;
   double best_cost = 1e300;
-  for (const Cand &c : cands) {
+  for (int k = 0; k < ncand; ++k) {
+    const Cand &c = cands[k];
     double cost = 0;
     for (int64_t m : lens) cost += (double)((m + 2 * c.T - 1) / (2 * c.T)) * 2.0 * c.T;
     cost /= c.speed;
@@ -343,7 +350,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       p.pairs.push_back(qp);
       pair_rows.push_back(2 * lens[(size_t)qp.qa]);  // ceil(2m / 2T) * 2T = 2T ceil(m / T)
     }
-    p.T = choose_T(pair_rows);
+    p.T = choose_T(pair_rows, true);
   } else {
     p.T = choose_T(lens);
   }
@@ -868,7 +875,8 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
     case SW_KNOB_INTRA_MIN_LEN: if (value < 0) return SW_EINVAL; g_knob_intra_min_len = value; return SW_OK;
     case SW_KNOB_RECOMPUTE_ALL: g_knob_recompute_all = value; return SW_OK;
     case SW_KNOB_STRIP_ROWS:
-      if (value != 0 && !inter16_supported((int)value)) return SW_EINVAL;
+      if (value != 0 && !inter16_supported((int)value) && !inter16q2_supported((int)value))
+        return SW_EINVAL;
       g_knob_strip_rows = value; return SW_OK;
     case SW_KNOB_GRID_WAVES: if (value < 0 || value > 64) return SW_EINVAL; g_knob_grid_waves = value; return SW_OK;
     case SW_KNOB_MEM_CAP_MB: if (value < 0) return SW_EINVAL; g_knob_mem_cap_mb = value; return SW_OK;

@@ -962,8 +962,9 @@ __device__ __forceinline__ void inter2_finish(const Inter2Args &a, int q, int sc
 template <int T, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_inter16q2(Inter2Args a) {
-  static_assert(T % 8 == 0, "strip height must be a multiple of 8");
-  constexpr int RS = 4 * T + 16;  // LDS bytes per code row; RS/16 is odd (fewer conflicts)
+  static_assert(T % 4 == 0, "strip height must be a multiple of 4");
+  // LDS bytes per code row: an odd number of 16-byte units (fewer bank conflicts)
+  constexpr int RS = (T / 4) % 2 == 1 ? 4 * T : 4 * T + 16;
   __shared__ __attribute__((aligned(16))) uint8_t lds[kCodes * RS];
   const int lane = threadIdx.x;
   uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
@@ -1041,14 +1042,20 @@ void k_inter16q2(Inter2Args a) {
           uint32_t smB_prev = 0;
 #pragma unroll
           for (int r8 = 0; r8 < T; r8 += 8) {
+            // 8 rows per block; a height that is not a multiple of 8 ends with 4
+            const bool full = r8 + 8 <= T;
             const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 4 * r8);
-            const uint4 A2 = *reinterpret_cast<const uint4 *>(plA + 4 * r8 + 16);
             const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 4 * r8);
-            const uint4 B2 = *reinterpret_cast<const uint4 *>(plB + 4 * r8 + 16);
+            uint4 A2 = make_uint4(0, 0, 0, 0), B2 = make_uint4(0, 0, 0, 0);
+            if (full) {
+              A2 = *reinterpret_cast<const uint4 *>(plA + 4 * r8 + 16);
+              B2 = *reinterpret_cast<const uint4 *>(plB + 4 * r8 + 16);
+            }
             const uint32_t av[8] = {A1.x, A1.y, A1.z, A1.w, A2.x, A2.y, A2.z, A2.w};
             const uint32_t bw[8] = {B1.x, B1.y, B1.z, B1.w, B2.x, B2.y, B2.z, B2.w};
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
+              if (!full && q >= 4) break;
               const int r = r8 + q;
               const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], av[q], Es[r], fa, vmaxA,
                                         goe2, ge2);
@@ -1088,21 +1095,28 @@ void k_inter16q2(Inter2Args a) {
   }
 }
 
+// Minimum waves per SIMD requested for each strip height of the pair kernel (28 rows
+// still fit three waves: it has no skew registers).
+template <int T> struct Inter16q2Occ { static constexpr int wpe = T <= 8 ? 6 : (T <= 16 ? 4 : (T <= 28 ? 3 : 2)); };
+
 template <int T>
 static hipError_t launch_inter16q2_t(const Inter2Args &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_inter16q2<T, Inter16Occ<T>::wpe>), dim3(grid), dim3(64), 0, s, a);
+  hipLaunchKernelGGL((k_inter16q2<T, Inter16q2Occ<T>::wpe>), dim3(grid), dim3(64), 0, s, a);
   return hipGetLastError();
 }
+
+bool inter16q2_supported(int T) { return T == 8 || T == 16 || T == 24 || T == 28 || T == 32 || T == 40; }
 
 int inter16q2_max_blocks_per_cu(int T) {
   int n = 0;
   hipError_t e = hipErrorInvalidValue;
   switch (T) {
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<8, Inter16Occ<8>::wpe>, 64, 0); break;
-    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<16, Inter16Occ<16>::wpe>, 64, 0); break;
-    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<24, Inter16Occ<24>::wpe>, 64, 0); break;
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<32, Inter16Occ<32>::wpe>, 64, 0); break;
-    case 40: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<40, Inter16Occ<40>::wpe>, 64, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<8, Inter16q2Occ<8>::wpe>, 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<16, Inter16q2Occ<16>::wpe>, 64, 0); break;
+    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<24, Inter16q2Occ<24>::wpe>, 64, 0); break;
+    case 28: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<28, Inter16q2Occ<28>::wpe>, 64, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<32, Inter16q2Occ<32>::wpe>, 64, 0); break;
+    case 40: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_inter16q2<40, Inter16q2Occ<40>::wpe>, 64, 0); break;
     default: break;
   }
   return e == hipSuccess ? n : 0;
@@ -1114,6 +1128,7 @@ hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s)
     case 8: return launch_inter16q2_t<8>(a, grid, s);
     case 16: return launch_inter16q2_t<16>(a, grid, s);
     case 24: return launch_inter16q2_t<24>(a, grid, s);
+    case 28: return launch_inter16q2_t<28>(a, grid, s);
     case 32: return launch_inter16q2_t<32>(a, grid, s);
     case 40: return launch_inter16q2_t<40>(a, grid, s);
     default: return hipErrorInvalidValue;

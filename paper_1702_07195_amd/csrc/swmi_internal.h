@@ -213,6 +213,7 @@ hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStr
 // intra-task kernel.
 bool inter16_supported(int T);
 int inter16_max_blocks_per_cu(int T);
+bool inter16q2_supported(int T);  // strip heights of the pair kernel (also 28)
 int inter16q2_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
 constexpr int kIntraBuf = 4;     // profile-row buffers per lane (prefetch distance + 1)

@@ -86,6 +86,8 @@ def test_knobs_validate_and_round_trip():
         swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, 12)
     swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, 16)
     assert swmi.get_knob(swmi.SW_KNOB_STRIP_ROWS) == 16
+    swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, 28)  # a height of the query-pair kernel
+    assert swmi.get_knob(swmi.SW_KNOB_STRIP_ROWS) == 28
     swmi.set_knob(swmi.SW_KNOB_STRIP_ROWS, old)
     with pytest.raises(swmi.SwError):
         swmi.set_knob(99, 1)

@@ -72,7 +72,7 @@ LENGTH_SETS = {
 
 
 @pytest.mark.parametrize("name", sorted(LENGTH_SETS))
-@pytest.mark.parametrize("T", [8, 16, 24, 32, 40])
+@pytest.mark.parametrize("T", [8, 16, 24, 28, 32, 40])
 def test_pairs_equal_oracle_at_every_strip_height(pdb, phandle, name, T):
     qs = _queries(LENGTH_SETS[name], seed=len(name) * 31 + T)
     want = _want(qs, pdb, synth.BLOSUM62, 10, 2)
@@ -139,3 +139,14 @@ def test_pairs_in_a_captured_plan(pdb, phandle):
                 assert np.array_equal(out.cpu().numpy(), want), f"replay {rep}"
                 one = phandle.search(qs[rep], synth.BLOSUM62, 10, 2)
                 assert np.array_equal(one, want[rep])
+
+
+def test_pair_only_height_on_a_single_query(pdb, phandle):
+    # 28 rows exist only in the pair kernel: a single-query search with that height forced
+    # chooses its own height and stays exact
+    rng = np.random.Generator(np.random.PCG64(28))
+    q = synth.residues(rng, 210)
+    _say("single query with strip rows 28")
+    with _Knobs(strip_rows=28, route_len=1 << 30):
+        got = phandle.search(q, synth.BLOSUM62, 10, 2)
+    assert np.array_equal(got, oracle.search(q, pdb.residues, pdb.offsets, synth.BLOSUM62, 10, 2))
