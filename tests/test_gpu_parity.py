@@ -356,6 +356,20 @@ def test_split_pairs_across_workgroups(m, cap):
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
 
 
+def test_many_critical_pairs():
+    # A database of long sequences only, against a query of six 1024-row bands: every
+    # pair is on the critical path and goes to the critical-pair launch (8 rows per
+    # lane, 11 bands in three segments on workgroups of their own, 120 segments in
+    # all).  Sequences from 6,000 (in groups) to 12,000 (stored apart).
+    rng = np.random.Generator(np.random.PCG64(5478))
+    db = synth.db_from_lengths(rng, rng.integers(6000, 12000, 40))
+    q = synth.residues(rng, 5478)
+    _say("many critical pairs")
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        got = h.search(q, synth.BLOSUM62, 10, 2)
+    assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
+
+
 @pytest.fixture(scope="module")
 def mixed_db():
     # lengths from empty to 3000 (narrow pairs below 1152, wide pairs above)
