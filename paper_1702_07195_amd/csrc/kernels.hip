@@ -401,9 +401,14 @@ __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
 // row's H and F (passed one lane down after every step), the H that becomes the next
 // step's diagonal for its first row, the band-top values and residues of the current
 // 64-column chunk (lane l holds column 64k + l), and the profile rows of the next
-// kIntraBuf steps, already requested (cfar is the residue code of the last of them).
+// IntraBuf<R>::n steps, already requested (cfar is the residue code of the last of them).
 // One lane's R int8 profile rows for one code (R = 4, 8 or 16: one 4-, 8- or 16-byte
 // load).
+// Profile-row buffers per lane (prefetch distance + 1): 8 where the registers allow
+// (R <= 8; for the latency-bound long pairs of the 8-row launch the deeper prefetch was
+// about 5% faster), kIntraBuf at R = 16.
+template <int R> struct IntraBuf { static constexpr int n = R <= 8 ? 8 : kIntraBuf; };
+
 template <int R> struct RowBuf;
 template <> struct RowBuf<4> {
   uint32_t v;
@@ -426,7 +431,7 @@ struct BandLane {
   int32_t hbot, fbot, hdiag, cfar;
   int2 tq;
   int rq;
-  RowBuf<R> P[kIntraBuf];
+  RowBuf<R> P[IntraBuf<R>::n];
 };
 
 // Profile rows (int8) of one lane: `prof` points at its R rows for code 0; code c's rows
@@ -438,7 +443,7 @@ __device__ __forceinline__ void load_rows(RowBuf<R> &dst, const uint8_t *prof, u
 }
 
 // Start a band: zero state, load the first chunk's band-top values and residues, and
-// request the profile rows of steps 0 .. kIntraBuf - 2.  The code lane l needs at step s
+// request the profile rows of steps 0 .. IntraBuf<R>::n - 2.  The code lane l needs at step s
 // is that of column s - l: its left neighbour's code of step s - 1 (lane 0 takes column
 // s's residue), so codes run ahead as a chain of wave shifts.
 template <int R>
@@ -451,16 +456,16 @@ __device__ __forceinline__ void band_start(BandLane<R> &L, int lane, int n, cons
   L.tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
   L.rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
 #pragma unroll
-  for (int t = 0; t + 1 < kIntraBuf; ++t) {
+  for (int t = 0; t + 1 < IntraBuf<R>::n; ++t) {
     L.cfar = wave_shr1(L.cfar, __builtin_amdgcn_readlane(L.rq, t));
     load_rows(L.P[t], prof, pstride, L.cfar);
   }
 }
 
 // Chunk k (steps 64k .. 64k + 63) of a band sweep.  Raises vmax to the largest H
-// computed.  Step s computes with the rows in buffer s % kIntraBuf and requests those of
-// step s + kIntraBuf - 1 into the buffer step s - 1 used, so each request has
-// kIntraBuf - 1 steps to arrive; steps go in groups of kIntraBuf, so no buffer is ever
+// computed.  Step s computes with the rows in buffer s % NB (NB = IntraBuf<R>::n) and
+// requests those of step s + NB - 1 into the buffer step s - 1 used, so each request has
+// NB - 1 steps to arrive; steps go in groups of NB, so no buffer is ever
 // copied.  Each row's diagonal sum H(i-1, j-1) + SM is formed before the row above is
 // overwritten, which lets H stay in place from step to step.
 template <int R>
@@ -469,8 +474,9 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
                                            bool has_top, int2 *bot, bool has_bot,
                                            const uint8_t *resbase, int cs,
                                            const uint8_t *prof, uint32_t pstride) {
-  constexpr int D = kIntraBuf - 1;  // prefetch distance in steps
-  static_assert(64 % kIntraBuf == 0, "a chunk must hold whole groups of steps");
+  constexpr int NB = IntraBuf<R>::n;
+  constexpr int D = NB - 1;  // prefetch distance in steps
+  static_assert(64 % NB == 0, "a chunk must hold whole groups of steps");
   const int col_next = 64 * (k + 1) + lane;
   const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
   const int rq_next = col_next < n
@@ -506,10 +512,10 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
     L.fbot = f;
     if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
   };
-  for (int i = 0; i < 64; i += kIntraBuf) {
+  for (int i = 0; i < 64; i += NB) {
 #pragma unroll
-    for (int u = 0; u < kIntraBuf; ++u)
-      step(i + u, L.P[u], L.P[(u + kIntraBuf - 1) % kIntraBuf]);
+    for (int u = 0; u < NB; ++u)
+      step(i + u, L.P[u], L.P[(u + NB - 1) % NB]);
   }
   L.tq = tq_next;
   L.rq = rq_next;
@@ -528,7 +534,7 @@ struct BandLane16 {
   int cfarA, cfarB;
   int2 tq;  // band-top (H, F), both halves packed
   int rqA, rqB;
-  RowBuf<R> PA[kIntraBuf], PB[kIntraBuf];
+  RowBuf<R> PA[IntraBuf<R>::n], PB[IntraBuf<R>::n];
 };
 
 // Row r's scores for A (low half) and B (high half), sign-extended from their int8
@@ -556,7 +562,7 @@ __device__ __forceinline__ void band_start16(BandLane16<R> &L, int lane, int nA,
   L.rqA = lane < nA ? resA[(lane >> 2) * (int64_t)csA + (lane & 3)] : kPadCode;
   L.rqB = lane < nB ? resB[(lane >> 2) * (int64_t)csB + (lane & 3)] : kPadCode;
 #pragma unroll
-  for (int t = 0; t + 1 < kIntraBuf; ++t) {
+  for (int t = 0; t + 1 < IntraBuf<R>::n; ++t) {
     L.cfarA = wave_shr1(L.cfarA, __builtin_amdgcn_readlane(L.rqA, t));
     L.cfarB = wave_shr1(L.cfarB, __builtin_amdgcn_readlane(L.rqB, t));
     load_rows(L.PA[t], prof, pstride, L.cfarA);
@@ -573,7 +579,8 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
                                              bool has_bot, const uint8_t *resA, int csA,
                                              const uint8_t *resB, int csB,
                                              const uint8_t *prof, uint32_t pstride) {
-  constexpr int D = kIntraBuf - 1;
+  constexpr int NB = IntraBuf<R>::n;
+  constexpr int D = NB - 1;
   const int col_next = 64 * (k + 1) + lane;
   const int2 tq_next = (has_top && col_next < nA) ? top[col_next] : make_int2(0, 0);
   const int rqA_next = col_next < nA
@@ -613,11 +620,11 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
     if (has_bot && lane == 63 && s >= 63 && s - 63 < nA)
       bot[s - 63] = make_int2((int)h, (int)f);
   };
-  for (int i = 0; i < 64; i += kIntraBuf) {
+  for (int i = 0; i < 64; i += NB) {
 #pragma unroll
-    for (int u = 0; u < kIntraBuf; ++u)
-      step(i + u, L.PA[u], L.PB[u], L.PA[(u + kIntraBuf - 1) % kIntraBuf],
-           L.PB[(u + kIntraBuf - 1) % kIntraBuf]);
+    for (int u = 0; u < NB; ++u)
+      step(i + u, L.PA[u], L.PB[u], L.PA[(u + NB - 1) % NB],
+           L.PB[(u + NB - 1) % NB]);
   }
   L.tq = tq_next;
   L.rqA = rqA_next;
