@@ -404,10 +404,11 @@ __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
 // IntraBuf<R>::n steps, already requested (cfar is the residue code of the last of them).
 // One lane's R int8 profile rows for one code (R = 4, 8 or 16: one 4-, 8- or 16-byte
 // load).
-// Profile-row buffers per lane (prefetch distance + 1): 8 where the registers allow
-// (R <= 8; for the latency-bound long pairs of the 8-row launch the deeper prefetch was
-// about 5% faster), kIntraBuf at R = 16.
-template <int R> struct IntraBuf { static constexpr int n = R <= 8 ? 8 : kIntraBuf; };
+// Profile-row buffers per lane (prefetch distance + 1): 8 where the registers allow (for
+// the latency-bound long pairs of the 8-row launch the deeper prefetch was about 5%
+// faster); the two-pair path at R = 16, which holds two sets, keeps kIntraBuf.
+template <int R> struct IntraBuf { static constexpr int n = 8; };
+template <int R> struct IntraBuf16 { static constexpr int n = R <= 8 ? 8 : kIntraBuf; };
 
 template <int R> struct RowBuf;
 template <> struct RowBuf<4> {
@@ -534,7 +535,7 @@ struct BandLane16 {
   int cfarA, cfarB;
   int2 tq;  // band-top (H, F), both halves packed
   int rqA, rqB;
-  RowBuf<R> PA[IntraBuf<R>::n], PB[IntraBuf<R>::n];
+  RowBuf<R> PA[IntraBuf16<R>::n], PB[IntraBuf16<R>::n];
 };
 
 // Row r's scores for A (low half) and B (high half), sign-extended from their int8
@@ -562,7 +563,7 @@ __device__ __forceinline__ void band_start16(BandLane16<R> &L, int lane, int nA,
   L.rqA = lane < nA ? resA[(lane >> 2) * (int64_t)csA + (lane & 3)] : kPadCode;
   L.rqB = lane < nB ? resB[(lane >> 2) * (int64_t)csB + (lane & 3)] : kPadCode;
 #pragma unroll
-  for (int t = 0; t + 1 < IntraBuf<R>::n; ++t) {
+  for (int t = 0; t + 1 < IntraBuf16<R>::n; ++t) {
     L.cfarA = wave_shr1(L.cfarA, __builtin_amdgcn_readlane(L.rqA, t));
     L.cfarB = wave_shr1(L.cfarB, __builtin_amdgcn_readlane(L.rqB, t));
     load_rows(L.PA[t], prof, pstride, L.cfarA);
@@ -579,7 +580,7 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
                                              bool has_bot, const uint8_t *resA, int csA,
                                              const uint8_t *resB, int csB,
                                              const uint8_t *prof, uint32_t pstride) {
-  constexpr int NB = IntraBuf<R>::n;
+  constexpr int NB = IntraBuf16<R>::n;
   constexpr int D = NB - 1;
   const int col_next = 64 * (k + 1) + lane;
   const int2 tq_next = (has_top && col_next < nA) ? top[col_next] : make_int2(0, 0);

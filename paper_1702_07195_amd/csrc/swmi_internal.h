@@ -216,7 +216,7 @@ int inter16_max_blocks_per_cu(int T);
 bool inter16q2_supported(int T);  // strip heights of the pair kernel (also 28)
 int inter16q2_max_blocks_per_cu(int T);
 constexpr int kIntraR = 16;
-constexpr int kIntraBuf = 4;     // profile-row buffers per lane at R = 16 (prefetch distance + 1)
+constexpr int kIntraBuf = 4;     // profile-row buffers per lane, two-pair path at R = 16
 constexpr int kIntraWaves = 8;
 constexpr int kCritR = 8;        // rows per lane of the critical-pair launch
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
