@@ -120,3 +120,24 @@ def test_long_mix_longest_pairs():
         want = list(ex.map(lambda q: int(oracle.score(q, db.seq(longest), w.matrix_values,
                                                       w.gap_open, w.gap_extend)), queries))
     assert got == want
+
+
+def test_served_config_sampled():
+    # The served configuration: the 4.35e6-sequence database resident, queries of the
+    # served length law submitted to the server in the configuration bench.py times
+    # (2 stream slots, batches of up to 8, 64 GiB budget); sampled scores of three of
+    # them against the oracle, all six complete.
+    w = synth.SERVED
+    _say("generate served database")
+    db = w.make_db()
+    qs = synth.served_queries(6)
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        with swmi.SwServer(h, synth.BLOSUM62, 10, 2, slots=2, max_batch=8,
+                           mem_budget_bytes=64 << 30) as sv:
+            _say("served queries " + ", ".join(str(len(q)) for q in qs))
+            results = [sv.wait(t) for t in [sv.submit(q) for q in qs]]
+    idx = _sample(db, 200, 11)
+    for k in (0, 3, 5):
+        want = oracle.search(qs[k], db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
+        assert np.array_equal(results[k][0][idx], want), k
+    assert all(r[0].min() >= 0 for r in results)
