@@ -118,7 +118,9 @@ int sw_search_async(const sw_db *db, const uint8_t *query, int32_t query_len,
 
 /*
  * sw_search_batch -- many queries against the database in one launch of the search
- * kernels (work items are (query, sequence group) pairs, longest first).
+ * kernels.  The queries are paired longest first and each pair shares the lanes of the
+ * inter-task kernel, one query per int16 half (SW_KNOB_QUERY_PAIRS; 0 = one query per
+ * lane); work items are (query pair, sequence group), longest first.
  *
  *   queries        host, uint8: the queries concatenated.
  *   query_offsets  host, int64[n_queries + 1], offsets[0] == 0, non-decreasing.
