@@ -84,7 +84,8 @@ def test_pairs_equal_oracle_at_every_strip_height(pdb, phandle, name, T):
 
 
 @pytest.mark.parametrize("route", [0, 1 << 30])
-@pytest.mark.parametrize("mat,go,ge", [("BLOSUM50", 11, 1), ("BLOSUM62", 10, 2)])
+@pytest.mark.parametrize("mat,go,ge", [("BLOSUM50", 11, 1), ("BLOSUM62", 10, 2),
+                                        ("BLOSUM62", 0, 0), ("BLOSUM62", 16383, 0)])
 def test_pairs_on_equal_pairs_off(pdb, phandle, route, mat, go, ge):
     qs = synth.batched_queries(9, 1, 500, seed=77)
     sm = synth.MATRICES[mat]
