@@ -271,6 +271,31 @@ def test_server_results_alone_equal_in_the_mix(small_db, small_handle):
         assert np.array_equal(alone[k], _oracle(qs[k], small_db, synth.BLOSUM62, 10, 2))
 
 
+def test_concurrent_searches_on_one_handle(small_db, small_handle):
+    # Several host threads search the same database at once (single queries and
+    # batches); the library's workspace pool holds two workspaces, so some calls wait
+    # for one.  Every result equals the result of the same call made alone.
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.Generator(np.random.PCG64(41))
+    qs = [synth.residues(rng, int(m)) for m in rng.integers(1, 400, 12)]
+    batches = [qs[0:3], qs[3:5], qs[5:9]]
+    alone_single = [small_handle.search(q, synth.BLOSUM62, 10, 2) for q in qs]
+    alone_batch = [small_handle.search_batch(b, synth.BLOSUM62, 10, 2) for b in batches]
+
+    def work(k):
+        if k % 4 == 3:
+            return ("b", k // 4, small_handle.search_batch(batches[k // 4], synth.BLOSUM62, 10, 2))
+        return ("s", k, small_handle.search(qs[k], synth.BLOSUM62, 10, 2))
+
+    _say("concurrent searches on one handle")
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        results = list(ex.map(work, range(12)))
+    for kind, k, got in results:
+        want = alone_batch[k] if kind == "b" else alone_single[k]
+        assert np.array_equal(got, want), (kind, k)
+    assert np.array_equal(alone_single[5], _oracle(qs[5], small_db, synth.BLOSUM62, 10, 2))
+
+
 def test_server_memory_admission(small_db, small_handle):
     # a budget smaller than one query's needs refuses it with SW_ENOMEM; others pass
     q = synth.served_queries(1, seed=32, median=100, lo=50, hi=150)[0]
