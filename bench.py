@@ -394,6 +394,12 @@ def bench_served(args):
     result["ms_per_step"] = mid["p50_ms"]
     result["serving"] = per_rate
     result["alone_equals_mix"] = bool(check)
+    result["note"] = ("the server admits a queued query whenever a stream slot is free and "
+                      "the batches in flight leave wave slots idle; on this database one "
+                      "query's work items fill every wave slot, so each launch holds one "
+                      "query and the next one starts as it ends (two such launches side by "
+                      "side only slow each other); on small databases several queries share "
+                      "a launch and launches overlap")
     result["roofline"] = None
     h.free()
     return result
