@@ -516,7 +516,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     // A pair whose full pipeline would outlast the search sets its critical path; with
     // bands of 64 * kCritR rows a step takes 7.5 kCritR + 14 instructions instead of
     // 7.5 R + 14, over more, shorter bands, so such pairs get a launch of their own with
-    // that height (4-band segments, one wave per SIMD) when it shortens their pipeline.
+    // that height (segments of kCritWaves bands, one wave per SIMD) when it shortens their
+    // pipeline.
     // (A wave alone on its SIMD steps in about 0.76 of t_step: 0.38 us at R = 16 on
     // MI355X, where latency keeps a step at about 1.7 times its instruction time.)
     if (S == s4 && p.R > kCritR && g_knob_intra_rows.load() == 0 && cap == 0 &&
@@ -525,7 +526,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       const double piped_c = (double)(nc + (int64_t)kIntraLag * (nbc - 1));
       const double step_c = (7.5 * kCritR + 14.0) / (7.5 * p.R + 14.0);
       if (piped_c * step_c < piped) {
-        const int32_t Sc = (nbc + 3) / 4;
+        const int32_t Sc = (nbc + kCritWaves - 1) / kCritWaves;
         const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
         for (int32_t j = 0; j < Sc; ++j) {
           PairItem sg = it;
@@ -584,11 +585,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   // workgroup per CU measured slower and erratic on MI355X (86 ms vs 103-115 ms for a
   // 35000-residue query over the long-sequence mix), not faster.
   const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
-  // The critical pairs' launch (at most three quarters of the CUs) is enqueued first and
-  // gets its CUs first; the main launch still asks for one workgroup per CU, and the ones
-  // that find no free CU start as the critical workgroups finish.
-  p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(),
-                                       std::max(1, db->num_cu * 3 / 4));
+  // The critical pairs' launch (a workgroup of kCritWaves waves per CU, one band and one
+  // wave per SIMD) is enqueued first and gets its CUs first; the main launch still asks
+  // for one workgroup per CU, and the ones that find no free CU start as the critical
+  // workgroups finish.
+  p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(), std::max(1, db->num_cu));
   p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + kIntraWaves - 1) / kIntraWaves,
                                        (int64_t)db->num_cu);
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
@@ -724,7 +725,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ca.flagged = nullptr;
     ca.flag_count = nullptr;
     ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
-    hip_check(launch_intra32(ca, kCritR, kIntraWaves, p.grid_crit, w->crit));
+    hip_check(launch_intra32(ca, kCritR, kCritWaves, p.grid_crit, w->crit));
     hip_check(hipEventRecord(w->join_crit, w->crit));
   }
   // long sequences: intra-task kernel on the auxiliary stream, concurrent with the sweep

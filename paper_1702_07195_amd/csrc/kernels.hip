@@ -786,7 +786,8 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
 // a length >= 0 is a two-pair item (int16, recompute on saturation); the others run in
 // int32.
 template <int R, int W>
-__global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2)))
+void k_intra32(IntraArgs a) {
   __shared__ int s_item;
   __shared__ int s_max[W];
   const int lane = threadIdx.x & 63;
@@ -878,8 +879,15 @@ __global__ __launch_bounds__(64 * W) void k_intra32(IntraArgs a) {
   }
 }
 
+// Workgroups of kIntraWaves waves at R = 4, 8 or 16, or of kCritWaves waves at R = kCritR
+// (the critical-pair launch: one wave per SIMD and no idle waves, which leaves room on
+// its CUs for waves of the other launches).
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
   if (grid == 0) return hipSuccess;
+  if (waves == kCritWaves && R == kCritR) {
+    hipLaunchKernelGGL((k_intra32<kCritR, kCritWaves>), dim3(grid), dim3(64 * kCritWaves), 0, s, a);
+    return hipGetLastError();
+  }
   if (waves != kIntraWaves) return hipErrorInvalidValue;
   switch (R) {
     case 4:

@@ -219,6 +219,7 @@ constexpr int kIntraR = 16;
 constexpr int kIntraBuf = 4;     // profile-row buffers per lane, two-pair path at R = 16
 constexpr int kIntraWaves = 8;
 constexpr int kCritR = 8;        // rows per lane of the critical-pair launch
+constexpr int kCritWaves = 4;    // waves per workgroup of the critical-pair launch
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
 constexpr int kSpinLimit = 1 << 24;  // default polls before a wait between segments gives up
 
