@@ -248,18 +248,59 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
 }
 
 // Rows per lane of the intra-task kernel for one search.  Its band is 64R query rows,
-// so a short query leaves most lanes of a large band on padding rows, while a lane's
-// per-step overhead (residue and boundary shifts, the profile request) is paid once per
-// R rows: a step issues about 7.5 R + 14 instructions.  Pick the R in {4, 8, 16} that
-// minimises the sum over the queries of bands(R) * (7.5 R + 14).
-int choose_R(const std::vector<int64_t> &lens) {
+// and a step (one anti-diagonal of a band) issues about 7.5 R + 14 instructions: the
+// lane's per-step overhead (residue and boundary shifts, the profile request) is paid
+// once per R rows, so over many bands R = 16 issues the fewest instructions per cell.
+// But a pair of n columns is swept in about n steps whatever R, its bands pipelined
+// kIntraLag chunks of 64 steps apart, so with few bands the step time of the longest
+// pair sets the search's critical path, and shorter steps win.  For each R in
+// {16, 8, 4} the search time is estimated as the larger of
+//   - the throughput time: every intra-task pair's bands of 64R rows at the kernel's
+//     rate, about 3.6e12 cells/s at R = 16 on MI355X, scaling as R / (7.5 R + 14); a
+//     query with more bands than a workgroup has waves is swept in several rounds, where
+//     short steps measured less efficient (0.77 at R = 8, 0.34 at R = 4, on a 35,000-row
+//     query), and
+//   - the longest pair's path: one band alone is one wave among two per SIMD, n + 63
+//     steps of 0.5 us x (7.5 R + 14) / 134 per band; several bands (a pair at least
+//     `wide_len` long) are a pipeline of waves alone on their SIMDs, 0.76 of that step,
+//     which at R > kCritR may run at kCritR rows in the critical-pair launch,
+// and the smallest estimate wins, a tie going to the larger R (R = 16 and 8 tie when
+// both leave the longest pairs to the critical-pair launch, and 16 measured faster
+// there).  (Measured on the
+// long-sequence mix, whose longest sequence has 35,000 residues: queries of 300 and
+// 1,000 residues ran 1.8 and 2.8 times faster at R = 4 than at the R an instruction
+// count alone picks.)
+int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
+             int64_t wide_len, int num_cu) {
   const int64_t forced = g_knob_intra_rows.load();
   if (forced == 4 || forced == 8 || forced == 16) return (int)forced;
+  if (n_max <= 0 || intra_res <= 0) return kIntraR;
+  auto step_scale = [](int R) { return (7.5 * R + 14.0) / (7.5 * 16 + 14.0); };
+  auto bands = [](int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); };
+  auto pipe = [&](int64_t m, int R) {  // a pipeline of waves alone on their SIMDs
+    const double chunks = (double)((n_max + 126) / 64 + (int64_t)kIntraLag * (bands(m, R) - 1));
+    return chunks * 64 * 0.76 * 0.5e-6 * step_scale(R);
+  };
   int best = kIntraR;
   double best_cost = 1e300;
   for (int R : {16, 8, 4}) {
-    double cost = 0;
-    for (int64_t m : lens) cost += (double)((m + 64 * R - 1) / (64 * R)) * (7.5 * R + 14.0);
+    const double rate = 3.6e12 * (R / 16.0) / step_scale(R) * (std::max(1, num_cu) / 256.0);
+    const double eff_rounds = R == 16 ? 1.0 : (R == 8 ? 0.77 : 0.34);
+    double thr = 0, path = 0;
+    for (int64_t m : lens) {
+      if (m == 0) continue;
+      const int64_t b = bands(m, R);
+      thr += (double)b * 64 * R * intra_res / (rate * (b > kIntraWaves ? eff_rounds : 1.0));
+      double t;
+      if (b >= 2 && n_max >= wide_len) {
+        t = pipe(m, R);
+        if (R > kCritR) t = std::min(t, pipe(m, kCritR));
+      } else {
+        t = (double)b * (double)(n_max + 63) * 0.5e-6 * step_scale(R);
+      }
+      path = std::max(path, t);
+    }
+    const double cost = std::max(thr, path);
     if (cost < best_cost * 0.999) {
       best_cost = cost;
       best = R;
@@ -354,10 +395,6 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   } else {
     p.T = choose_T(lens);
   }
-  p.R = choose_R(lens);
-  p.nbandsR.resize((size_t)nq);
-  for (int64_t q = 0; q < nq; ++q)
-    p.nbandsR[q] = (int32_t)((lens[q] + 64 * p.R - 1) / (64 * p.R));
   const int band = 64 * kIntraR;
   p.qd.resize((size_t)nq);
   for (int64_t q = 0; q < nq; ++q) {
@@ -404,6 +441,27 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   while (ninter > 0 && db->hgroups[ninter - 1].maxlen > route) --ninter;
   p.ngroups_inter = ninter;
 
+  // rows per lane of the intra-task kernel, from the pairs it gets (long sequences and
+  // routed groups, the latter estimated at their longest sequence)
+  const int64_t wide_len = g_knob_wide_len.load() > 0 ? g_knob_wide_len.load()
+                                                      : (int64_t)64 * 6 * kIntraLag;
+  {
+    double intra_res = 0;
+    int64_t n_max = 0;
+    for (const auto &L : db->longs) {
+      intra_res += L.len;
+      n_max = std::max<int64_t>(n_max, L.len);
+    }
+    for (int32_t g = ninter; g < db->ngroups; ++g) {
+      intra_res += (double)db->hgroups[g].count * db->hgroups[g].maxlen;
+      n_max = std::max<int64_t>(n_max, db->hgroups[g].maxlen);
+    }
+    p.R = choose_R(lens, intra_res, n_max, wide_len, db->num_cu);
+  }
+  p.nbandsR.resize((size_t)nq);
+  for (int64_t q = 0; q < nq; ++q)
+    p.nbandsR[q] = (int32_t)((lens[q] + 64 * p.R - 1) / (64 * p.R));
+
   // intra-task items: long sequences and the sequences of routed groups, for every query;
   // "wide" (a whole workgroup per pair) when the pair has several bands and enough
   // columns to fill the band pipeline, else "narrow" (one wave per pair); each part
@@ -423,8 +481,6 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     it.segment = 0;
     it.nsegments = 1;
     const double cost = (double)len * (double)lens[q];
-    const int64_t wide_len = g_knob_wide_len.load() > 0 ? g_knob_wide_len.load()
-                                                        : (int64_t)64 * 6 * kIntraLag;
     const bool is_wide = len >= wide_len && p.nbandsR[q] >= 2;
     (is_wide ? wide : narrow).emplace_back(cost, it);
   };
@@ -459,7 +515,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   for (auto &x : wide) intra_cells += x.first;
   for (auto &x : narrow) intra_cells += x.first;
   const double step_scale = (7.5 * p.R + 14.0) / (7.5 * 16 + 14.0);
-  const double t_search = intra_cells / (2.5e12 * (16.0 / p.R) / step_scale) *
+  const double t_search = intra_cells / (2.5e12 * (p.R / 16.0) / step_scale) *
                           (256.0 / std::max(1, db->num_cu));
   const double t_step = 0.5e-6 * step_scale;
   const int64_t cap = g_knob_max_segments.load();
