@@ -423,6 +423,26 @@ def test_intra_rows_per_lane(mixed_db, R, m):
     assert np.array_equal(got, _oracle(q, mixed_db, synth.BLOSUM62, 10, 2))
 
 
+def test_automatic_rows_with_very_long_sequences():
+    # Sequences longer than the inter-task limit next to ordinary ones: the host picks the
+    # rows per lane from throughput and the longest pair's path (few bands of 4 rows per
+    # lane for the mid-length queries, 16 for the longest), splits long pairs across
+    # workgroups as it sees fit, and every score still equals the oracle's, one query at
+    # a time and in one batch.
+    rng = np.random.Generator(np.random.PCG64(2718))
+    lengths = np.concatenate([synth.lognormal_lengths(rng, 400, 300, 0.8, 10, 3000),
+                              rng.integers(9000, 20001, 10)])
+    db = synth.db_from_lengths(rng, lengths)
+    qs = [synth.residues(rng, m) for m in (300, 1000, 2005, 5478)]
+    want = [_oracle(q, db, synth.BLOSUM62, 10, 2) for q in qs]
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        for q, w in zip(qs, want):
+            _say(f"automatic rows per lane, m={len(q)}")
+            assert np.array_equal(h.search(q, synth.BLOSUM62, 10, 2), w), len(q)
+        _say("automatic rows per lane, batch")
+        assert np.array_equal(h.search_batch(qs, synth.BLOSUM62, 10, 2), np.stack(want))
+
+
 def test_server_runs_one_query_per_launch_when_it_fills_the_device():
     # 1,000,000 sequences are 15,625 groups of 64: one query's work items fill every
     # wave slot (256 CUs x 12 waves) more than four times over, so the server neither
