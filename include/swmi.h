@@ -263,8 +263,8 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          wave (0 = automatic: 1152);
  *   SW_KNOB_MAX_SEGMENTS   most workgroups one intra-task pair may be split across
  *                          (0 = automatic, 1 = never split);
- *   SW_KNOB_INTRA_ROWS     query rows per lane of the intra-task kernel: 4, 8 or 16
- *                          (bands of 256, 512 or 1024 rows; 0 = chosen per search);
+ *   SW_KNOB_INTRA_ROWS     query rows per lane of the intra-task kernel: 2, 4, 8 or 16
+ *                          (bands of 128, 256, 512 or 1024 rows; 0 = chosen per search);
  *   SW_KNOB_INTRA_PAIRS    1 (default): when a search has many narrow intra-task pairs,
  *                          short ones run two per wave in packed int16 (saturated halves
  *                          recomputed in int32); 0: every intra-task pair runs alone in

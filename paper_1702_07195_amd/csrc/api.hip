@@ -254,26 +254,29 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
 // But a pair of n columns is swept in about n steps whatever R, its bands pipelined
 // kIntraLag chunks of 64 steps apart, so with few bands the step time of the longest
 // pair sets the search's critical path, and shorter steps win.  For each R in
-// {16, 8, 4} the search time is estimated as the larger of
+// {16, 8, 4, 2} the search time is estimated as the larger of
 //   - the throughput time: every intra-task pair's bands of 64R rows at the kernel's
 //     rate, about 3.6e12 cells/s at R = 16 on MI355X, scaling as R / (7.5 R + 14); a
 //     query with more bands than a workgroup has waves is swept in several rounds, where
 //     short steps measured less efficient (0.77 at R = 8, 0.34 at R = 4, on a 35,000-row
-//     query), and
+//     query; 0.15 assumed at R = 2), and R = 2 reached 0.45 of that rate even with few
+//     bands (a 1,000-row query over 6.4e6 residues), and
 //   - the longest pair's path: one band alone is one wave among two per SIMD, n + 63
 //     steps of 0.5 us x (7.5 R + 14) / 134 per band; several bands (a pair at least
 //     `wide_len` long) are a pipeline of waves alone on their SIMDs, 0.76 of that step,
 //     which at R > kCritR may run at kCritR rows in the critical-pair launch,
 // and the smallest estimate wins, a tie going to the larger R (R = 16 and 8 tie when
 // both leave the longest pairs to the critical-pair launch, and 16 measured faster
-// there).  (Measured on the
+// there).  R = 2 is weighed only when the path at R = 4 exceeds a millisecond: below
+// that, per-search costs the estimate leaves out dominate, and R = 2 measured no faster
+// (a 144-row query over 2,000 sequences of at most 2,000 residues).  (Measured on the
 // long-sequence mix, whose longest sequence has 35,000 residues: queries of 300 and
 // 1,000 residues ran 1.8 and 2.8 times faster at R = 4 than at the R an instruction
 // count alone picks.)
 int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
              int64_t wide_len, int num_cu) {
   const int64_t forced = g_knob_intra_rows.load();
-  if (forced == 4 || forced == 8 || forced == 16) return (int)forced;
+  if (forced == 2 || forced == 4 || forced == 8 || forced == 16) return (int)forced;
   if (n_max <= 0 || intra_res <= 0) return kIntraR;
   auto step_scale = [](int R) { return (7.5 * R + 14.0) / (7.5 * 16 + 14.0); };
   auto bands = [](int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); };
@@ -282,15 +285,17 @@ int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
     return chunks * 64 * 0.76 * 0.5e-6 * step_scale(R);
   };
   int best = kIntraR;
-  double best_cost = 1e300;
-  for (int R : {16, 8, 4}) {
+  double best_cost = 1e300, path4 = 0;
+  for (int R : {16, 8, 4, 2}) {
+    if (R == 2 && path4 < 1e-3) break;
     const double rate = 3.6e12 * (R / 16.0) / step_scale(R) * (std::max(1, num_cu) / 256.0);
-    const double eff_rounds = R == 16 ? 1.0 : (R == 8 ? 0.77 : 0.34);
+    const double eff_rounds = R == 16 ? 1.0 : (R == 8 ? 0.77 : (R == 4 ? 0.34 : 0.15));
+    const double eff_few = R == 2 ? 0.45 : 1.0;
     double thr = 0, path = 0;
     for (int64_t m : lens) {
       if (m == 0) continue;
       const int64_t b = bands(m, R);
-      thr += (double)b * 64 * R * intra_res / (rate * (b > kIntraWaves ? eff_rounds : 1.0));
+      thr += (double)b * 64 * R * intra_res / (rate * (b > kIntraWaves ? eff_rounds : eff_few));
       double t;
       if (b >= 2 && n_max >= wide_len) {
         t = pipe(m, R);
@@ -300,6 +305,7 @@ int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
       }
       path = std::max(path, t);
     }
+    if (R == 4) path4 = path;
     const double cost = std::max(thr, path);
     if (cost < best_cost * 0.999) {
       best_cost = cost;
@@ -943,7 +949,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
     case SW_KNOB_WIDE_LEN: if (value < 0) return SW_EINVAL; g_knob_wide_len = value; return SW_OK;
     case SW_KNOB_MAX_SEGMENTS: if (value < 0) return SW_EINVAL; g_knob_max_segments = value; return SW_OK;
     case SW_KNOB_INTRA_ROWS:
-      if (value != 0 && value != 4 && value != 8 && value != 16) return SW_EINVAL;
+      if (value != 0 && value != 2 && value != 4 && value != 8 && value != 16) return SW_EINVAL;
       g_knob_intra_rows = value;
       return SW_OK;
     case SW_KNOB_INTRA_PAIRS: if (value < 0 || value > 2) return SW_EINVAL; g_knob_intra_pairs = value; return SW_OK;

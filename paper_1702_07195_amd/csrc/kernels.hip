@@ -402,8 +402,8 @@ __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
 // step's diagonal for its first row, the band-top values and residues of the current
 // 64-column chunk (lane l holds column 64k + l), and the profile rows of the next
 // IntraBuf<R>::n steps, already requested (cfar is the residue code of the last of them).
-// One lane's R int8 profile rows for one code (R = 4, 8 or 16: one 4-, 8- or 16-byte
-// load).
+// One lane's R int8 profile rows for one code (R = 2, 4, 8 or 16: one 2-, 4-, 8- or
+// 16-byte load).
 // Profile-row buffers per lane (prefetch distance + 1): 8 where the registers allow (for
 // the latency-bound long pairs of the 8-row launch the deeper prefetch was about 5%
 // faster); the two-pair path at R = 16, which holds two sets, keeps kIntraBuf.
@@ -411,6 +411,10 @@ template <int R> struct IntraBuf { static constexpr int n = 8; };
 template <int R> struct IntraBuf16 { static constexpr int n = R <= 8 ? 8 : kIntraBuf; };
 
 template <int R> struct RowBuf;
+template <> struct RowBuf<2> {
+  uint16_t v;
+  __device__ uint32_t word(int) const { return v; }
+};
 template <> struct RowBuf<4> {
   uint32_t v;
   __device__ uint32_t word(int) const { return v; }
@@ -879,7 +883,7 @@ void k_intra32(IntraArgs a) {
   }
 }
 
-// Workgroups of kIntraWaves waves at R = 4, 8 or 16, or of kCritWaves waves at R = kCritR
+// Workgroups of kIntraWaves waves at R = 2, 4, 8 or 16, or of kCritWaves waves at R = kCritR
 // (the critical-pair launch: one wave per SIMD and no idle waves, which leaves room on
 // its CUs for waves of the other launches).
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
@@ -890,6 +894,9 @@ hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStr
   }
   if (waves != kIntraWaves) return hipErrorInvalidValue;
   switch (R) {
+    case 2:
+      hipLaunchKernelGGL((k_intra32<2, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
+      break;
     case 4:
       hipLaunchKernelGGL((k_intra32<4, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
       break;

@@ -116,10 +116,10 @@ def test_calibration_library_exports_its_header():
 def test_intra_rows_knob_takes_only_band_shapes():
     old = swmi.get_knob(swmi.SW_KNOB_INTRA_ROWS)
     try:
-        for bad in (1, 12, 32, -4):
+        for bad in (1, 3, 12, 32, -4):
             with pytest.raises(swmi.SwError):
                 swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, bad)
-        for good in (4, 8, 16, 0):
+        for good in (2, 4, 8, 16, 0):
             swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, good)
             assert swmi.get_knob(swmi.SW_KNOB_INTRA_ROWS) == good
     finally:

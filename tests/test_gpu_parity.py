@@ -403,7 +403,7 @@ def mixed_db():
     return synth.db_from_lengths(rng, lengths)
 
 
-@pytest.mark.parametrize("R", [4, 8, 16])
+@pytest.mark.parametrize("R", [2, 4, 8, 16])
 @pytest.mark.parametrize("m", [70, 300, 1500, 3000])
 def test_intra_rows_per_lane(mixed_db, R, m):
     # The intra-task kernel with bands of 64R rows (R query rows per lane), every
