@@ -278,6 +278,11 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          inter-task DP two queries per lane (the queries paired
  *                          longest first, both in packed int16 at the same database
  *                          column); 0: one query per lane.  Scores are the same.
+ *   SW_KNOB_MAIN_WAVES     waves per workgroup of the intra-task launch over long and
+ *                          routed sequences: 8 (one workgroup per compute unit) or 4
+ *                          (two per compute unit); 0 (default) = 4 when the search is
+ *                          estimated throughput-bound, 8 when the longest pair's
+ *                          pipeline bounds it.  Scores are the same.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -291,6 +296,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_INTRA_PAIRS    10
 #define SW_KNOB_SPIN_LIMIT     11
 #define SW_KNOB_QUERY_PAIRS    12
+#define SW_KNOB_MAIN_WAVES     13
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

@@ -37,6 +37,7 @@ std::atomic<int64_t> g_knob_intra_rows{0};
 std::atomic<int64_t> g_knob_intra_pairs{1};
 std::atomic<int64_t> g_knob_spin_limit{0};
 std::atomic<int64_t> g_knob_query_pairs{1};
+std::atomic<int64_t> g_knob_main_waves{0};
 
 struct HipFail {
   hipError_t err;
@@ -274,24 +275,20 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
 // 1,000 residues ran 1.8 and 2.8 times faster at R = 4 than at the R an instruction
 // count alone picks.)
 int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
-             int64_t wide_len, int num_cu) {
-  const int64_t forced = g_knob_intra_rows.load();
-  if (forced == 2 || forced == 4 || forced == 8 || forced == 16) return (int)forced;
-  if (n_max <= 0 || intra_res <= 0) return kIntraR;
+             int64_t wide_len, int num_cu, bool *throughput_bound) {
   auto step_scale = [](int R) { return (7.5 * R + 14.0) / (7.5 * 16 + 14.0); };
   auto bands = [](int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); };
   auto pipe = [&](int64_t m, int R) {  // a pipeline of waves alone on their SIMDs
     const double chunks = (double)((n_max + 126) / 64 + (int64_t)kIntraLag * (bands(m, R) - 1));
     return chunks * 64 * 0.76 * 0.5e-6 * step_scale(R);
   };
-  int best = kIntraR;
-  double best_cost = 1e300, path4 = 0;
-  for (int R : {16, 8, 4, 2}) {
-    if (R == 2 && path4 < 1e-3) break;
+  // (throughput time, longest path) at R
+  auto estimate = [&](int R, double &thr, double &path) {
     const double rate = 3.6e12 * (R / 16.0) / step_scale(R) * (std::max(1, num_cu) / 256.0);
     const double eff_rounds = R == 16 ? 1.0 : (R == 8 ? 0.77 : (R == 4 ? 0.34 : 0.15));
     const double eff_few = R == 2 ? 0.45 : 1.0;
-    double thr = 0, path = 0;
+    thr = 0;
+    path = 0;
     for (int64_t m : lens) {
       if (m == 0) continue;
       const int64_t b = bands(m, R);
@@ -305,13 +302,28 @@ int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
       }
       path = std::max(path, t);
     }
-    if (R == 4) path4 = path;
-    const double cost = std::max(thr, path);
-    if (cost < best_cost * 0.999) {
-      best_cost = cost;
-      best = R;
+  };
+  int best = kIntraR;
+  const int64_t forced = g_knob_intra_rows.load();
+  if (forced == 2 || forced == 4 || forced == 8 || forced == 16) {
+    best = (int)forced;
+  } else if (n_max > 0 && intra_res > 0) {
+    double best_cost = 1e300, path4 = 0;
+    for (int R : {16, 8, 4, 2}) {
+      if (R == 2 && path4 < 1e-3) break;
+      double thr, path;
+      estimate(R, thr, path);
+      if (R == 4) path4 = path;
+      const double cost = std::max(thr, path);
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        best = R;
+      }
     }
   }
+  double thr = 0, path = 0;
+  if (n_max > 0 && intra_res > 0) estimate(best, thr, path);
+  *throughput_bound = thr >= 1.2 * path;
   return best;
 }
 
@@ -347,6 +359,7 @@ int choose_T(const std::vector<int64_t> &lens, bool pairs = false) {
 struct Plan {
   int T = 32;
   int R = kIntraR;               // rows per lane of the long-pair intra-task launch
+  int main_waves = kIntraWaves;  // waves per workgroup of that launch (8, or 4 at two per CU)
   std::vector<int32_t> nbandsR;  // query bands of 64R rows
   int64_t xbnd_elems = 0;  // int2 elements of the boundary rows between pair segments
   int32_t nprog = 0;       // progress counters of those boundaries
@@ -462,7 +475,16 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       intra_res += (double)db->hgroups[g].count * db->hgroups[g].maxlen;
       n_max = std::max<int64_t>(n_max, db->hgroups[g].maxlen);
     }
-    p.R = choose_R(lens, intra_res, n_max, wide_len, db->num_cu);
+    // A throughput-bound search (estimated throughput time at least 1.2 times the
+    // longest path) runs four-wave workgroups, two per CU: the same occupancy, and one
+    // fits beside a critical-pair workgroup (an 8-wave one does not).  Otherwise
+    // eight-wave workgroups give a pair's few band waves a SIMD each (the rest of the
+    // workgroup idles).  (Long-sequence mix on MI355X: 5478-residue query 14.7 -> 10.8
+    // ms with four-wave workgroups; a 2005-residue query, at a ratio of 1.1, 8.2 -> 9.3.)
+    bool throughput_bound = false;
+    p.R = choose_R(lens, intra_res, n_max, wide_len, db->num_cu, &throughput_bound);
+    const int64_t mw = g_knob_main_waves.load();
+    p.main_waves = (mw == 4 || mw == 8) ? (int)mw : (throughput_bound ? kNarrowWaves : kIntraWaves);
   }
   p.nbandsR.resize((size_t)nq);
   for (int64_t q = 0; q < nq; ++q)
@@ -504,9 +526,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   };
   std::stable_sort(wide.begin(), wide.end(), by_cost);
   std::stable_sort(narrow.begin(), narrow.end(), by_cost);
-  // Critical path of the longest pairs.  A workgroup sweeps its bands in rounds of
-  // kIntraWaves, so a pair of nb bands takes about ceil(nb / kIntraWaves) sweeps of its
-  // columns; cut into segments of at most kIntraWaves consecutive bands on workgroups of
+  // Critical path of the longest pairs.  A workgroup sweeps its bands in rounds of its
+  // W = p.main_waves waves, so a pair of nb bands takes about ceil(nb / W) sweeps of its
+  // columns; cut into segments of at most W consecutive bands on workgroups of
   // their own, the bands form one pipeline (nc + kIntraLag * (nb - 1) chunks), and with at
   // most 4 bands per segment each band's wave has a SIMD to itself.  A pair is split as
   // little as keeps its estimated time within half the estimated time of the whole
@@ -562,11 +584,11 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     const PairItem &it = x.second;
     const int32_t nb = it.band1;
     const int64_t nc = ((int64_t)it.len + 126) / 64;
-    const int64_t nce = std::max<int64_t>(nc, (int64_t)kIntraLag * kIntraWaves);
+    const int64_t nce = std::max<int64_t>(nc, (int64_t)kIntraLag * p.main_waves);
     const int64_t lastb = nb - 1;
-    const double whole = (double)((lastb / kIntraWaves) * nce + kIntraLag * (lastb % kIntraWaves) + nc);
+    const double whole = (double)((lastb / p.main_waves) * nce + kIntraLag * (lastb % p.main_waves) + nc);
     const double piped = (double)(nc + (int64_t)kIntraLag * lastb);
-    const int32_t s8 = (nb + kIntraWaves - 1) / kIntraWaves, s4 = (nb + 3) / 4;
+    const int32_t s8 = (nb + p.main_waves - 1) / p.main_waves, s4 = (nb + 3) / 4;
     int32_t S = 1;
     if (whole * 64 * t_step > 0.5 * t_search) S = piped * 64 * t_step <= t_search ? s8 : s4;
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
@@ -642,18 +664,19 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
 
   const int64_t nitems16 = (int64_t)ninter * nunits;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
-  // One persistent workgroup (kIntraWaves waves) per compute unit: the kernel's
-  // per-step profile gathers touch one cache line per lane, and a second resident
-  // workgroup per CU measured slower and erratic on MI355X (86 ms vs 103-115 ms for a
-  // 35000-residue query over the long-sequence mix), not faster.
+  // Two waves per SIMD: one persistent 8-wave workgroup per compute unit, or two 4-wave
+  // ones.  The kernel's per-step profile gathers touch one cache line per lane, and a
+  // second resident 8-wave workgroup per CU (four waves per SIMD) measured slower and
+  // erratic on MI355X (86 ms vs 103-115 ms for a 35000-residue query over the
+  // long-sequence mix), not faster.
   const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
   // The critical pairs' launch (a workgroup of kCritWaves waves per CU, one band and one
   // wave per SIMD) is enqueued first and gets its CUs first; the main launch still asks
   // for one workgroup per CU, and the ones that find no free CU start as the critical
   // workgroups finish.
   p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(), std::max(1, db->num_cu));
-  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + kIntraWaves - 1) / kIntraWaves,
-                                       (int64_t)db->num_cu);
+  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + p.main_waves - 1) / p.main_waves,
+                                       (int64_t)db->num_cu * (kIntraWaves / p.main_waves));
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
   // and nothing is launched when no kernel can append to it
   const bool may_flag = (nitems16 > 0 && p.grid16 > 0) || p.nduos > 0;
@@ -820,7 +843,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
-    hip_check(launch_intra32(ia, p.R, kIntraWaves, p.grid_long, w->aux));
+    hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, w->aux));
     if (timed) {
       hip_check(hipEventRecord(w->t1[1], w->aux));
       w->timed[1] = true;
@@ -958,6 +981,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       g_knob_spin_limit = value;
       return SW_OK;
     case SW_KNOB_QUERY_PAIRS: if (value < 0 || value > 1) return SW_EINVAL; g_knob_query_pairs = value; return SW_OK;
+    case SW_KNOB_MAIN_WAVES:
+      if (value != 0 && value != 4 && value != 8) return SW_EINVAL;
+      g_knob_main_waves = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -976,6 +1003,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_INTRA_PAIRS: return g_knob_intra_pairs.load();
     case SW_KNOB_SPIN_LIMIT: return g_knob_spin_limit.load();
     case SW_KNOB_QUERY_PAIRS: return g_knob_query_pairs.load();
+    case SW_KNOB_MAIN_WAVES: return g_knob_main_waves.load();
     default: return SW_EINVAL;
   }
 }

@@ -883,13 +883,20 @@ void k_intra32(IntraArgs a) {
   }
 }
 
-// Workgroups of kIntraWaves waves at R = 2, 4, 8 or 16, or of kCritWaves waves at R = kCritR
-// (the critical-pair launch: one wave per SIMD and no idle waves, which leaves room on
-// its CUs for waves of the other launches).
+// Workgroups of kIntraWaves (8) or 4 waves at R = 2, 4, 8 or 16.  Four-wave workgroups
+// serve the critical-pair launch (one wave per SIMD, none idle) and throughput-bound
+// main launches (two per CU; one fits beside a critical-pair workgroup).
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
   if (grid == 0) return hipSuccess;
-  if (waves == kCritWaves && R == kCritR) {
-    hipLaunchKernelGGL((k_intra32<kCritR, kCritWaves>), dim3(grid), dim3(64 * kCritWaves), 0, s, a);
+  static_assert(kCritWaves == 4 && kNarrowWaves == 4, "four-wave instances below");
+  if (waves == 4) {
+    switch (R) {
+      case 2: hipLaunchKernelGGL((k_intra32<2, 4>), dim3(grid), dim3(256), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_intra32<4, 4>), dim3(grid), dim3(256), 0, s, a); break;
+      case 8: hipLaunchKernelGGL((k_intra32<8, 4>), dim3(grid), dim3(256), 0, s, a); break;
+      case 16: hipLaunchKernelGGL((k_intra32<16, 4>), dim3(grid), dim3(256), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   if (waves != kIntraWaves) return hipErrorInvalidValue;

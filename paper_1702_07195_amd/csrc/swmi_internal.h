@@ -220,6 +220,7 @@ constexpr int kIntraBuf = 4;     // profile-row buffers per lane, two-pair path 
 constexpr int kIntraWaves = 8;
 constexpr int kCritR = 8;        // rows per lane of the critical-pair launch
 constexpr int kCritWaves = 4;    // waves per workgroup of the critical-pair launch
+constexpr int kNarrowWaves = 4;  // waves per workgroup of a throughput-bound main intra launch
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
 constexpr int kSpinLimit = 1 << 24;  // default polls before a wait between segments gives up
 

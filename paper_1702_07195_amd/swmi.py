@@ -37,6 +37,7 @@ SW_KNOB_INTRA_ROWS = 9
 SW_KNOB_INTRA_PAIRS = 10
 SW_KNOB_SPIN_LIMIT = 11
 SW_KNOB_QUERY_PAIRS = 12
+SW_KNOB_MAIN_WAVES = 13
 
 # Every entry point declared in include/swmi.h.
 SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_async",

@@ -166,6 +166,20 @@ def test_query_pairs_knob_values():
         swmi.set_knob(swmi.SW_KNOB_QUERY_PAIRS, old)
 
 
+def test_main_waves_knob_values():
+    old = swmi.get_knob(swmi.SW_KNOB_MAIN_WAVES)
+    assert old == 0  # automatic by default
+    try:
+        for bad in (-1, 1, 2, 16):
+            with pytest.raises(swmi.SwError):
+                swmi.set_knob(swmi.SW_KNOB_MAIN_WAVES, bad)
+        for good in (4, 8, 0):
+            swmi.set_knob(swmi.SW_KNOB_MAIN_WAVES, good)
+            assert swmi.get_knob(swmi.SW_KNOB_MAIN_WAVES) == good
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_MAIN_WAVES, old)
+
+
 def test_binding_constants_match_the_header():
     # every #define of include/swmi.h has the same value in the binding
     text = open(HEADER).read()

@@ -358,26 +358,28 @@ def test_search_of_fasta_database(tmp_path):
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
 
 
+@pytest.mark.parametrize("waves", [0, 4, 8])
 @pytest.mark.parametrize("m,cap", [(9000, 0), (17000, 0), (17000, 2), (17000, 1)])
-def test_split_pairs_across_workgroups(m, cap):
+def test_split_pairs_across_workgroups(m, cap, waves):
     # Queries with more query bands than a workgroup has waves: wide pairs are split
     # into segments on different workgroups that hand the boundary row over through
-    # global memory (cap: most segments per pair, 0 = automatic, 1 = none); every
-    # sequence is routed to the intra-task kernel.
+    # global memory (cap: most segments per pair, 0 = automatic, 1 = none; waves per
+    # workgroup 4, 8 or automatic); every sequence is routed to the intra-task kernel.
     rng = np.random.Generator(np.random.PCG64(70 + m))
     lengths = np.concatenate([rng.integers(1200, 3000, 6), rng.integers(1, 900, 40)])
     db = synth.db_from_lengths(rng, lengths)
     q = synth.residues(rng, m)
-    old = (swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN), swmi.get_knob(swmi.SW_KNOB_MAX_SEGMENTS))
-    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
-    swmi.set_knob(swmi.SW_KNOB_MAX_SEGMENTS, cap)
+    knobs = (swmi.SW_KNOB_ROUTE_LEN, swmi.SW_KNOB_MAX_SEGMENTS, swmi.SW_KNOB_MAIN_WAVES)
+    old = [swmi.get_knob(k) for k in knobs]
+    for k, v in zip(knobs, (1, cap, waves)):
+        swmi.set_knob(k, v)
     try:
-        _say(f"split pairs m={m} cap={cap}")
+        _say(f"split pairs m={m} cap={cap} waves={waves}")
         with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
             got = h.search(q, synth.BLOSUM62, 10, 2)
     finally:
-        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
-        swmi.set_knob(swmi.SW_KNOB_MAX_SEGMENTS, old[1])
+        for k, v in zip(knobs, old):
+            swmi.set_knob(k, v)
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
 
 
@@ -403,23 +405,26 @@ def mixed_db():
     return synth.db_from_lengths(rng, lengths)
 
 
+@pytest.mark.parametrize("waves", [4, 8])
 @pytest.mark.parametrize("R", [2, 4, 8, 16])
 @pytest.mark.parametrize("m", [70, 300, 1500, 3000])
-def test_intra_rows_per_lane(mixed_db, R, m):
-    # The intra-task kernel with bands of 64R rows (R query rows per lane), every
-    # sequence routed to it; with small databases the longest pairs are also split.
+def test_intra_rows_per_lane(mixed_db, R, m, waves):
+    # The intra-task kernel with bands of 64R rows (R query rows per lane) on workgroups
+    # of 4 or 8 waves, every sequence routed to it; with small databases the longest
+    # pairs are also split.
     rng = np.random.Generator(np.random.PCG64(900 + m))
     q = synth.residues(rng, m)
-    old = (swmi.get_knob(swmi.SW_KNOB_ROUTE_LEN), swmi.get_knob(swmi.SW_KNOB_INTRA_ROWS))
-    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
-    swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, R)
+    knobs = (swmi.SW_KNOB_ROUTE_LEN, swmi.SW_KNOB_INTRA_ROWS, swmi.SW_KNOB_MAIN_WAVES)
+    old = [swmi.get_knob(k) for k in knobs]
+    for k, v in zip(knobs, (1, R, waves)):
+        swmi.set_knob(k, v)
     try:
-        _say(f"intra rows per lane R={R} m={m}")
+        _say(f"intra rows per lane R={R} m={m} waves={waves}")
         with swmi.sw_db_load(mixed_db.residues, mixed_db.offsets, ALPHA) as h:
             got = h.search(q, synth.BLOSUM62, 10, 2)
     finally:
-        swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old[0])
-        swmi.set_knob(swmi.SW_KNOB_INTRA_ROWS, old[1])
+        for k, v in zip(knobs, old):
+            swmi.set_knob(k, v)
     assert np.array_equal(got, _oracle(q, mixed_db, synth.BLOSUM62, 10, 2))
 
 
