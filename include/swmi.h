@@ -200,6 +200,30 @@ int sw_server_stats(sw_server *server, int64_t *launches, int64_t *max_in_flight
 void sw_server_free(sw_server *server);
 
 /*
+ * sw_server_counters -- the server's counters, written to values[0 .. min(n, 7)):
+ *   SW_SC_LAUNCHES      kernel launches (batch mode: batched searches; session mode:
+ *                       session launches, each serving every query admitted while it ran)
+ *   SW_SC_MAX_IN_FLIGHT largest number of batches (batch mode) or records (session mode)
+ *                       on the device at once
+ *   SW_SC_REFUSED       requests refused with SW_ENOMEM
+ *   SW_SC_SESSION_MODE  1 if the server runs sessions, 0 if batches
+ *   SW_SC_RECORDS       records published (session mode)
+ *   SW_SC_PAIRED        of those, records holding two queries
+ *   SW_SC_EXACT_RUNS    queries served by the standard search path (a score at the int16
+ *                       ceiling, or a query longer than a session takes)
+ * Errors: SW_EINVAL (NULL server or values, n < 0).
+ */
+#define SW_SC_LAUNCHES       0
+#define SW_SC_MAX_IN_FLIGHT  1
+#define SW_SC_REFUSED        2
+#define SW_SC_SESSION_MODE   3
+#define SW_SC_RECORDS        4
+#define SW_SC_PAIRED         5
+#define SW_SC_EXACT_RUNS     6
+#define SW_SERVER_NCOUNTERS  7
+int sw_server_counters(sw_server *server, int64_t *values, int32_t n);
+
+/*
  * sw_topk -- sorting stage (Section 4, step 3: scores sorted in descending order),
  * restricted to the k best hits: selects, on the device, the min(k, n_seqs) highest
  * scores of a search and returns them sorted by score descending, ties by database index

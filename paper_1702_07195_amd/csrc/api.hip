@@ -766,6 +766,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   pa.ctr = ctr;
   pa.zero = (int32_t *)w->xprog.ptr;
   pa.nzero = 2 * (int64_t)std::max<int32_t>(1, p.nprog);
+  pa.scores = scores_dev;
+  pa.n_seqs = db->n_seqs;
   if (nq > 0) hip_check(launch_profile(pa, s));
   if (q2 && nitems16 > 0) {
     Profile2Args pb;
@@ -1412,11 +1414,23 @@ SW_API void sw_plan_free(sw_plan *plan) {
 }
 
 // ------------------------------------------------------------------------ serving
-// Continuous batching over a resident database.  Requests are queued by sw_server_submit;
-// a worker thread launches every queued request it can admit as one batched search on a
-// free stream slot, as soon as a slot is free and the device-memory budget allows, so new
-// requests join while earlier batches are still on the GPU and their kernels overlap on
-// the device.  Each slot owns a workspace; completion is detected with events.
+// Continuous batching over a resident database.  Two modes, chosen at creation:
+//
+// Session mode (a database that fills the device several times over, with no sequence
+// long enough for the intra-task kernel): one persistent launch of k_serve serves every
+// query admitted while it runs.  The worker thread turns queued requests into records
+// (one query, or two of similar length sharing the lanes), writes them into host memory
+// and raises the doorbell; the running kernel's work list grows by the record's groups,
+// so a query that arrives while others are on the device joins the same launch right
+// behind them.  The kernel reports each completed record through host memory; scores are
+// already in host memory and are copied into the caller's buffer.  The session is closed
+// once the server is idle, or before a query that must take the standard path (one longer
+// than the session's query cache, or one with a score at the int16 ceiling, which is
+// searched again exactly).
+//
+// Batch mode (small databases, or long sequences): every queued request the budget
+// admits is launched as one batched search on a free stream slot; batches in flight on
+// different slots overlap on the device.
 namespace {
 
 struct ServerRequest {
@@ -1424,6 +1438,7 @@ struct ServerRequest {
   std::vector<uint8_t> query;
   int32_t *scores_out = nullptr;  // caller's host buffer (n_seqs)
   int status = 1;                 // 1 = pending, 0 = done, < 0 = error
+  bool exact = false;             // must run (again) through the standard search path
   double t_submit = 0, t_start = 0, t_done = 0;
 };
 
@@ -1436,11 +1451,49 @@ struct ServerSlot {
   std::vector<ServerRequest *> batch;
   DevBuf scores;
   HostBuf host_scores;
+  HostBuf host_error;                   // Counters::error of the batch, copied after it
+};
+
+// A record of the running session: its number, slot, queries and score rows.
+struct SessionRecord {
+  int32_t r = 0;
+  int32_t slot = 0;
+  ServerRequest *qa = nullptr, *qb = nullptr;
+  int32_t row_a = -1, row_b = -1;
 };
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+// Host memory the device reads and writes while a session runs (coherent, mapped).
+struct CoherentBuf {
+  void *ptr = nullptr;  // host address
+  void *dev = nullptr;  // the same memory as the device addresses it
+  size_t bytes = 0;
+  void alloc(size_t n) {
+    hip_check(hipHostMalloc(&ptr, std::max<size_t>(n, 64), hipHostMallocMapped | hipHostMallocCoherent));
+    bytes = n;
+    std::memset(ptr, 0, bytes);
+    hip_check(hipHostGetDevicePointer(&dev, ptr, 0));
+  }
+  void release() {
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = dev = nullptr;
+    bytes = 0;
+  }
+};
+
+template <class T> T *dev_of(const CoherentBuf &b, const T *host) {
+  return (T *)((uint8_t *)b.dev + ((const uint8_t *)host - (const uint8_t *)b.ptr));
+}
+
+constexpr int kServeMaxQuery = 16384;  // longest query a session takes
+// bytes per query in a record slot: the strips of the longest query, padded to 64
+constexpr int kServeQcap = ((kServeMaxQuery + 2 * kServeT1 + 63) / 64) * 64 + 64;
+constexpr double kServeLinger = 0.002;  // idle seconds before a session is closed
+constexpr double kServePairSpeed = 1.10;  // two-query strips vs one-query strips, per row
+constexpr int64_t kServeTimeoutS = 30;   // a session wave waits at most this long for work
 
 }  // namespace
 
@@ -1450,10 +1503,8 @@ struct sw_server {
   int32_t gap_open = 0, gap_extend = 0;
   int32_t max_batch = 1;
   int64_t mem_budget = 0;
-  int64_t fill_items = 0;  // inter-task work items that keep every wave slot busy
-  std::vector<ServerSlot> slots;
   std::mutex mu;
-  std::condition_variable cv;     // wakes the worker
+  std::condition_variable cv;       // wakes the worker
   std::condition_variable done_cv;  // wakes waiters
   std::deque<ServerRequest *> queue;
   std::unordered_map<uint64_t, ServerRequest *> requests;
@@ -1461,6 +1512,28 @@ struct sw_server {
   bool stop = false;
   std::thread worker;
   int64_t launches = 0, max_in_flight = 0, refused = 0;
+  int64_t records = 0, paired = 0, exact_runs = 0;
+
+  // batch mode
+  int64_t fill_items = 0;  // inter-task work items that keep every wave slot busy
+  std::vector<ServerSlot> slots;
+
+  // session mode
+  bool session_mode = false;
+  int32_t max_records = 2;  // records in flight at once
+  int32_t nrec = 0, nrows = 0, grid = 0;
+  hipStream_t sstream = nullptr;
+  hipEvent_t sended = nullptr;
+  bool open = false;        // a session launch is running
+  bool closing = false;     // its doorbell carries the closed bit
+  int32_t published = 0;    // records published in the running launch
+  double idle_since = 0;
+  int64_t timeout_ticks = 0;
+  CoherentBuf hrec, hq, hscores, hbell;  // records, query staging, score rows, doorbell + flags
+  DevBuf dmatrix, dctr, qcache, bnd;
+  std::vector<int32_t> free_rows;
+  std::deque<SessionRecord> inflight;
+  std::vector<ServerRequest *> exact_queue;  // requests waiting for the standard path
 };
 
 namespace {
@@ -1475,122 +1548,439 @@ size_t batch_bytes(const sw_db *db, const std::vector<ServerRequest *> &batch) {
   return b;
 }
 
+// Free device memory, or SIZE_MAX if it cannot be read.
+size_t device_free_bytes() {
+  size_t fr = 0, tot = 0;
+  return hipMemGetInfo(&fr, &tot) == hipSuccess ? fr : SIZE_MAX;
+}
+
+void finish_request(sw_server *sv, ServerRequest *r, int status) {
+  r->status = status;
+  r->t_done = now_s();
+  sv->done_cv.notify_all();
+}
+
+// ---- batch mode
+
 void server_finish_slot(sw_server *sv, ServerSlot &sl) {
   // called with sv->mu held, after sl.finished has completed
-  const double t = now_s();
   const size_t n = (size_t)sv->db->n_seqs;
+  // a bounded wait between the segments of a split pair that gave up leaves some scores
+  // unwritten: the whole batch fails
+  const int32_t err = *(const int32_t *)sl.host_error.ptr;
   for (size_t k = 0; k < sl.batch.size(); ++k) {
     ServerRequest *r = sl.batch[k];
-    if (n && r->scores_out)
+    if (!err && n && r->scores_out)
       std::memcpy(r->scores_out, (const int32_t *)sl.host_scores.ptr + k * n, n * 4);
-    r->status = 0;
-    r->t_done = t;
+    finish_request(sv, r, err ? SW_EDEVICE : SW_OK);
   }
   sl.batch.clear();
   sl.busy = false;
   sl.mem = 0;
-  sv->done_cv.notify_all();
+}
+
+// One pass of the batch-mode worker; returns false when the worker should wait.
+bool batch_step(sw_server *sv, int in_flight, size_t mem_in_flight, int64_t items_in_flight) {
+  // Admit queued requests into a free slot, but only while the batches in flight leave
+  // wave slots idle, and stop growing a batch once it alone fills them: a second batch
+  // running beside a device-filling one only halves the speed of both.
+  ServerSlot *free_slot = nullptr;
+  for (ServerSlot &sl : sv->slots)
+    if (!sl.busy) { free_slot = &sl; break; }
+  const int64_t per_query = std::max<int64_t>(1, sv->db->ngroups);
+  if (!free_slot || sv->queue.empty() || items_in_flight >= sv->fill_items) return false;
+  const size_t dev_free = device_free_bytes();
+  std::vector<ServerRequest *> batch;
+  while (!sv->queue.empty() && (int)batch.size() < sv->max_batch &&
+         (int64_t)batch.size() * per_query < sv->fill_items) {
+    batch.push_back(sv->queue.front());
+    const size_t need = batch_bytes(sv->db, batch);
+    if ((sv->mem_budget > 0 && (int64_t)(mem_in_flight + need) > sv->mem_budget) ||
+        need > dev_free) {
+      batch.pop_back();
+      break;
+    }
+    sv->queue.pop_front();
+  }
+  if (batch.empty()) {
+    if (in_flight > 0) return false;  // wait for memory to free up
+    // a single request larger than the budget (or the free memory) can never be admitted
+    ServerRequest *r = sv->queue.front();
+    sv->queue.pop_front();
+    ++sv->refused;
+    finish_request(sv, r, SW_ENOMEM);
+    return true;
+  }
+  ServerSlot &sl = *free_slot;
+  std::vector<uint8_t> cat;
+  std::vector<int64_t> offs(1, 0);
+  for (ServerRequest *r : batch) {
+    cat.insert(cat.end(), r->query.begin(), r->query.end());
+    offs.push_back((int64_t)cat.size());
+  }
+  if (cat.empty()) cat.push_back(0);
+  const size_t n = (size_t)sv->db->n_seqs * batch.size();
+  int rc = SW_OK;
+  try {
+    grow(sl.scores, std::max<size_t>(1, n) * 4);
+    grow_host(sl.host_scores, std::max<size_t>(1, n) * 4);
+    grow_host(sl.host_error, 4);
+    *(int32_t *)sl.host_error.ptr = 0;
+    const double t = now_s();
+    for (ServerRequest *r : batch) r->t_start = t;
+    if (n > 0) {
+      enqueue_search(sv->db, sl.w, cat.data(), offs.data(), (int64_t)batch.size(),
+                     sv->matrix.data(), sv->gap_open, sv->gap_extend, (int32_t *)sl.scores.ptr,
+                     sl.w->own, false);
+      hip_check(hipMemcpyAsync(sl.host_scores.ptr, sl.scores.ptr, n * 4, hipMemcpyDeviceToHost,
+                               sl.w->own));
+      hip_check(hipMemcpyAsync(sl.host_error.ptr, &((Counters *)sl.w->ctr.ptr)->error, 4,
+                               hipMemcpyDeviceToHost, sl.w->own));
+    }
+    hip_check(hipEventRecord(sl.finished, sl.w->own));
+  } catch (const HipFail &f) {
+    rc = map_hip(f.err);
+  } catch (const std::bad_alloc &) {
+    rc = SW_ENOMEM;
+  }
+  if (rc != SW_OK) {
+    (void)hipStreamSynchronize(sl.w->own);
+    for (ServerRequest *r : batch) finish_request(sv, r, rc);
+  } else {
+    sl.batch = std::move(batch);
+    sl.busy = true;
+    sl.mem = batch_bytes(sv->db, sl.batch);
+    sl.items = (int64_t)sl.batch.size() * per_query;
+    ++sv->launches;
+    sv->max_in_flight = std::max<int64_t>(sv->max_in_flight, in_flight + 1);
+  }
+  return true;
+}
+
+// ---- session mode
+
+int32_t *bell(sw_server *sv) { return (int32_t *)sv->hbell.ptr; }
+int32_t *complete_flags(sw_server *sv) { return (int32_t *)sv->hbell.ptr + 64; }
+int32_t *sat_flags(sw_server *sv) { return (int32_t *)sv->hbell.ptr + 64 + sv->nrec; }
+
+size_t session_device_bytes(const sw_db *db, int grid, int nrec) {
+  return (size_t)grid * db->max_ncols * 128 * 4 + (size_t)grid * 2 * kServeQcap +
+         (size_t)(64 + 2 * nrec) * 4 + (size_t)kCodes * kCodes * 4;
+}
+
+// Allocate the session's buffers (device scratch, coherent host memory for records,
+// queries, scores and flags).  Throws HipFail.
+void session_setup(sw_server *sv) {
+  sw_db *db = sv->db;
+  sv->nrec = std::max(4, 2 * sv->max_records);
+  sv->hrec.alloc((size_t)sv->nrec * sizeof(ServeRecord));
+  sv->hq.alloc((size_t)sv->nrec * 2 * kServeQcap);
+  sv->hscores.alloc((size_t)sv->nrows * db->n_seqs * 4);
+  sv->hbell.alloc((size_t)(64 + 2 * sv->nrec) * 4);
+  grow(sv->dmatrix, (size_t)db->alphabet * db->alphabet * 4);
+  hip_check(hipMemcpy(sv->dmatrix.ptr, sv->matrix.data(), sv->matrix.size() * 4,
+                      hipMemcpyHostToDevice));
+  grow(sv->dctr, (size_t)(64 + 2 * sv->nrec) * 4);
+  grow(sv->qcache, (size_t)sv->grid * 2 * kServeQcap);
+  grow(sv->bnd, (size_t)sv->grid * db->max_ncols * 128 * 4);
+  hip_check(hipStreamCreateWithFlags(&sv->sstream, hipStreamNonBlocking));
+  hip_check(hipEventCreateWithFlags(&sv->sended, hipEventDisableTiming));
+  int khz = 0;
+  hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, db->device));
+  sv->timeout_ticks = (int64_t)std::max(khz, 1) * 1000 * kServeTimeoutS;
+  for (int32_t k = sv->nrows - 1; k >= 0; --k) sv->free_rows.push_back(k);
+}
+
+void session_release(sw_server *sv) {
+  if (sv->sstream) (void)hipStreamSynchronize(sv->sstream);
+  if (sv->sended) (void)hipEventDestroy(sv->sended);
+  if (sv->sstream) (void)hipStreamDestroy(sv->sstream);
+  sv->sended = nullptr;
+  sv->sstream = nullptr;
+  for (DevBuf *b : {&sv->dmatrix, &sv->dctr, &sv->qcache, &sv->bnd}) b->release();
+  for (CoherentBuf *b : {&sv->hrec, &sv->hq, &sv->hscores, &sv->hbell}) b->release();
+}
+
+// Start a session launch (the previous one has ended).  Throws HipFail.
+void session_open(sw_server *sv) {
+  sw_db *db = sv->db;
+  std::memset(complete_flags(sv), 0, (size_t)sv->nrec * 4);
+  std::memset(sat_flags(sv), 0, (size_t)sv->nrec * 4);
+  __atomic_store_n(bell(sv), 0, __ATOMIC_RELEASE);
+  hip_check(hipMemsetAsync(sv->dctr.ptr, 0, sv->dctr.bytes, sv->sstream));
+  int32_t *c = (int32_t *)sv->dctr.ptr;
+  ServeArgs a;
+  a.packed = (const uint8_t *)db->packed.ptr;
+  a.groups = (const GroupDesc *)db->groups.ptr;
+  a.ngroups = db->ngroups;
+  a.perm = (const int32_t *)db->perm.ptr;
+  a.goe = sv->gap_open + sv->gap_extend;
+  a.ge = sv->gap_extend;
+  a.matrix = (const int32_t *)sv->dmatrix.ptr;
+  a.alphabet = db->alphabet;
+  a.nrec = sv->nrec;
+  a.qcap = kServeQcap;
+  a.records = (const ServeRecord *)sv->hrec.dev;
+  a.qstage = (const uint8_t *)sv->hq.dev;
+  a.hscores = (int32_t *)sv->hscores.dev;
+  a.doorbell = dev_of(sv->hbell, bell(sv));
+  a.complete = dev_of(sv->hbell, complete_flags(sv));
+  a.hsat = dev_of(sv->hbell, sat_flags(sv));
+  a.mirror = c + 0;
+  a.claim = c + 1;
+  a.error = c + 2;
+  a.done = c + 64;
+  a.satf = c + 64 + sv->nrec;
+  a.qcache = (uint8_t *)sv->qcache.ptr;
+  a.bnd = (uint32_t *)sv->bnd.ptr;
+  a.bnd_slot_words = (int64_t)db->max_ncols * 128;
+  a.npoll = std::min(sv->grid, 8);
+  a.pad = 0;
+  a.timeout_ticks = sv->timeout_ticks;
+  hip_check(launch_serve(a, sv->grid, sv->sstream));
+  hip_check(hipEventRecord(sv->sended, sv->sstream));
+  sv->open = true;
+  sv->closing = false;
+  sv->published = 0;
+  ++sv->launches;
+}
+
+void session_close(sw_server *sv) {
+  if (!sv->open || sv->closing) return;
+  __atomic_store_n(bell(sv), 2 * sv->published + 1, __ATOMIC_RELEASE);
+  sv->closing = true;
+}
+
+// Rows a record of queries (ma, mb) costs in the pair kernel vs as two one-query records.
+bool worth_pairing(int64_t ma, int64_t mb) {
+  auto single = [](int64_t m) { return (double)((m + 2 * kServeT1 - 1) / (2 * kServeT1)) * 2 * kServeT1; };
+  const int64_t mx = std::max(ma, mb);
+  const double paired = 2.0 * (double)((mx + kServeT2 - 1) / kServeT2) * kServeT2 / kServePairSpeed;
+  return paired < single(ma) + single(mb);
+}
+
+// Write a record for `qa` (and `qb`) into its slot and raise the doorbell.  Opens a
+// session if none is running.  Throws HipFail.
+void session_publish(sw_server *sv, ServerRequest *qa, ServerRequest *qb) {
+  if (!sv->open) session_open(sv);
+  const int32_t r = sv->published;
+  const int32_t slot = r % sv->nrec;
+  SessionRecord sr;
+  sr.r = r;
+  sr.slot = slot;
+  sr.qa = qa;
+  sr.qb = qb;
+  sr.row_a = sv->free_rows.back();
+  sv->free_rows.pop_back();
+  if (qb) {
+    sr.row_b = sv->free_rows.back();
+    sv->free_rows.pop_back();
+  }
+  const int64_t ma = (int64_t)qa->query.size(), mb = qb ? (int64_t)qb->query.size() : 0;
+  uint8_t *stage = (uint8_t *)sv->hq.ptr + (size_t)slot * 2 * kServeQcap;
+  std::memset(stage, kPadCode, (size_t)2 * kServeQcap);
+  std::memcpy(stage, qa->query.data(), (size_t)ma);
+  if (qb) std::memcpy(stage + kServeQcap, qb->query.data(), (size_t)mb);
+  ServeRecord rec;
+  rec.out_a = (int64_t)sr.row_a * sv->db->n_seqs;
+  rec.out_b = qb ? (int64_t)sr.row_b * sv->db->n_seqs : -1;
+  rec.ma = (int32_t)ma;
+  rec.mb = (int32_t)mb;
+  rec.kind = qb ? 2 : 1;
+  rec.nstrips = qb ? (int32_t)((std::max(ma, mb) + kServeT2 - 1) / kServeT2)
+                   : (int32_t)((ma + 2 * kServeT1 - 1) / (2 * kServeT1));
+  ((ServeRecord *)sv->hrec.ptr)[slot] = rec;
+  const double t = now_s();
+  qa->t_start = t;
+  if (qb) qb->t_start = t;
+  sv->published = r + 1;
+  __atomic_store_n(bell(sv), 2 * sv->published, __ATOMIC_RELEASE);
+  sv->inflight.push_back(sr);
+  ++sv->records;
+  if (qb) ++sv->paired;
+  sv->max_in_flight = std::max<int64_t>(sv->max_in_flight, (int64_t)sv->inflight.size());
+}
+
+// Hand over completed records (scores already in host memory).
+void session_collect(sw_server *sv) {
+  const size_t n = (size_t)sv->db->n_seqs;
+  while (!sv->inflight.empty()) {
+    SessionRecord &sr = sv->inflight.front();
+    if (__atomic_load_n(complete_flags(sv) + sr.slot, __ATOMIC_ACQUIRE) != sr.r + 1) break;
+    const int32_t bits = __atomic_load_n(sat_flags(sv) + sr.slot, __ATOMIC_ACQUIRE);
+    const int32_t *rows = (const int32_t *)sv->hscores.ptr;
+    ServerRequest *qs[2] = {sr.qa, sr.qb};
+    const int32_t row[2] = {sr.row_a, sr.row_b};
+    for (int h = 0; h < 2; ++h) {
+      if (!qs[h]) continue;
+      if (bits & (1 << h)) {
+        // a score at the int16 ceiling: the whole query is searched again exactly
+        qs[h]->exact = true;
+        sv->exact_queue.push_back(qs[h]);
+        continue;
+      }
+      if (n && qs[h]->scores_out) std::memcpy(qs[h]->scores_out, rows + (size_t)row[h] * n, n * 4);
+      finish_request(sv, qs[h], SW_OK);
+    }
+    sv->free_rows.push_back(sr.row_a);
+    if (sr.row_b >= 0) sv->free_rows.push_back(sr.row_b);
+    sv->inflight.pop_front();
+  }
+}
+
+// The standard search of one request, blocking, with the server lock released.
+void run_exact(sw_server *sv, std::unique_lock<std::mutex> &lk, ServerRequest *r) {
+  const int64_t qoff[2] = {0, (int64_t)r->query.size()};
+  const uint8_t z = 0;
+  lk.unlock();
+  const int rc = run_search(sv->db, r->query.empty() ? &z : r->query.data(), qoff, 1,
+                            sv->matrix.data(), sv->gap_open, sv->gap_extend, r->scores_out,
+                            nullptr, nullptr);
+  lk.lock();
+  ++sv->exact_runs;
+  finish_request(sv, r, rc);
+}
+
+// One pass of the session-mode worker (lock held); returns false when it should wait.
+bool session_step(sw_server *sv, std::unique_lock<std::mutex> &lk) {
+  if (sv->open) session_collect(sv);
+  // a launch that has ended: every record it took is complete unless a wait timed out
+  if (sv->open && hipEventQuery(sv->sended) == hipSuccess) {
+    session_collect(sv);
+    for (SessionRecord &sr : sv->inflight) {
+      if (sr.qa) finish_request(sv, sr.qa, SW_EDEVICE);
+      if (sr.qb) finish_request(sv, sr.qb, SW_EDEVICE);
+      sv->free_rows.push_back(sr.row_a);
+      if (sr.row_b >= 0) sv->free_rows.push_back(sr.row_b);
+    }
+    sv->inflight.clear();
+    sv->open = false;
+    sv->closing = false;
+    return true;
+  }
+  // requests for the standard path run once the session has drained
+  if (!sv->exact_queue.empty()) {
+    if (sv->open) {
+      session_close(sv);
+      return false;
+    }
+    ServerRequest *r = sv->exact_queue.front();
+    sv->exact_queue.erase(sv->exact_queue.begin());
+    run_exact(sv, lk, r);
+    return true;
+  }
+  if (sv->closing) return false;  // wait for the closed launch to end
+  // the launch's int32 item counter stays far from overflow: a long-running session is
+  // closed (its records still complete) and the next record opens a new one
+  if (sv->open && (int64_t)(sv->published + 1) * sv->db->ngroups + sv->grid >= ((int64_t)1 << 30)) {
+    session_close(sv);
+    return false;
+  }
+  // admit: keep at most max_records records in flight, so that requests wait here, where
+  // two of similar length can still share a record, rather than on the device
+  bool did = false;
+  while (!sv->queue.empty() && (int32_t)sv->inflight.size() < sv->max_records &&
+         sv->free_rows.size() >= 1) {
+    ServerRequest *qa = sv->queue.front();
+    if (qa->query.empty()) {
+      sv->queue.pop_front();
+      if (sv->db->n_seqs && qa->scores_out) std::memset(qa->scores_out, 0, (size_t)sv->db->n_seqs * 4);
+      qa->t_start = now_s();
+      finish_request(sv, qa, SW_OK);
+      did = true;
+      continue;
+    }
+    if ((int64_t)qa->query.size() > kServeMaxQuery) {
+      sv->queue.pop_front();
+      qa->exact = true;
+      sv->exact_queue.push_back(qa);
+      return true;
+    }
+    // the queued request of the most similar length, if sharing lanes pays
+    ServerRequest *qb = nullptr;
+    size_t qb_at = 0;
+    if (sv->max_batch >= 2 && sv->free_rows.size() >= 2) {
+      const size_t look = std::min<size_t>(sv->queue.size(), 64);
+      int64_t best = -1;
+      for (size_t k = 1; k < look; ++k) {
+        ServerRequest *c = sv->queue[k];
+        if (c->query.empty() || (int64_t)c->query.size() > kServeMaxQuery) continue;
+        const int64_t d = std::llabs((int64_t)c->query.size() - (int64_t)qa->query.size());
+        if (worth_pairing((int64_t)qa->query.size(), (int64_t)c->query.size()) &&
+            (best < 0 || d < best)) {
+          best = d;
+          qb = c;
+          qb_at = k;
+        }
+      }
+    }
+    if (qb) sv->queue.erase(sv->queue.begin() + (std::ptrdiff_t)qb_at);
+    sv->queue.pop_front();
+    try {
+      session_publish(sv, qa, qb);
+    } catch (const HipFail &f) {
+      finish_request(sv, qa, map_hip(f.err));
+      if (qb) finish_request(sv, qb, map_hip(f.err));
+    }
+    did = true;
+  }
+  // close an idle session after a short linger
+  const double t = now_s();
+  if (sv->open && sv->inflight.empty() && sv->queue.empty()) {
+    if (sv->idle_since == 0) sv->idle_since = t;
+    if (t - sv->idle_since >= kServeLinger || sv->stop) session_close(sv);
+  } else {
+    sv->idle_since = 0;
+  }
+  return did;
 }
 
 void server_loop(sw_server *sv) {
   std::unique_lock<std::mutex> lk(sv->mu);
   (void)hipSetDevice(sv->db->device);
   for (;;) {
-    // retire finished batches
-    int in_flight = 0;
-    size_t mem_in_flight = 0;
-    int64_t items_in_flight = 0;
-    for (ServerSlot &sl : sv->slots) {
-      if (sl.busy && hipEventQuery(sl.finished) == hipSuccess) server_finish_slot(sv, sl);
-      if (sl.busy) {
-        ++in_flight;
-        mem_in_flight += sl.mem;
-        items_in_flight += sl.items;
+    bool busy;
+    if (sv->session_mode) {
+      const bool progressed = session_step(sv, lk);
+      busy = sv->open || !sv->exact_queue.empty();
+      if (sv->stop && sv->queue.empty() && !busy) break;
+      if (progressed) continue;
+    } else {
+      // retire finished batches
+      int in_flight = 0;
+      size_t mem_in_flight = 0;
+      int64_t items_in_flight = 0;
+      for (ServerSlot &sl : sv->slots) {
+        if (sl.busy && hipEventQuery(sl.finished) == hipSuccess) server_finish_slot(sv, sl);
+        if (sl.busy) {
+          ++in_flight;
+          mem_in_flight += sl.mem;
+          items_in_flight += sl.items;
+        }
       }
+      if (sv->stop && sv->queue.empty() && in_flight == 0) break;
+      if (batch_step(sv, in_flight, mem_in_flight, items_in_flight)) continue;
+      busy = in_flight > 0;
     }
-    if (sv->stop && sv->queue.empty() && in_flight == 0) break;
-    // Admit queued requests into a free slot, but only while the batches in flight leave
-    // wave slots idle, and stop growing a batch once it alone fills them: on a large
-    // database one query already fills the GPU, and a second batch running beside it
-    // only halves the speed of both; on a small one several queries share a launch.
-    ServerSlot *free_slot = nullptr;
-    for (ServerSlot &sl : sv->slots)
-      if (!sl.busy) { free_slot = &sl; break; }
-    const int64_t per_query = std::max<int64_t>(1, sv->db->ngroups);
-    if (free_slot && !sv->queue.empty() && items_in_flight < sv->fill_items) {
-      std::vector<ServerRequest *> batch;
-      while (!sv->queue.empty() && (int)batch.size() < sv->max_batch &&
-             (int64_t)batch.size() * per_query < sv->fill_items) {
-        batch.push_back(sv->queue.front());
-        if (sv->mem_budget > 0 && (int64_t)(mem_in_flight + batch_bytes(sv->db, batch)) > sv->mem_budget) {
-          batch.pop_back();
-          break;
-        }
-        sv->queue.pop_front();
-      }
-      if (batch.empty() && in_flight == 0) {
-        // a single request larger than the whole budget can never be admitted
-        ServerRequest *r = sv->queue.front();
-        sv->queue.pop_front();
-        r->status = SW_ENOMEM;
-        r->t_done = now_s();
-        ++sv->refused;
-        sv->done_cv.notify_all();
-        continue;
-      }
-      if (!batch.empty()) {
-        ServerSlot &sl = *free_slot;
-        std::vector<uint8_t> cat;
-        std::vector<int64_t> offs(1, 0);
-        for (ServerRequest *r : batch) {
-          cat.insert(cat.end(), r->query.begin(), r->query.end());
-          offs.push_back((int64_t)cat.size());
-        }
-        if (cat.empty()) cat.push_back(0);
-        const size_t n = (size_t)sv->db->n_seqs * batch.size();
-        int rc = SW_OK;
-        try {
-          grow(sl.scores, std::max<size_t>(1, n) * 4);
-          grow_host(sl.host_scores, std::max<size_t>(1, n) * 4);
-          const double t = now_s();
-          for (ServerRequest *r : batch) r->t_start = t;
-          if (n > 0) {
-            enqueue_search(sv->db, sl.w, cat.data(), offs.data(), (int64_t)batch.size(),
-                           sv->matrix.data(), sv->gap_open, sv->gap_extend,
-                           (int32_t *)sl.scores.ptr, sl.w->own, false);
-            hip_check(hipMemcpyAsync(sl.host_scores.ptr, sl.scores.ptr, n * 4,
-                                     hipMemcpyDeviceToHost, sl.w->own));
-          }
-          hip_check(hipEventRecord(sl.finished, sl.w->own));
-        } catch (const HipFail &f) {
-          rc = map_hip(f.err);
-        } catch (const std::bad_alloc &) {
-          rc = SW_ENOMEM;
-        }
-        if (rc != SW_OK) {
-          (void)hipStreamSynchronize(sl.w->own);
-          for (ServerRequest *r : batch) {
-            r->status = rc;
-            r->t_done = now_s();
-          }
-          sv->done_cv.notify_all();
-        } else {
-          sl.batch = std::move(batch);
-          sl.busy = true;
-          sl.mem = batch_bytes(sv->db, sl.batch);
-          sl.items = (int64_t)sl.batch.size() * per_query;
-          ++sv->launches;
-          sv->max_in_flight = std::max<int64_t>(sv->max_in_flight, in_flight + 1);
-        }
-        continue;
-      }
-    }
-    // wait for new work or poll the batches in flight
-    if (in_flight > 0)
-      sv->cv.wait_for(lk, std::chrono::microseconds(100));
+    // wait for new work, or poll the work in flight
+    if (busy)
+      sv->cv.wait_for(lk, std::chrono::microseconds(50));
     else
       sv->cv.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
   }
+}
+
+void server_destroy(sw_server *sv) {
+  for (ServerSlot &sl : sv->slots) {
+    if (sl.w) destroy_workspace(sl.w);
+    if (sl.finished) (void)hipEventDestroy(sl.finished);
+    sl.scores.release();
+    sl.host_scores.release();
+    sl.host_error.release();
+  }
+  session_release(sv);
+  for (auto &kv : sv->requests) delete kv.second;
+  delete sv;
 }
 
 }  // namespace
@@ -1605,32 +1995,52 @@ SW_API int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open,
     return SW_EINVAL;
   sw_server *sv = new (std::nothrow) sw_server();
   if (!sv) return SW_ENOMEM;
-  sv->db = db;
-  sv->matrix.assign(matrix, matrix + (size_t)db->alphabet * db->alphabet);
-  sv->gap_open = gap_open;
-  sv->gap_extend = gap_extend;
-  sv->max_batch = max_batch;
-  {
+  try {
+    sv->db = db;
+    sv->matrix.assign(matrix, matrix + (size_t)db->alphabet * db->alphabet);
+    sv->gap_open = gap_open;
+    sv->gap_extend = gap_extend;
+    sv->max_batch = max_batch;
+    sv->mem_budget = mem_budget_bytes;
+    hip_check(hipSetDevice(db->device));
     const int per_cu = std::max(1, inter16_max_blocks_per_cu(24));
     sv->fill_items = 4LL * per_cu * std::max(1, db->num_cu);
-  }
-  sv->mem_budget = mem_budget_bytes;
-  sv->slots.resize((size_t)slots);
-  try {
-    hip_check(hipSetDevice(db->device));
-    for (ServerSlot &sl : sv->slots) {
-      sl.w = new_workspace();
-      hip_check(hipEventCreateWithFlags(&sl.finished, hipEventDisableTiming));
+    // Session mode when every record fills the device four times over and no sequence
+    // needs the intra-task kernel; its device scratch must fit the free memory and the
+    // budget, which also bounds the score rows.
+    sv->grid = std::max(1, serve_max_blocks_per_cu()) * std::max(1, db->num_cu);
+    sv->max_records = std::max(2, (int)slots);
+    sv->nrows = 2 * sv->max_records;
+    const size_t dev_bytes = session_device_bytes(db, sv->grid, std::max(4, 2 * sv->max_records));
+    const size_t row_bytes = (size_t)db->n_seqs * 4;
+    const bool fits = dev_bytes + ((size_t)1 << 30) < device_free_bytes() &&
+                      (mem_budget_bytes == 0 ||
+                       (int64_t)(dev_bytes + 2 * row_bytes) <= mem_budget_bytes);
+    sv->session_mode = db->longs.empty() && db->n_seqs > 0 &&
+                       (int64_t)db->ngroups >= 4LL * sv->grid && fits;
+    if (sv->session_mode) {
+      if (mem_budget_bytes > 0)
+        sv->nrows = (int32_t)std::max<int64_t>(
+            2, std::min<int64_t>(sv->nrows, (mem_budget_bytes - (int64_t)dev_bytes) / (int64_t)row_bytes));
+      session_setup(sv);
+    } else {
+      sv->slots.resize((size_t)slots);
+      for (ServerSlot &sl : sv->slots) {
+        sl.w = new_workspace();
+        hip_check(hipEventCreateWithFlags(&sl.finished, hipEventDisableTiming));
+      }
     }
+    sv->worker = std::thread(server_loop, sv);
   } catch (const HipFail &f) {
-    for (ServerSlot &sl : sv->slots) {
-      if (sl.finished) (void)hipEventDestroy(sl.finished);
-      if (sl.w) destroy_workspace(sl.w);
-    }
-    delete sv;
+    server_destroy(sv);
     return map_hip(f.err);
+  } catch (const std::bad_alloc &) {
+    server_destroy(sv);
+    return SW_ENOMEM;
+  } catch (...) {  // std::system_error from the worker thread
+    server_destroy(sv);
+    return SW_EDEVICE;
   }
-  sv->worker = std::thread(server_loop, sv);
   *out = sv;
   return SW_OK;
 }
@@ -1643,10 +2053,10 @@ SW_API int sw_server_submit(sw_server *sv, const uint8_t *query, int32_t query_l
   if (rc) return rc;
   ServerRequest *r = new (std::nothrow) ServerRequest();
   if (!r) return SW_ENOMEM;
-  r->query.assign(query, query + query_len);
-  r->scores_out = scores_out;
-  r->t_submit = now_s();
-  {
+  try {
+    r->query.assign(query, query + query_len);
+    r->scores_out = scores_out;
+    r->t_submit = now_s();
     std::lock_guard<std::mutex> lk(sv->mu);
     if (sv->stop) {
       delete r;
@@ -1656,6 +2066,9 @@ SW_API int sw_server_submit(sw_server *sv, const uint8_t *query, int32_t query_l
     sv->requests[r->ticket] = r;
     sv->queue.push_back(r);
     *ticket = r->ticket;
+  } catch (...) {  // std::bad_alloc
+    delete r;
+    return SW_ENOMEM;
   }
   sv->cv.notify_one();
   return SW_OK;
@@ -1687,6 +2100,16 @@ SW_API int sw_server_stats(sw_server *sv, int64_t *launches, int64_t *max_in_fli
   return SW_OK;
 }
 
+SW_API int sw_server_counters(sw_server *sv, int64_t *values, int32_t n) {
+  if (!sv || !values || n < 0) return SW_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  const int64_t v[SW_SERVER_NCOUNTERS] = {sv->launches, sv->max_in_flight, sv->refused,
+                                          sv->session_mode ? 1 : 0, sv->records, sv->paired,
+                                          sv->exact_runs};
+  for (int32_t k = 0; k < n && k < SW_SERVER_NCOUNTERS; ++k) values[k] = v[k];
+  return SW_OK;
+}
+
 SW_API void sw_server_free(sw_server *sv) {
   if (!sv) return;
   {
@@ -1696,14 +2119,7 @@ SW_API void sw_server_free(sw_server *sv) {
   sv->cv.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
   (void)hipSetDevice(sv->db->device);
-  for (ServerSlot &sl : sv->slots) {
-    if (sl.w) destroy_workspace(sl.w);
-    if (sl.finished) (void)hipEventDestroy(sl.finished);
-    sl.scores.release();
-    sl.host_scores.release();
-  }
-  for (auto &kv : sv->requests) delete kv.second;
-  delete sv;
+  server_destroy(sv);
 }
 
 // ------------------------------------------------------------------------ sorting stage

@@ -65,6 +65,12 @@ __global__ void k_profile(ProfileArgs a) {
   const uint8_t *qs = a.query + a.qoff[q];
   const int twoT = 2 * a.T;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // An empty query scores 0 against every sequence.  No DP kernel gets an item of it
+  // (the intra-task lists skip it), so its whole row is written here, before any of them
+  // runs on the stream.
+  if (d.m == 0)
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.n_seqs; e += stride)
+      a.scores[d.out + e] = 0;
   const int64_t n16 = (int64_t)d.nstrips * kCodes * twoT;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n16; e += stride) {
     const int r = (int)(e % twoT);
@@ -164,12 +170,142 @@ __device__ __forceinline__ uint32_t cell16(uint32_t hd, uint32_t sm, uint32_t &E
   return h;
 }
 
+// The strip loop of one (query, group) item of the one-query inter-task kernel (see
+// k_inter16).  The caller fills the LDS profile slice of strip s (32 codes x 2T rows,
+// code rows Inter16Lds<T>::RS bytes apart, low rows [0, T) then high rows [T, 2T)) in
+// `stage(s)`, which runs between two barriers of the single-wave workgroup.  `res`
+// points at the lane's first packed residue dword, `bnd` at its strip-boundary column 0.
+// Returns the packed running maximum of H.
+template <int T> struct Inter16Lds {
+  static constexpr int RS = 4 * T + 16;  // LDS bytes per code row; RS/16 is odd (fewer conflicts)
+  static constexpr int bytes = kCodes * RS;
+};
+
+template <int T, class Stage>
+__device__ __forceinline__ uint32_t inter16_strips(uint8_t *lds, const uint32_t *res, int ncols,
+                                                   uint32_t *bnd, int nstrips, uint32_t goe2,
+                                                   uint32_t ge2, Stage &&stage) {
+  static_assert(T % 8 == 0, "strip half-height must be a multiple of 8");
+  constexpr int RS = Inter16Lds<T>::RS;
+  const int nchunks = ncols >> 2;
+  uint32_t vmaxA = 0, vmaxB = 0;
+  for (int s = 0; s < nstrips; ++s) {
+    __syncthreads();
+    stage(s);
+    __syncthreads();
+
+    const bool first = (s == 0);
+    const bool last = (s == nstrips - 1);
+    uint32_t Hs[T], Es[T];
+#pragma unroll
+    for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
+    // low-half outputs of earlier columns, handed to the high half two columns later
+    uint32_t hA = 0, fA = 0;   // lead of the previous pair (column c - 2)
+    uint32_t hB = 0, fB = 0;   // lag of the previous pair (column c - 1)
+    uint32_t hBB = 0;          // lag of the pair before (column c - 3)
+    uint32_t hbnd_prev = 0;    // boundary H of column c - 1
+    uint32_t rwp = 0x1f1f1f1fu;  // codes of the previous 4 columns (all padding)
+
+    uint32_t rw = res[0];
+    uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+    if (!first) { b0 = bnd[0]; b1 = bnd[64]; b2 = bnd[128]; b3 = bnd[192]; }
+
+    for (int c = 0; c < nchunks; ++c) {
+      uint32_t rwn = 0, n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+      if (c + 1 < nchunks) {
+        rwn = res[(int64_t)(c + 1) * 64];
+        if (!first) {
+          const uint32_t *bp = bnd + (int64_t)(c + 1) * 256;
+          n0 = bp[0]; n1 = bp[64]; n2 = bp[128]; n3 = bp[192];
+        }
+      }
+      // the pair's codes (J, J + 1) are the low two bytes of cw, those of (J - 2, J - 1)
+      // the low two bytes of pw; boundary words of (J, J + 1) are bJ, bJ1
+      uint32_t cw = rw, pw = rwp >> 16;
+      uint32_t bJ = b0, bJ1 = b1;
+#pragma unroll 1
+      for (int p = 0; p < 2; ++p) {
+        const int J = c * 4 + 2 * p;  // lead column (low half); lag is J + 1
+        const uint32_t dJ = cw & 0xffu;
+        const uint32_t dJ1 = (cw >> 8) & 0xffu;
+        const uint32_t dJm2 = pw & 0xffu;
+        const uint32_t dJm1 = (pw >> 8) & 0xffu;
+        const uint8_t *plA = lds + dJ * RS;               // lead low rows, column J
+        const uint8_t *phA = lds + dJm2 * RS + 2 * T;     // lead high rows, column J - 2
+        const uint8_t *plB = lds + dJ1 * RS;              // lag low rows, column J + 1
+        const uint8_t *phB = lds + dJm1 * RS + 2 * T;     // lag high rows, column J - 1
+        // row-0 inputs: low half from the boundary row, high half from the low rows
+        uint32_t hdA = pack_lo(hbnd_prev, hBB);  // H(row-1, col-1)
+        uint32_t fa = pack_hl(bJ, fA);           // F entering row 0
+        uint32_t hdB = pack_lo(bJ, hA);
+        uint32_t fb = pack_hl(bJ1, fB);
+        // Row r of the lead column runs next to row r - 1 of the lag column: the lead
+        // reads Hs[r-1] (H of column J - 1) just before the lag overwrites it with
+        // column J + 1, so every row keeps one H and one E register.
+        uint32_t ha = 0, hb = 0;
+        uint32_t dA1 = hdB, dA2 = 0;  // lead H of rows r-1 and r-2 (lag diagonals)
+        uint32_t smB_prev = 0;
+#pragma unroll
+        for (int r8 = 0; r8 < T; r8 += 8) {
+          // 8 profile rows per stream: one 16-byte LDS read each
+          const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 2 * r8);
+          const uint4 A2 = *reinterpret_cast<const uint4 *>(phA + 2 * r8);
+          const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 2 * r8);
+          const uint4 B2 = *reinterpret_cast<const uint4 *>(phB + 2 * r8);
+          const uint32_t a1[4] = {A1.x, A1.y, A1.z, A1.w}, a2[4] = {A2.x, A2.y, A2.z, A2.w};
+          const uint32_t b1v[4] = {B1.x, B1.y, B1.z, B1.w}, b2v[4] = {B2.x, B2.y, B2.z, B2.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int r = r8 + q;
+            const uint32_t smA = (q & 1) ? pack_hi(a1[q >> 1], a2[q >> 1])
+                                         : pack_lo(a1[q >> 1], a2[q >> 1]);
+            const uint32_t smB = (q & 1) ? pack_hi(b1v[q >> 1], b2v[q >> 1])
+                                         : pack_lo(b1v[q >> 1], b2v[q >> 1]);
+            // lead, row r
+            const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], smA, Es[r], fa, vmaxA,
+                                      goe2, ge2);
+            // lag, row r - 1 (its diagonal is the lead's H of row r - 2)
+            if (r >= 1) Hs[r - 1] = cell16(dA2, smB_prev, Es[r - 1], fb, vmaxB, goe2, ge2);
+            dA2 = dA1;
+            dA1 = h;
+            smB_prev = smB;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        ha = dA1;
+        hb = cell16(dA2, smB_prev, Es[T - 1], fb, vmaxB, goe2, ge2);
+        Hs[T - 1] = hb;
+        // high halves finished columns J - 2 (lead) and J - 1 (lag): hand them down
+        if (!last) {
+          if (J >= 2) bnd[(int64_t)(J - 2) * 64] = pack_hi(ha, fa);
+          if (J >= 1) bnd[(int64_t)(J - 1) * 64] = pack_hi(hb, fb);
+        }
+        hBB = hB;
+        hA = ha; fA = fa;
+        hB = hb; fB = fb;
+        hbnd_prev = bJ1;
+        pw = cw;
+        cw >>= 16;
+        bJ = b2;
+        bJ1 = b3;
+      }
+      rwp = rw;
+      rw = rwn; b0 = n0; b1 = n1; b2 = n2; b3 = n3;
+    }
+    // the last two columns are padding that the high half never reaches
+    if (!last) {
+      bnd[(int64_t)(ncols - 2) * 64] = 0u;
+      bnd[(int64_t)(ncols - 1) * 64] = 0u;
+    }
+  }
+  return pk_max(vmaxA, vmaxB);
+}
+
 template <int T, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_inter16(InterArgs a) {
-  static_assert(T % 8 == 0, "strip half-height must be a multiple of 8");
-  constexpr int RS = 4 * T + 16;  // LDS bytes per code row; RS/16 is odd (fewer conflicts)
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kCodes * RS];
+  constexpr int RS = Inter16Lds<T>::RS;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[Inter16Lds<T>::bytes];
   const int lane = threadIdx.x;
   uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
   const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
@@ -190,130 +326,18 @@ void k_inter16(InterArgs a) {
     const QueryDesc qd = a.queries[qi];
     const int16_t *qp = a.qp16 + qd.qp16;
     const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
-    const int nchunks = gd.ncols >> 2;
-    uint32_t vmaxA = 0, vmaxB = 0;
-
-    for (int s = 0; s < qd.nstrips; ++s) {
-      // Stage this strip's profile slice (32 codes x 2T rows) into LDS.
-      __syncthreads();
-      {
-        const uint4 *src = reinterpret_cast<const uint4 *>(qp + (int64_t)s * kCodes * 2 * T);
-        constexpr int PER_CODE = T / 4;  // 16-byte pieces per code row
-        constexpr int PIECES = kCodes * PER_CODE;
+    // each strip's profile slice (32 codes x 2T rows) is copied into LDS
+    auto stage = [&](int s) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(qp + (int64_t)s * kCodes * 2 * T);
+      constexpr int PER_CODE = T / 4;  // 16-byte pieces per code row
+      constexpr int PIECES = kCodes * PER_CODE;
 #pragma unroll
-        for (int c = lane; c < PIECES; c += 64) {
-          const int code = c / PER_CODE, k = c - code * PER_CODE;
-          *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
-        }
+      for (int c = lane; c < PIECES; c += 64) {
+        const int code = c / PER_CODE, k = c - code * PER_CODE;
+        *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
       }
-      __syncthreads();
-
-      const bool first = (s == 0);
-      const bool last = (s == qd.nstrips - 1);
-      uint32_t Hs[T], Es[T];
-#pragma unroll
-      for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
-      // low-half outputs of earlier columns, handed to the high half two columns later
-      uint32_t hA = 0, fA = 0;   // lead of the previous pair (column c - 2)
-      uint32_t hB = 0, fB = 0;   // lag of the previous pair (column c - 1)
-      uint32_t hBB = 0;          // lag of the pair before (column c - 3)
-      uint32_t hbnd_prev = 0;    // boundary H of column c - 1
-      uint32_t rwp = 0x1f1f1f1fu;  // codes of the previous 4 columns (all padding)
-
-      uint32_t rw = res[0];
-      uint32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-      if (!first) { b0 = bnd[0]; b1 = bnd[64]; b2 = bnd[128]; b3 = bnd[192]; }
-
-      for (int c = 0; c < nchunks; ++c) {
-        uint32_t rwn = 0, n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-        if (c + 1 < nchunks) {
-          rwn = res[(int64_t)(c + 1) * 64];
-          if (!first) {
-            const uint32_t *bp = bnd + (int64_t)(c + 1) * 256;
-            n0 = bp[0]; n1 = bp[64]; n2 = bp[128]; n3 = bp[192];
-          }
-        }
-        // the pair's codes (J, J + 1) are the low two bytes of cw, those of (J - 2, J - 1)
-        // the low two bytes of pw; boundary words of (J, J + 1) are bJ, bJ1
-        uint32_t cw = rw, pw = rwp >> 16;
-        uint32_t bJ = b0, bJ1 = b1;
-#pragma unroll 1
-        for (int p = 0; p < 2; ++p) {
-          const int J = c * 4 + 2 * p;  // lead column (low half); lag is J + 1
-          const uint32_t dJ = cw & 0xffu;
-          const uint32_t dJ1 = (cw >> 8) & 0xffu;
-          const uint32_t dJm2 = pw & 0xffu;
-          const uint32_t dJm1 = (pw >> 8) & 0xffu;
-          const uint8_t *plA = lds + dJ * RS;               // lead low rows, column J
-          const uint8_t *phA = lds + dJm2 * RS + 2 * T;     // lead high rows, column J - 2
-          const uint8_t *plB = lds + dJ1 * RS;              // lag low rows, column J + 1
-          const uint8_t *phB = lds + dJm1 * RS + 2 * T;     // lag high rows, column J - 1
-          // row-0 inputs: low half from the boundary row, high half from the low rows
-          uint32_t hdA = pack_lo(hbnd_prev, hBB);  // H(row-1, col-1)
-          uint32_t fa = pack_hl(bJ, fA);           // F entering row 0
-          uint32_t hdB = pack_lo(bJ, hA);
-          uint32_t fb = pack_hl(bJ1, fB);
-          // Row r of the lead column runs next to row r - 1 of the lag column: the lead
-          // reads Hs[r-1] (H of column J - 1) just before the lag overwrites it with
-          // column J + 1, so every row keeps one H and one E register.
-          uint32_t ha = 0, hb = 0;
-          uint32_t dA1 = hdB, dA2 = 0;  // lead H of rows r-1 and r-2 (lag diagonals)
-          uint32_t smB_prev = 0;
-#pragma unroll
-          for (int r8 = 0; r8 < T; r8 += 8) {
-            // 8 profile rows per stream: one 16-byte LDS read each
-            const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 2 * r8);
-            const uint4 A2 = *reinterpret_cast<const uint4 *>(phA + 2 * r8);
-            const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 2 * r8);
-            const uint4 B2 = *reinterpret_cast<const uint4 *>(phB + 2 * r8);
-            const uint32_t a1[4] = {A1.x, A1.y, A1.z, A1.w}, a2[4] = {A2.x, A2.y, A2.z, A2.w};
-            const uint32_t b1v[4] = {B1.x, B1.y, B1.z, B1.w}, b2v[4] = {B2.x, B2.y, B2.z, B2.w};
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              const int r = r8 + q;
-              const uint32_t smA = (q & 1) ? pack_hi(a1[q >> 1], a2[q >> 1])
-                                           : pack_lo(a1[q >> 1], a2[q >> 1]);
-              const uint32_t smB = (q & 1) ? pack_hi(b1v[q >> 1], b2v[q >> 1])
-                                           : pack_lo(b1v[q >> 1], b2v[q >> 1]);
-              // lead, row r
-              const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], smA, Es[r], fa, vmaxA,
-                                        goe2, ge2);
-              // lag, row r - 1 (its diagonal is the lead's H of row r - 2)
-              if (r >= 1) Hs[r - 1] = cell16(dA2, smB_prev, Es[r - 1], fb, vmaxB, goe2, ge2);
-              dA2 = dA1;
-              dA1 = h;
-              smB_prev = smB;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          ha = dA1;
-          hb = cell16(dA2, smB_prev, Es[T - 1], fb, vmaxB, goe2, ge2);
-          Hs[T - 1] = hb;
-          // high halves finished columns J - 2 (lead) and J - 1 (lag): hand them down
-          if (!last) {
-            if (J >= 2) bnd[(int64_t)(J - 2) * 64] = pack_hi(ha, fa);
-            if (J >= 1) bnd[(int64_t)(J - 1) * 64] = pack_hi(hb, fb);
-          }
-          hBB = hB;
-          hA = ha; fA = fa;
-          hB = hb; fB = fb;
-          hbnd_prev = bJ1;
-          pw = cw;
-          cw >>= 16;
-          bJ = b2;
-          bJ1 = b3;
-        }
-        rwp = rw;
-        rw = rwn; b0 = n0; b1 = n1; b2 = n2; b3 = n3;
-      }
-      // the last two columns are padding that the high half never reaches
-      if (!last) {
-        bnd[(int64_t)(gd.ncols - 2) * 64] = 0u;
-        bnd[(int64_t)(gd.ncols - 1) * 64] = 0u;
-      }
-    }
-
-    const uint32_t vmax = pk_max(vmaxA, vmaxB);
+    };
+    const uint32_t vmax = inter16_strips<T>(lds, res, gd.ncols, bnd, qd.nstrips, goe2, ge2, stage);
     const int lo = (int)(int16_t)(vmax & 0xffffu);
     const int hi = (int)(int16_t)(vmax >> 16);
     const int sc = lo > hi ? lo : hi;
@@ -989,13 +1013,121 @@ __device__ __forceinline__ void inter2_finish(const Inter2Args &a, int q, int sc
   }
 }
 
+// The strip loop of one (query pair, group) item of the two-query inter-task kernel (see
+// k_inter16q2).  The caller fills the LDS slice of strip s (32 codes x T rows of packed
+// dwords, code rows Inter16q2Lds<T>::RS bytes apart) in `stage(s)`, which runs between
+// two barriers of the single-wave workgroup.  Returns the packed running maximum of H.
+template <int T> struct Inter16q2Lds {
+  // LDS bytes per code row: an odd number of 16-byte units (fewer bank conflicts)
+  static constexpr int RS = (T / 4) % 2 == 1 ? 4 * T : 4 * T + 16;
+  static constexpr int bytes = kCodes * RS;
+};
+
+template <int T, class Stage>
+__device__ __forceinline__ uint32_t inter16q2_strips(uint8_t *lds, const uint32_t *res, int ncols,
+                                                     uint32_t *bnd, int nstrips, uint32_t goe2,
+                                                     uint32_t ge2, Stage &&stage) {
+  static_assert(T % 4 == 0, "strip height must be a multiple of 4");
+  constexpr int RS = Inter16q2Lds<T>::RS;
+  const int nchunks = ncols >> 2;
+  uint32_t vmaxA = 0, vmaxB = 0;
+  for (int s = 0; s < nstrips; ++s) {
+    __syncthreads();
+    stage(s);
+    __syncthreads();
+
+    const bool first = (s == 0);
+    const bool last = (s == nstrips - 1);
+    uint32_t Hs[T], Es[T];
+#pragma unroll
+    for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
+    uint32_t hprev = 0;  // boundary H pair of the column before the lead
+    uint32_t rw = res[0];
+    uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+    if (!first) {
+      h0 = bnd[0]; h1 = bnd[128]; h2 = bnd[256]; h3 = bnd[384];
+      f0 = bnd[64]; f1 = bnd[192]; f2 = bnd[320]; f3 = bnd[448];
+    }
+
+    for (int c = 0; c < nchunks; ++c) {
+      uint32_t rwn = 0, nh0 = 0, nh1 = 0, nh2 = 0, nh3 = 0, nf0 = 0, nf1 = 0, nf2 = 0, nf3 = 0;
+      if (c + 1 < nchunks) {
+        rwn = res[(int64_t)(c + 1) * 64];
+        if (!first) {
+          const uint32_t *bp = bnd + (int64_t)(c + 1) * 512;
+          nh0 = bp[0]; nh1 = bp[128]; nh2 = bp[256]; nh3 = bp[384];
+          nf0 = bp[64]; nf1 = bp[192]; nf2 = bp[320]; nf3 = bp[448];
+        }
+      }
+      // codes of the pair's columns (J, J + 1) in the low two bytes of cw; boundary
+      // words of those columns in hJ, hJ1 (H pairs) and fJ, fJ1 (F pairs)
+      uint32_t cw = rw;
+      uint32_t hJ = h0, hJ1 = h1, fJ = f0, fJ1 = f1;
+#pragma unroll 1
+      for (int p = 0; p < 2; ++p) {
+        const int J = c * 4 + 2 * p;  // lead column; the lag column is J + 1
+        const uint8_t *plA = lds + (cw & 0xffu) * RS;
+        const uint8_t *plB = lds + ((cw >> 8) & 0xffu) * RS;
+        // row-0 inputs from the boundary row: diagonal H and the F entering row 0
+        const uint32_t hdA = hprev;
+        uint32_t fa = fJ;
+        const uint32_t hdB = hJ;
+        uint32_t fb = fJ1;
+        // The lead runs row r next to the lag's row r - 1, as in k_inter16.
+        uint32_t dA1 = hdB, dA2 = 0;
+        uint32_t smB_prev = 0;
+#pragma unroll
+        for (int r8 = 0; r8 < T; r8 += 8) {
+          // 8 rows per block; a height that is not a multiple of 8 ends with 4
+          const bool full = r8 + 8 <= T;
+          const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 4 * r8);
+          const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 4 * r8);
+          uint4 A2 = make_uint4(0, 0, 0, 0), B2 = make_uint4(0, 0, 0, 0);
+          if (full) {
+            A2 = *reinterpret_cast<const uint4 *>(plA + 4 * r8 + 16);
+            B2 = *reinterpret_cast<const uint4 *>(plB + 4 * r8 + 16);
+          }
+          const uint32_t av[8] = {A1.x, A1.y, A1.z, A1.w, A2.x, A2.y, A2.z, A2.w};
+          const uint32_t bw[8] = {B1.x, B1.y, B1.z, B1.w, B2.x, B2.y, B2.z, B2.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            if (!full && q >= 4) break;
+            const int r = r8 + q;
+            const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], av[q], Es[r], fa, vmaxA,
+                                      goe2, ge2);
+            if (r >= 1) Hs[r - 1] = cell16(dA2, smB_prev, Es[r - 1], fb, vmaxB, goe2, ge2);
+            dA2 = dA1;
+            dA1 = h;
+            smB_prev = bw[q];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        const uint32_t ha = dA1;
+        const uint32_t hb = cell16(dA2, smB_prev, Es[T - 1], fb, vmaxB, goe2, ge2);
+        Hs[T - 1] = hb;
+        if (!last) {
+          uint32_t *bp = bnd + (int64_t)J * 128;
+          bp[0] = ha; bp[64] = fa;
+          bp[128] = hb; bp[192] = fb;
+        }
+        hprev = hJ1;
+        cw >>= 16;
+        hJ = h2; hJ1 = h3;
+        fJ = f2; fJ1 = f3;
+      }
+      rw = rwn;
+      h0 = nh0; h1 = nh1; h2 = nh2; h3 = nh3;
+      f0 = nf0; f1 = nf1; f2 = nf2; f3 = nf3;
+    }
+  }
+  return pk_max(vmaxA, vmaxB);
+}
+
 template <int T, int WPE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE)))
 void k_inter16q2(Inter2Args a) {
-  static_assert(T % 4 == 0, "strip height must be a multiple of 4");
-  // LDS bytes per code row: an odd number of 16-byte units (fewer bank conflicts)
-  constexpr int RS = (T / 4) % 2 == 1 ? 4 * T : 4 * T + 16;
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kCodes * RS];
+  constexpr int RS = Inter16q2Lds<T>::RS;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[Inter16q2Lds<T>::bytes];
   const int lane = threadIdx.x;
   uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
   const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
@@ -1013,109 +1145,19 @@ void k_inter16q2(Inter2Args a) {
     const GroupDesc gd = a.groups[g];
     const uint32_t *qp = a.qp2 + pr.qp2;
     const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
-    const int nchunks = gd.ncols >> 2;
-    uint32_t vmaxA = 0, vmaxB = 0;
-
-    for (int s = 0; s < pr.nstrips; ++s) {
-      __syncthreads();
-      {
-        const uint4 *src = reinterpret_cast<const uint4 *>(qp + (int64_t)s * kCodes * T);
-        constexpr int PER_CODE = T / 4;  // 16-byte pieces per code row
-        constexpr int PIECES = kCodes * PER_CODE;
+    // each strip's pair-profile slice (32 codes x T rows) is copied into LDS
+    auto stage = [&](int s) {
+      const uint4 *src = reinterpret_cast<const uint4 *>(qp + (int64_t)s * kCodes * T);
+      constexpr int PER_CODE = T / 4;  // 16-byte pieces per code row
+      constexpr int PIECES = kCodes * PER_CODE;
 #pragma unroll
-        for (int c = lane; c < PIECES; c += 64) {
-          const int code = c / PER_CODE, k = c - code * PER_CODE;
-          *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
-        }
+      for (int c = lane; c < PIECES; c += 64) {
+        const int code = c / PER_CODE, k = c - code * PER_CODE;
+        *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
       }
-      __syncthreads();
-
-      const bool first = (s == 0);
-      const bool last = (s == pr.nstrips - 1);
-      uint32_t Hs[T], Es[T];
-#pragma unroll
-      for (int r = 0; r < T; ++r) { Hs[r] = 0; Es[r] = 0; }
-      uint32_t hprev = 0;  // boundary H pair of the column before the lead
-      uint32_t rw = res[0];
-      uint32_t h0 = 0, h1 = 0, h2 = 0, h3 = 0, f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-      if (!first) {
-        h0 = bnd[0]; h1 = bnd[128]; h2 = bnd[256]; h3 = bnd[384];
-        f0 = bnd[64]; f1 = bnd[192]; f2 = bnd[320]; f3 = bnd[448];
-      }
-
-      for (int c = 0; c < nchunks; ++c) {
-        uint32_t rwn = 0, nh0 = 0, nh1 = 0, nh2 = 0, nh3 = 0, nf0 = 0, nf1 = 0, nf2 = 0, nf3 = 0;
-        if (c + 1 < nchunks) {
-          rwn = res[(int64_t)(c + 1) * 64];
-          if (!first) {
-            const uint32_t *bp = bnd + (int64_t)(c + 1) * 512;
-            nh0 = bp[0]; nh1 = bp[128]; nh2 = bp[256]; nh3 = bp[384];
-            nf0 = bp[64]; nf1 = bp[192]; nf2 = bp[320]; nf3 = bp[448];
-          }
-        }
-        // codes of the pair's columns (J, J + 1) in the low two bytes of cw; boundary
-        // words of those columns in hJ, hJ1 (H pairs) and fJ, fJ1 (F pairs)
-        uint32_t cw = rw;
-        uint32_t hJ = h0, hJ1 = h1, fJ = f0, fJ1 = f1;
-#pragma unroll 1
-        for (int p = 0; p < 2; ++p) {
-          const int J = c * 4 + 2 * p;  // lead column; the lag column is J + 1
-          const uint8_t *plA = lds + (cw & 0xffu) * RS;
-          const uint8_t *plB = lds + ((cw >> 8) & 0xffu) * RS;
-          // row-0 inputs from the boundary row: diagonal H and the F entering row 0
-          const uint32_t hdA = hprev;
-          uint32_t fa = fJ;
-          const uint32_t hdB = hJ;
-          uint32_t fb = fJ1;
-          // The lead runs row r next to the lag's row r - 1, as in k_inter16.
-          uint32_t dA1 = hdB, dA2 = 0;
-          uint32_t smB_prev = 0;
-#pragma unroll
-          for (int r8 = 0; r8 < T; r8 += 8) {
-            // 8 rows per block; a height that is not a multiple of 8 ends with 4
-            const bool full = r8 + 8 <= T;
-            const uint4 A1 = *reinterpret_cast<const uint4 *>(plA + 4 * r8);
-            const uint4 B1 = *reinterpret_cast<const uint4 *>(plB + 4 * r8);
-            uint4 A2 = make_uint4(0, 0, 0, 0), B2 = make_uint4(0, 0, 0, 0);
-            if (full) {
-              A2 = *reinterpret_cast<const uint4 *>(plA + 4 * r8 + 16);
-              B2 = *reinterpret_cast<const uint4 *>(plB + 4 * r8 + 16);
-            }
-            const uint32_t av[8] = {A1.x, A1.y, A1.z, A1.w, A2.x, A2.y, A2.z, A2.w};
-            const uint32_t bw[8] = {B1.x, B1.y, B1.z, B1.w, B2.x, B2.y, B2.z, B2.w};
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-              if (!full && q >= 4) break;
-              const int r = r8 + q;
-              const uint32_t h = cell16(r == 0 ? hdA : Hs[r - 1], av[q], Es[r], fa, vmaxA,
-                                        goe2, ge2);
-              if (r >= 1) Hs[r - 1] = cell16(dA2, smB_prev, Es[r - 1], fb, vmaxB, goe2, ge2);
-              dA2 = dA1;
-              dA1 = h;
-              smB_prev = bw[q];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-          }
-          const uint32_t ha = dA1;
-          const uint32_t hb = cell16(dA2, smB_prev, Es[T - 1], fb, vmaxB, goe2, ge2);
-          Hs[T - 1] = hb;
-          if (!last) {
-            uint32_t *bp = bnd + (int64_t)J * 128;
-            bp[0] = ha; bp[64] = fa;
-            bp[128] = hb; bp[192] = fb;
-          }
-          hprev = hJ1;
-          cw >>= 16;
-          hJ = h2; hJ1 = h3;
-          fJ = f2; fJ1 = f3;
-        }
-        rw = rwn;
-        h0 = nh0; h1 = nh1; h2 = nh2; h3 = nh3;
-        f0 = nf0; f1 = nf1; f2 = nf2; f3 = nf3;
-      }
-    }
-
-    const uint32_t vmax = pk_max(vmaxA, vmaxB);
+    };
+    const uint32_t vmax =
+        inter16q2_strips<T>(lds, res, gd.ncols, bnd, pr.nstrips, goe2, ge2, stage);
     if (lane < gd.count) {
       const int p = gd.first + lane;
       const int orig = a.perm[p];
@@ -1163,6 +1205,214 @@ hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s)
     case 40: return launch_inter16q2_t<40>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ------------------------------------------------------------------------ serving session
+// Continuous batching (not in the paper, whose queries run one after another): one
+// persistent launch serves every query admitted while it runs.  Work item i belongs to
+// record i / ngroups and is its group ngroups - 1 - i % ngroups (longest first), so the
+// items of a record admitted while others are on the device queue up right behind them
+// and the waves move on to it as they finish, with no launch in between.
+//
+// A record is one query (the one-query strip loop of k_inter16, strips of 2 * T1 rows) or
+// two queries of similar length sharing the lanes (the strip loop of k_inter16q2, T2
+// rows).  The host writes records and query residues into host memory and then raises a
+// doorbell (2 * records published, plus 1 once no more will come).  A wave that claims
+// an item of a record not yet published waits: workgroups [0, npoll) read the doorbell
+// over the bus and raise a device-memory mirror of it, the others read the mirror, with
+// a growing sleep between reads.  Nothing but this kernel runs on the device while a
+// session is open, so the waves build each strip's profile slice themselves, in LDS,
+// from the query residues (copied once per record into a per-wave cache) and the
+// substitution matrix (kept in LDS), and write scores straight into host memory.  The
+// wave that finishes a record's last item publishes its completion (and whether any
+// score reached the int16 ceiling, Section 4.2, in which case the host recomputes that
+// query exactly) with a system-scope release.
+
+// Claim the next item and wait until its record is published.  Lane 0 only.  Returns
+// the item, or -1 once the session is closed before the item's record came, or when the
+// wait timed out (then the error flag is set).
+__device__ int serve_claim(const ServeArgs &a) {
+  const int item = atomicAdd(a.claim, 1);
+  const int need = item / a.ngroups + 1;  // records that must be published
+  const bool poller = (int)blockIdx.x < a.npoll;
+  const int64_t t0 = wall_clock64();
+  int backoff = 1;
+  for (;;) {
+    int v;
+    if (poller) {
+      v = __hip_atomic_load(a.doorbell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      __hip_atomic_fetch_max(a.mirror, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      v = __hip_atomic_load(a.mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((v >> 1) >= need) return item;
+    if (v & 1) return -1;  // closed: this record will never be published
+    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return -1;
+    if (wall_clock64() - t0 > a.timeout_ticks) {
+      __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return -1;
+    }
+    for (int k = 0; k < backoff; ++k) __builtin_amdgcn_s_sleep(127);
+    if (backoff < 16) backoff += 1;
+  }
+}
+
+template <int T1, int T2>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void k_serve(ServeArgs a) {
+  constexpr int RS1 = Inter16Lds<T1>::RS, RS2 = Inter16q2Lds<T2>::RS;
+  constexpr int LB = Inter16Lds<T1>::bytes > Inter16q2Lds<T2>::bytes ? Inter16Lds<T1>::bytes
+                                                                     : Inter16q2Lds<T2>::bytes;
+  static_assert(2 * T1 <= 64 && T2 <= 64, "a strip's residues fit one 64-byte row");
+  __shared__ __attribute__((aligned(16))) uint8_t lds[LB];
+  __shared__ int16_t smat[kCodes * kCodes];  // [query code][database code]
+  __shared__ __attribute__((aligned(16))) uint8_t sres[2][64];  // residues of one strip
+  __shared__ int s_item;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < kCodes * kCodes; e += 64) {
+    const int d = e >> 5, c = e & 31;
+    smat[e] = (int16_t)((d < a.alphabet && c < a.alphabet) ? a.matrix[d * a.alphabet + c]
+                                                           : kPadScore);
+  }
+  uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
+  uint8_t *qc = a.qcache + (int64_t)blockIdx.x * 2 * a.qcap;
+  const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
+  const uint32_t ge2 = (uint32_t)a.ge * 0x10001u;
+  int cur = -1;  // record whose queries are in this wave's cache
+  int64_t out_a = 0, out_b = -1;
+  int ma = 0, mb = 0, kind = 1, nstrips = 0;
+
+  for (;;) {
+    __syncthreads();
+    if (lane == 0) s_item = serve_claim(a);
+    __syncthreads();
+    const int item = s_item;
+    if (item < 0) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the record was written before the doorbell
+    const int r = item / a.ngroups;
+    const int g = a.ngroups - 1 - (item - r * a.ngroups);
+    const int slot = r % a.nrec;
+    if (r != cur) {
+      // a new record: its descriptor, then both queries into this wave's cache
+      const int32_t *rw = reinterpret_cast<const int32_t *>(a.records + slot);
+      constexpr int NW = (int)(sizeof(ServeRecord) / 4);
+      const int v = lane < NW ? __hip_atomic_load(rw + lane, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_SYSTEM) : 0;
+      const uint32_t oa_lo = (uint32_t)__builtin_amdgcn_readlane(v, 0);
+      const uint32_t oa_hi = (uint32_t)__builtin_amdgcn_readlane(v, 1);
+      const uint32_t ob_lo = (uint32_t)__builtin_amdgcn_readlane(v, 2);
+      const uint32_t ob_hi = (uint32_t)__builtin_amdgcn_readlane(v, 3);
+      out_a = (int64_t)(((uint64_t)oa_hi << 32) | oa_lo);
+      out_b = (int64_t)(((uint64_t)ob_hi << 32) | ob_lo);
+      ma = __builtin_amdgcn_readlane(v, 4);
+      mb = __builtin_amdgcn_readlane(v, 5);
+      kind = __builtin_amdgcn_readlane(v, 6);
+      nstrips = __builtin_amdgcn_readlane(v, 7);
+      const uint32_t *src = reinterpret_cast<const uint32_t *>(a.qstage + (int64_t)slot * 2 * a.qcap);
+      uint32_t *dst = reinterpret_cast<uint32_t *>(qc);
+      // every row the strips read, padding included (the staging is padded that far)
+      const int nbytes = (nstrips * (kind == 1 ? 2 * T1 : T2) + 63) & ~63;
+      const int na = nbytes >> 2, nbq = kind == 1 ? 0 : nbytes >> 2;
+      const int qw = a.qcap >> 2;
+      // (bus reads that bypass the caches: the slot held other queries before)
+      for (int k = lane; k < na; k += 64)
+        dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      for (int k = lane; k < nbq; k += 64)
+        dst[qw + k] = __hip_atomic_load(src + qw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      // the copy must be visible to every lane's later reads of the cache
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      cur = r;
+    }
+    const GroupDesc gd = a.groups[g];
+    const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
+    uint32_t vmax;
+    if (kind == 1) {
+      // strip s: rows [s * 2T1, (s + 1) * 2T1) of query a, as int16 row pairs per code
+      auto stage = [&](int s) {
+        constexpr int ROWS = 2 * T1;
+        if (lane < ROWS / 4)
+          *reinterpret_cast<uint32_t *>(&sres[0][4 * lane]) =
+              reinterpret_cast<const uint32_t *>(qc + (int64_t)s * ROWS)[lane];
+        __syncthreads();
+        constexpr int DW = kCodes * ROWS / 2;  // dwords of the slice
+#pragma unroll
+        for (int w = lane; w < DW; w += 64) {
+          const int code = w / (ROWS / 2), rp = w - code * (ROWS / 2);
+          const uint32_t lo = (uint16_t)smat[sres[0][2 * rp] * kCodes + code];
+          const uint32_t hi = (uint16_t)smat[sres[0][2 * rp + 1] * kCodes + code];
+          *reinterpret_cast<uint32_t *>(lds + code * RS1 + 4 * rp) = lo | (hi << 16);
+        }
+      };
+      vmax = inter16_strips<T1>(lds, res, gd.ncols, bnd, nstrips, goe2, ge2, stage);
+      const int lo = (int)(int16_t)(vmax & 0xffffu), hi = (int)(int16_t)(vmax >> 16);
+      vmax = (uint32_t)(lo > hi ? lo : hi);
+    } else {
+      // strip s: rows [s * T2, (s + 1) * T2) of both queries, packed per code and row
+      auto stage = [&](int s) {
+        if (lane < 2 * (T2 / 4)) {
+          const int q = lane >= T2 / 4, k = lane - q * (T2 / 4);
+          *reinterpret_cast<uint32_t *>(&sres[q][4 * k]) =
+              reinterpret_cast<const uint32_t *>(qc + q * a.qcap + (int64_t)s * T2)[k];
+        }
+        __syncthreads();
+        constexpr int DW = kCodes * T2;
+#pragma unroll
+        for (int w = lane; w < DW; w += 64) {
+          const int code = w / T2, rr = w - code * T2;
+          const uint32_t lo = (uint16_t)smat[sres[0][rr] * kCodes + code];
+          const uint32_t hi = (uint16_t)smat[sres[1][rr] * kCodes + code];
+          *reinterpret_cast<uint32_t *>(lds + code * RS2 + 4 * rr) = lo | (hi << 16);
+        }
+      };
+      vmax = inter16q2_strips<T2>(lds, res, gd.ncols, bnd, nstrips, goe2, ge2, stage);
+    }
+    int sat = 0;
+    if (lane < gd.count) {
+      const int orig = a.perm[gd.first + lane];
+      if (kind == 1) {
+        a.hscores[out_a + orig] = (int)vmax;
+        sat = (int)vmax >= kSat16 ? 1 : 0;
+      } else {
+        const int sa = (int)(int16_t)(vmax & 0xffffu), sb = (int)(int16_t)(vmax >> 16);
+        a.hscores[out_a + orig] = sa;
+        sat = sa >= kSat16 ? 1 : 0;
+        if (out_b >= 0) {
+          a.hscores[out_b + orig] = sb;
+          sat |= sb >= kSat16 ? 2 : 0;
+        }
+      }
+    }
+    // saturation bits of the wave, then the item count of the record; the wave that
+    // finishes the record's last item reports it to the host
+    for (int off = 32; off > 0; off >>= 1) sat |= __shfl_xor(sat, off);
+    if (lane == 0) {
+      if (sat) __hip_atomic_fetch_or(a.satf + slot, sat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int old = __hip_atomic_fetch_add(a.done + slot, 1, __ATOMIC_ACQ_REL,
+                                             __HIP_MEMORY_SCOPE_SYSTEM);
+      if (old == a.ngroups - 1) {
+        const int bits = __hip_atomic_load(a.satf + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.satf + slot, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.done + slot, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.hsat + slot, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(a.complete + slot, r + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
+}
+
+int serve_max_blocks_per_cu() {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &n, k_serve<kServeT1, kServeT2>, 64, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+hipError_t launch_serve(const ServeArgs &a, int grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_serve<kServeT1, kServeT2>), dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace swmi

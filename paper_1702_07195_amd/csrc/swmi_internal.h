@@ -159,6 +159,8 @@ struct ProfileArgs {
   Counters *ctr;
   int32_t *zero;             // an int32 array cleared with the counters (segment progress)
   int64_t nzero;
+  int32_t *scores;           // score rows (QueryDesc::out); an empty query's row is zeroed
+  int64_t n_seqs;            // scores per row
 };
 
 struct Profile2Args {
@@ -179,6 +181,53 @@ struct PackArgs {
   const GroupDesc *groups;
   int32_t ngroups;
   uint8_t *packed;
+};
+
+// ---- Serving session (continuous batching): one persistent launch whose work list grows
+// while it runs.  The host appends records (one query, or two queries sharing the lanes)
+// and publishes them through a doorbell in host memory; work item i is group
+// ngroups - 1 - (i % ngroups) of record i / ngroups, so a record's items follow those of
+// the records published before it.
+
+// One admitted unit of work, in host memory (record r lives in slot r % nrec).
+struct ServeRecord {
+  int64_t out_a;     // element offset of query a's score row in the host score arena
+  int64_t out_b;     // query b's row, or -1 (one query per lane)
+  int32_t ma, mb;    // query lengths (mb = 0 without query b)
+  int32_t kind;      // 1: one query per lane (strips of 2 * T1 rows); 2: two per lane (T2 rows)
+  int32_t nstrips;   // strips of the record's kind
+};
+
+struct ServeArgs {
+  const uint8_t *packed;
+  const GroupDesc *groups;
+  int32_t ngroups;
+  const int32_t *perm;          // sorted position -> caller's index
+  int32_t goe, ge;
+  const int32_t *matrix;        // device, alphabet x alphabet
+  int32_t alphabet;
+  int32_t nrec;                 // record slots
+  int32_t qcap;                 // bytes per query in a slot (a multiple of 64)
+  const ServeRecord *records;   // host, nrec records
+  const uint8_t *qstage;        // host, per slot: query a at [0, qcap), query b at [qcap, 2 qcap),
+                                // each padded with kPadCode to a multiple of 64 bytes
+  int32_t *hscores;             // host, score rows
+  const int32_t *doorbell;      // host: 2 * (records published) + (1 once closed)
+  int32_t *complete;            // host, per slot: r + 1 once record r is complete
+  int32_t *hsat;                // host, per slot: saturation bits of the completed record
+                                // (1: query a, 2: query b), written before `complete`
+  int32_t *mirror;              // device: largest doorbell value a polling wave has seen
+  int32_t *claim;               // device: next work item
+  int32_t *done;                // device, per slot: items finished
+  int32_t *satf;                // device, per slot: saturation bits so far
+  int32_t *error;               // device: set when a wait timed out
+  uint8_t *qcache;              // device, per wave: 2 * qcap bytes (the current record's queries)
+  uint32_t *bnd;                // strip-boundary scratch, one slot per wave
+  int64_t bnd_slot_words;       // dwords per slot (>= 128 * widest group's columns)
+  int32_t npoll;                // workgroups [0, npoll) read the host doorbell; the others
+                                // read its device mirror
+  int32_t pad;
+  int64_t timeout_ticks;        // wall-clock ticks a wave waits for work before giving up
 };
 
 // Top-k selection state (device memory); prefix/remaining start at 0/k, count at 0.
@@ -208,6 +257,10 @@ hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s);
 hipError_t launch_profile2(const Profile2Args &a, hipStream_t s);
 hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s);
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s);
+hipError_t launch_serve(const ServeArgs &a, int grid, hipStream_t s);
+int serve_max_blocks_per_cu();
+constexpr int kServeT1 = 24;  // strip half-height of one-query records
+constexpr int kServeT2 = 28;  // strip height of two-query records
 
 // Strip heights compiled for the inter-task kernel, and band rows per lane for the
 // intra-task kernel.

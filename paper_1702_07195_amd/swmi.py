@@ -44,7 +44,20 @@ SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_asy
            "sw_search_batch", "sw_strerror", "sw_timing_enable", "sw_timing_read",
            "sw_timing_read_kernel", "sw_set_knob", "sw_get_knob", "sw_plan_create",
            "sw_plan_launch", "sw_plan_free", "sw_server_create", "sw_server_submit",
-           "sw_server_wait", "sw_server_stats", "sw_server_free", "sw_topk")
+           "sw_server_wait", "sw_server_stats", "sw_server_counters", "sw_server_free",
+           "sw_topk")
+
+# sw_server_counters indices
+SW_SC_LAUNCHES = 0
+SW_SC_MAX_IN_FLIGHT = 1
+SW_SC_REFUSED = 2
+SW_SC_SESSION_MODE = 3
+SW_SC_RECORDS = 4
+SW_SC_PAIRED = 5
+SW_SC_EXACT_RUNS = 6
+SW_SERVER_NCOUNTERS = 7
+SW_SC_NAMES = ("launches", "max_in_flight", "refused", "session_mode", "records", "paired",
+               "exact_runs")
 
 SW_KERNEL_INTER16 = 0
 SW_KERNEL_INTRA_LONG = 1
@@ -121,6 +134,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_double)]
         L.sw_server_stats.restype = ctypes.c_int
         L.sw_server_stats.argtypes = [_vp, _i64p, _i64p, _i64p]
+        L.sw_server_counters.restype = ctypes.c_int
+        L.sw_server_counters.argtypes = [_vp, _i64p, ctypes.c_int32]
         L.sw_server_free.restype = None
         L.sw_server_free.argtypes = [_vp]
         L.sw_topk.restype = ctypes.c_int
@@ -155,6 +170,25 @@ def _i32(a):
 def _i64(a):
     a = np.ascontiguousarray(a, dtype=np.int64)
     return a, a.ctypes.data_as(_i64p)
+
+
+def _dev_i32(t, need: int, where: str) -> int:
+    """Device address of an int32 tensor that can hold ``need`` scores, after checking
+    that it is int32, on the GPU, contiguous and large enough (the library writes
+    ``need`` elements there, so anything else would be an out-of-bounds device write)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{where}: scores_dev must be a torch tensor")
+    if t.dtype != torch.int32:
+        raise ValueError(f"{where}: scores_dev must be int32, not {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{where}: scores_dev must be on the GPU, not {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{where}: scores_dev must be contiguous")
+    if t.numel() < need:
+        raise ValueError(f"{where}: scores_dev holds {t.numel()} elements, {need} needed")
+    return int(t.data_ptr())
 
 
 def set_knob(knob: int, value: int):
@@ -226,8 +260,9 @@ class SwDb:
         q, pq = _u8(query)
         m, pm = _i32(matrix)
         sptr = 0 if stream is None else int(stream.cuda_stream)
+        dptr = _dev_i32(scores_dev, self.n_seqs, "sw_search_async")
         rc = lib().sw_search_async(self.handle, pq, len(q), pm, int(gap_open), int(gap_extend),
-                                   _vp(scores_dev.data_ptr()), _vp(sptr))
+                                   _vp(dptr), _vp(sptr))
         _check(rc, "sw_search_async")
 
     def search_batch(self, queries, matrix, gap_open: int, gap_extend: int) -> np.ndarray:
@@ -260,9 +295,9 @@ class SwDb:
         o, po = _i64(offs)
         m, pm = _i32(matrix)
         handle = _vp()
+        dptr = _dev_i32(scores_dev, len(qs) * self.n_seqs, "sw_plan_create")
         rc = lib().sw_plan_create(self.handle, pc, po, len(qs), pm, int(gap_open),
-                                  int(gap_extend), _vp(scores_dev.data_ptr()),
-                                  ctypes.byref(handle))
+                                  int(gap_extend), _vp(dptr), ctypes.byref(handle))
         _check(rc, "sw_plan_create")
         return SwPlan(handle, self, scores_dev)
 
@@ -273,7 +308,8 @@ class SwDb:
         sc = np.zeros(k, dtype=np.int32)
         nh = ctypes.c_int32(0)
         sptr = 0 if stream is None else int(stream.cuda_stream)
-        rc = lib().sw_topk(self.handle, _vp(scores_dev.data_ptr()), int(k),
+        dptr = _dev_i32(scores_dev, self.n_seqs, "sw_topk")
+        rc = lib().sw_topk(self.handle, _vp(dptr), int(k),
                            idx.ctypes.data_as(_i32p), sc.ctypes.data_as(_i32p),
                            ctypes.byref(nh), _vp(sptr))
         _check(rc, "sw_topk")
@@ -360,6 +396,13 @@ class SwServer:
         _check(lib().sw_server_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
                "sw_server_stats")
         return {"launches": a.value, "max_in_flight": b.value, "refused": c.value}
+
+    def counters(self) -> dict:
+        """Every counter of sw_server_counters, by name."""
+        v = np.zeros(len(SW_SC_NAMES), dtype=np.int64)
+        _check(lib().sw_server_counters(self._h, v.ctypes.data_as(_i64p), len(v)),
+               "sw_server_counters")
+        return {k: int(x) for k, x in zip(SW_SC_NAMES, v)}
 
     def free(self):
         if self._h is not None and self._h.value:

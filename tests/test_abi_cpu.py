@@ -188,3 +188,15 @@ def test_binding_constants_match_the_header():
     for name, expr in defs.items():
         assert hasattr(swmi, name), name
         assert getattr(swmi, name) == eval(expr), name  # literal integers and shifts only
+
+
+def test_binding_refuses_bad_score_tensors_before_calling_the_library():
+    # the checks run before any library call, so they need no GPU: a tensor of the wrong
+    # type or on the host is refused with ValueError
+    import torch
+    with pytest.raises(ValueError):
+        swmi._dev_i32(np.zeros(4, np.int32), 4, "t")
+    with pytest.raises(ValueError):
+        swmi._dev_i32(torch.zeros(4, dtype=torch.int64), 4, "t")
+    with pytest.raises(ValueError):
+        swmi._dev_i32(torch.zeros(4, dtype=torch.int32), 4, "t")

@@ -167,6 +167,53 @@ def test_empty_cases():
         assert np.array_equal(got, _oracle(synth.encode("CDEF"), db, synth.BLOSUM62, 10, 2))
 
 
+def test_empty_query_after_a_search_scores_zero():
+    # An empty query scores 0 against every sequence, also against sequences that the
+    # search routes to the intra-task kernel (groups longer than 64 residues on a small
+    # database) or that the database keeps for it (longer than 8192), and also right
+    # after a search that left other scores in the pooled buffers; alone, in a batch and
+    # asynchronously.
+    import torch
+    rng = np.random.Generator(np.random.PCG64(97))
+    lengths = np.concatenate([[10, 100, 500, 9000, 20, 70, 8500],
+                              rng.integers(1, 300, 150)])
+    db = synth.db_from_lengths(rng, lengths)
+    q = synth.residues(rng, 200)
+    empty = np.zeros(0, np.uint8)
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        _say("search, then an empty query")
+        want = h.search(q, synth.BLOSUM62, 10, 2)
+        assert want.max() > 0
+        assert not h.search(empty, synth.BLOSUM62, 10, 2).any()
+        _say("batch with an empty query")
+        got = h.search_batch([q, empty, q[:50]], synth.BLOSUM62, 10, 2)
+        assert np.array_equal(got[0], want) and not got[1].any()
+        _say("async empty query into a buffer holding other scores")
+        out = torch.full((db.n_seqs,), 5, dtype=torch.int32, device="cuda")
+        h.search_async(empty, synth.BLOSUM62, 10, 2, out)
+        torch.cuda.synchronize()
+        assert not out.cpu().numpy().any()
+    assert np.array_equal(want, _oracle(q, db, synth.BLOSUM62, 10, 2))
+    assert np.array_equal(got[2], _oracle(q[:50], db, synth.BLOSUM62, 10, 2))
+
+
+def test_device_buffers_are_checked_by_the_binding(small_db, small_handle):
+    # a wrong score tensor is refused before the library could write out of bounds
+    import torch
+    q = synth.encode("ACDEFGH")
+    for bad in (torch.zeros(small_db.n_seqs, dtype=torch.int64, device="cuda"),
+                torch.zeros(small_db.n_seqs - 1, dtype=torch.int32, device="cuda"),
+                torch.zeros(2 * small_db.n_seqs, dtype=torch.int32, device="cuda")[::2],
+                torch.zeros(small_db.n_seqs, dtype=torch.int32)):
+        with pytest.raises(ValueError):
+            small_handle.search_async(q, synth.BLOSUM62, 10, 2, bad)
+        with pytest.raises(ValueError):
+            small_handle.topk(bad, 5)
+    with pytest.raises(ValueError):
+        small_handle.plan([q, q], synth.BLOSUM62, 10, 2,
+                          torch.zeros(small_db.n_seqs, dtype=torch.int32, device="cuda"))
+
+
 def test_bad_search_arguments(small_handle):
     with pytest.raises(swmi.SwError) as e:
         small_handle.search(np.array([0, 40], np.uint8), synth.BLOSUM62, 10, 2)
@@ -446,29 +493,6 @@ def test_automatic_rows_with_very_long_sequences():
             assert np.array_equal(h.search(q, synth.BLOSUM62, 10, 2), w), len(q)
         _say("automatic rows per lane, batch")
         assert np.array_equal(h.search_batch(qs, synth.BLOSUM62, 10, 2), np.stack(want))
-
-
-def test_server_runs_one_query_per_launch_when_it_fills_the_device():
-    # 1,000,000 sequences are 15,625 groups of 64: one query's work items fill every
-    # wave slot (256 CUs x 12 waves) more than four times over, so the server neither
-    # batches nor overlaps launches.
-    rng = np.random.Generator(np.random.PCG64(61))
-    db = synth.db_from_lengths(rng, synth.lognormal_lengths(rng, 1_000_000, 30, 0.5, 5, 100))
-    qs = [synth.residues(rng, m) for m in (40, 75, 60, 90, 55, 70)]
-    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
-        alone = [h.search(q, synth.BLOSUM62, 10, 2) for q in qs]
-        _say("server on a device-filling database")
-        with swmi.SwServer(h, synth.BLOSUM62, 10, 2, slots=2, max_batch=4) as sv:
-            tickets = [sv.submit(q) for q in qs]
-            results = [sv.wait(t) for t in tickets]
-            st = sv.stats()
-    assert st["launches"] == len(qs)
-    assert st["max_in_flight"] == 1
-    for k, (scores, _, _) in enumerate(results):
-        assert np.array_equal(scores, alone[k]), k
-    idx = np.linspace(0, db.n_seqs - 1, 40).astype(np.int64)
-    want = oracle.search(qs[0], db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
-    assert np.array_equal(alone[0][idx], want)
 
 
 @pytest.mark.parametrize("R", [0, 4, 16])
