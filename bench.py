@@ -61,8 +61,9 @@ def kernel_hash(section: str = "inter") -> str:
     return hashlib.sha256(head + (src[q2:] if q2 >= 0 else b"")).hexdigest()[:16]
 
 
-def load_traffic(path: str = TRAFFIC_FILE, section: str = "inter"):
-    """HBM bytes per launch from committed PMC runs, if taken on the current kernel."""
+def load_counters(path: str = TRAFFIC_FILE, section: str = "inter"):
+    """Per-launch figures from committed PMC runs (HBM bytes, VALU instructions), if they
+    were taken on the current kernel source; else None."""
     try:
         with open(path) as f:
             t = json.load(f)
@@ -70,7 +71,22 @@ def load_traffic(path: str = TRAFFIC_FILE, section: str = "inter"):
         return None
     if t.get("kernel_sha") != kernel_hash(section):
         return None
-    return t.get("bytes_per_launch")
+    return t
+
+
+def load_traffic(path: str = TRAFFIC_FILE, section: str = "inter"):
+    """HBM bytes per launch from committed PMC runs, if taken on the current kernel."""
+    t = load_counters(path, section)
+    return t.get("bytes_per_launch") if t else None
+
+
+def valu_issue(counters, avg_s: float):
+    """VALU issue utilisation of a launch: wave instructions x 64 lanes over the lane
+    slots of the chip (256 CUs x 64 lanes x 2.4 GHz) in the launch's average time."""
+    if not counters or not counters.get("sq_insts_valu_per_launch") or avg_s <= 0:
+        return None
+    lanes = counters["sq_insts_valu_per_launch"] * 64
+    return round(lanes / (PEAK_INT32_TOPS * 1e12 * avg_s), 3)
 
 
 def cpu_baseline(db, queries, sm, go, ge, gpu_scores, budget_cells: float):
@@ -103,12 +119,25 @@ def cpu_baseline(db, queries, sm, go, ge, gpu_scores, budget_cells: float):
         cells1 += len(q) * int(lengths[idx1].sum())
     dt1 = time.perf_counter() - t1
     return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "machine_cores": os.cpu_count(), "cpu_model": cpu_model(),
+            "cores_note": "all cores of this GPU's host share (16 threads, or every core "
+                          "if the machine has fewer)",
             "sample": f"{n} database sequences (stratified by length) x {len(queries)} "
                       f"queries, {cells:.3e} cells, {dt:.1f} s",
             "single_core": {"value": round(cells1 / dt1 / 1e9, 3), "unit": "GCUPS",
                             "sample": f"{len(idx1)} of those sequences, {cells1:.3e} cells, "
                                       f"{dt1:.1f} s"}}, exact
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 INT16_NOTE = ("achieved counts the recurrence's 10 int16 operations per cell; clamping E "
@@ -196,6 +225,18 @@ def run_searches(args, w, db, queries):
     step(per_q)
     per_query = {str(len(q)): round(len(q) * D / per_q[k] / 1e9, 1)
                  for k, q in enumerate(queries)}
+    # per-launch algorithmic cells of each kernel, query by query (same plans as timed)
+    stats = []
+    for k, q in enumerate(queries):
+        h.search_async(q, sm, go, ge, outs[k], stream)
+        stats.append(h.stats())
+    torch.cuda.synchronize()
+    # host-inclusive rate: the blocking call, scores copied to host memory
+    t = time.perf_counter()
+    for q in queries:
+        h.search(q, sm, go, ge)
+    host_s = time.perf_counter() - t
+    host_inclusive = round(sum(len(q) for q in queries) * D / host_s / 1e9, 1)
     scores = [o.cpu().numpy() for o in outs]
     # sorting stage: the 100 best hits of the last query, checked against a host sort
     h.topk(outs[-1], 100)
@@ -206,8 +247,71 @@ def run_searches(args, w, db, queries):
     order = np.lexsort((np.arange(db.n_seqs), -scores[-1].astype(np.int64)))[:len(idx)]
     topk = {"k": 100, "ms": round(topk_ms, 3),
             "exact": bool(np.array_equal(idx, order) and np.array_equal(sc, scores[-1][order]))}
+    latency = None
+    if args.workload == "plain":
+        latency = longest_pair_bound(args, db, queries, sm, go, ge, elapsed)
     h.free()
-    return elapsed, timing, per_query, scores, topk
+    return elapsed, timing, per_query, scores, topk, stats, host_inclusive, latency
+
+
+def longest_pair_bound(args, db, queries, sm, go, ge, elapsed):
+    """A search cannot end before its longest pair is swept: with the query in one band,
+    that pair alone takes (n + 63) anti-diagonal steps of a lane-to-lane dependency chain.
+    Measured by searching a database of that one sequence."""
+    import torch
+    from paper_1702_07195_amd import swmi, synth
+
+    k = int(np.argmax(db.lengths))
+    one = synth.db_from_seqs([db.seq(k)])
+    h1 = swmi.sw_db_load(one.residues, one.offsets, len(synth.ALPHABET))
+    out = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    for q in queries:
+        h1.search_async(q, sm, go, ge, out, stream)
+    torch.cuda.synchronize()
+    reps = 20
+    t = time.perf_counter()
+    for _ in range(reps):
+        for q in queries:
+            h1.search_async(q, sm, go, ge, out, stream)
+    torch.cuda.synchronize()
+    pair_ms = (time.perf_counter() - t) / reps * 1e3
+    st = h1.stats()
+    h1.free()
+    n = int(db.lengths[k])
+    search_ms = elapsed / args.steps * 1e3
+    return {"longest_sequence": n, "anti_diagonal_steps": n + 63,
+            "rows_per_lane": st["intra_rows"],
+            "longest_pair_alone_ms": round(pair_ms, 3),
+            "step_us": round(pair_ms * 1e3 / (n + 63), 4),
+            "search_ms": round(search_ms, 3),
+            "frac": round(pair_ms / search_ms, 3),
+            "note": "latency bound: the search takes frac of its time at the bound set by "
+                    "its longest pair's dependency chain"}
+
+
+def intra_roofline(stats, launches, total_ms):
+    """Roofline of the main intra-task launch from its own algorithmic cells: int32 cells
+    at the int32 peak and packed-int16 (two pairs per wave) cells at the int16 peak; frac
+    is the time that work needs at those peaks over the measured launch time."""
+    if launches <= 0 or total_ms <= 0:
+        return None
+    c32 = sum(st["cells_intra32"] for st in stats)
+    c16 = sum(st["cells_intra16"] for st in stats)
+    per = len(stats)  # launches per step (one per query)
+    avg_s = total_ms / launches / 1e3
+    c32l, c16l = c32 / per, c16 / per
+    t_peak = OPS_PER_CELL * (c32l / (PEAK_INT32_TOPS * 1e12) + c16l / (PEAK_INT16_TOPS * 1e12))
+    achieved = OPS_PER_CELL * (c32l + c16l) / avg_s / 1e12
+    peak = OPS_PER_CELL * (c32l + c16l) / t_peak / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
+            "unit": "Tops/s (int32, with packed-int16 cells at twice the rate)",
+            "frac": round(t_peak / avg_s, 3), "traffic": None,
+            "kernel": "k_intra32 (main intra-task launch)",
+            "avg_launch_ms": round(avg_s * 1e3, 3), "launches": launches,
+            "cells_int32_per_launch": int(c32l), "cells_int16_per_launch": int(c16l),
+            "note": "cells are the launch's own (query rows x residues of its pairs); the "
+                    "critical-pair launch and the inter-task kernel run beside it"}
 
 
 def bench_search(args, w, label):
@@ -216,27 +320,31 @@ def bench_search(args, w, label):
     db = w.make_db()
     queries = w.make_queries()
     D = int(db.offsets[-1])
-    elapsed, timing, per_query, scores, topk = run_searches(args, w, db, queries)
+    elapsed, timing, per_query, scores, topk, stats, host_inc, latency = \
+        run_searches(args, w, db, queries)
     cells_per_step = sum(len(q) for q in queries) * D
     gcups = cells_per_step * args.steps / elapsed / 1e9
     n16, ms16 = timing[swmi.SW_KERNEL_INTER16]
     nlo, mslo = timing[swmi.SW_KERNEL_INTRA_LONG]
-    # the dominant kernel is the one with more device time; its cells are estimated from
-    # the share of the database it covers (inter-task: all, when nothing is routed)
+    # the dominant kernel is the one with more device time, priced at its own cells
     if ms16 >= mslo:
-        roof = roofline("k_inter16", cells_per_step / len(queries), n16, ms16, True,
-                        load_traffic() if label == "full-scale plain search" else None)
-    else:
-        roof = roofline("k_intra32 (long and routed sequences)", cells_per_step / len(queries),
-                        nlo, mslo, False, None)
+        cells16 = sum(st["cells_inter16"] for st in stats) / len(stats)
+        counters = load_counters() if label == "full-scale plain search" else None
+        roof = roofline("k_inter16", cells16, n16, ms16, True,
+                        counters.get("bytes_per_launch") if counters else None)
         if roof is not None:
-            roof["note"] = ("cells counted over the whole database; the inter-task kernel "
-                            "runs concurrently on the rest")
+            roof["valu_issue"] = valu_issue(counters, roof["avg_launch_ms"] / 1e3)
+    else:
+        roof = intra_roofline(stats, nlo, mslo)
     config = {"workload": label, "db_seqs": db.n_seqs, "db_residues": D,
               "query_lengths": [len(q) for q in queries], "matrix": w.matrix,
               "gap_open": w.gap_open, "gap_extend": w.gap_extend}
     result = base_result(args, gcups, elapsed, "i16+i32", config)
     result["per_query_gcups"] = per_query
+    result["host_inclusive_gcups"] = host_inc
+    result["search_stats"] = stats
+    if latency is not None:
+        result["latency_bound"] = latency
     result["topk"] = topk
     result["roofline"] = roof
     result["kernel_ms_per_step"] = {
@@ -317,9 +425,15 @@ def bench_batched(args):
     # the algorithmic work per cell is the same 10 int16 operations)
     q2 = bool(swmi.get_knob(swmi.SW_KNOB_QUERY_PAIRS))
     kname = "k_inter16q2" if q2 else "k_inter16"
+    counters = load_counters(TRAFFIC_FILE_Q2, "inter_q2") if q2 else None
     result["roofline"] = roofline(f"{kname} (eager batch, default configuration)", cells,
                                   n16, ms16, True,
-                                  load_traffic(TRAFFIC_FILE_Q2, "inter_q2") if q2 else None)
+                                  counters.get("bytes_per_launch") if counters else None)
+    if result["roofline"] is not None:
+        # frac counts the recurrence's 10 operations per cell and can exceed the share of
+        # issue slots the kernel fills; this is that share, from the committed counters
+        result["roofline"]["valu_issue"] = valu_issue(
+            counters, result["roofline"]["avg_launch_ms"] / 1e3)
     result["graph_equals_eager"] = bool(np.array_equal(graph_scores, scores_host))
     if not args.no_cpu:
         base, exact = cpu_baseline(db, qs[:8], sm, 10, 2, list(scores_host[:8]),
@@ -342,10 +456,12 @@ def bench_served(args):
     sm, go, ge = w.matrix_values, w.gap_open, w.gap_extend
     h = swmi.sw_db_load(db.residues, db.offsets, len(synth.ALPHABET))
     rates = [float(r) for r in args.rates.split(",")]
+    counts = [int(x) for x in str(args.requests).split(",")]
+    counts = counts + [counts[-1]] * (len(rates) - len(counts))
     per_rate = {}
     check = None
     for ri, rate in enumerate(rates):
-        n = args.requests
+        n = counts[ri]
         queries = synth.served_queries(n, seed=1702_1004 + ri)
         arrivals = synth.poisson_arrivals(n, rate, seed=1702_2004 + ri)
         results = [None] * n
@@ -354,6 +470,7 @@ def bench_served(args):
             # warm the slots (workspaces) before timing
             for t in [sv.submit(queries[0]) for _ in range(args.slots)]:
                 sv.wait(t)
+            c_warm = sv.counters()
             tickets = [None] * n
             t0 = time.perf_counter()
 
@@ -370,16 +487,22 @@ def bench_served(args):
             for k in range(n):
                 results[k] = sv.wait(tickets[k])
             t_end = time.perf_counter()
-            stats = sv.stats()
+            c0 = sv.counters()
         lat = np.array([r[1] for r in results])
         cells = sum(len(q) for q in queries) * D
+        achieved = cells / (t_end - t0) / 1e9
+        # submission to completion of the first and last request: the served window
         per_rate[f"{rate:g}"] = {
             "requests": n, "p50_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "mean_queue_ms": round(float(np.mean([r[2] for r in results])), 2),
-            "achieved_gcups": round(cells / (t_end - t0) / 1e9, 1),
+            "achieved_gcups": round(achieved, 1),
             "offered_gcups": round(rate * float(np.mean([len(q) for q in queries])) * D / 1e9, 1),
-            "launches": stats["launches"], "max_batches_in_flight": stats["max_in_flight"]}
+            # served roofline: the window's algorithmic int16 operations over the peak
+            "roofline_frac": round(achieved * OPS_PER_CELL / 1e3 / PEAK_INT16_TOPS, 3),
+            "server": {k: c0[k] - (c_warm[k] if k in ("launches", "records", "paired",
+                                                      "exact_runs") else 0)
+                       for k in c0}}
         if check is None:
             # the same queries searched alone must give the same scores as in the mix
             check = all(np.array_equal(h.search(queries[k], sm, go, ge), results[k][0])
@@ -390,17 +513,24 @@ def bench_served(args):
               "rates_per_s": rates, "slots": args.slots, "max_batch": args.max_batch,
               "matrix": w.matrix, "gap_open": go, "gap_extend": ge}
     result = base_result(args, mid["achieved_gcups"], 0.0, "i16+i32", config)
-    result["steps"] = args.requests
+    result["steps"] = sum(counts[:len(rates)])
     result["ms_per_step"] = mid["p50_ms"]
     result["serving"] = per_rate
     result["alone_equals_mix"] = bool(check)
-    result["note"] = ("the server admits a queued query whenever a stream slot is free and "
-                      "the batches in flight leave wave slots idle; on this database one "
-                      "query's work items fill every wave slot, so each launch holds one "
-                      "query and the next one starts as it ends (two such launches side by "
-                      "side only slow each other); on small databases several queries share "
-                      "a launch and launches overlap")
-    result["roofline"] = None
+    result["note"] = ("continuous batching in sessions: one persistent launch serves every "
+                      "query admitted while it runs; a query arriving while others are on "
+                      "the device is published as a record whose work items queue right "
+                      "behind theirs (at most `slots` records in flight, the rest wait on the "
+                      "host, where two of similar length can share a record's lanes); "
+                      "server.launches counts session launches, server.max_in_flight the "
+                      "most records on the device at once")
+    # served roofline at the middle rate: its achieved int16 operations over the peak
+    result["roofline"] = {"bound": "alu",
+                          "achieved": round(mid["achieved_gcups"] * OPS_PER_CELL / 1e3, 2),
+                          "peak": round(PEAK_INT16_TOPS, 2), "unit": "Tops/s (int16)",
+                          "frac": mid["roofline_frac"], "traffic": None,
+                          "kernel": "k_serve (session launch)",
+                          "note": "whole served window, arrival gaps included"}
     h.free()
     return result
 
@@ -438,8 +568,9 @@ def main():
     ap.add_argument("--workload", default="full",
                     choices=["full", "plain", "long_mix", "batched", "served"])
     ap.add_argument("--rates", default="2,8,32", help="served: arrival rates per second")
-    ap.add_argument("--requests", type=int, default=48, help="served: requests per rate")
-    ap.add_argument("--slots", type=int, default=2, help="served: stream slots")
+    ap.add_argument("--requests", default="48,96,192",
+                    help="served: requests per rate (one value, or one per rate)")
+    ap.add_argument("--slots", type=int, default=2, help="served: records on the device at once (session mode) or stream slots (batch mode)")
     ap.add_argument("--max-batch", type=int, default=8, help="served: queries per launch")
     ap.add_argument("--mem-budget-gib", type=float, default=64.0,
                     help="served: device memory budget of the batches in flight")

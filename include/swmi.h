@@ -163,30 +163,47 @@ void sw_plan_free(sw_plan *plan);
  * Serving: continuous batching over a resident database (not in the paper, whose queries
  * run one after another).
  *
- * sw_server_create starts a worker thread that owns `slots` stream slots (1..16), each
- * with its own device workspace.  Queries submitted with sw_server_submit wait in a FIFO
- * queue; whenever a slot is free, the worker launches every queued query it can admit
- * (at most `max_batch`, 1..4096, and, if `mem_budget_bytes` > 0, only while the device
- * bytes of all batches in flight stay within the budget) as one batched search, so
- * requests that arrive while others are on the GPU join the next launch and run next to
- * them on the device.  A batch stops growing once its inter-task work items (database
- * groups x queries) fill every wave slot of the device four times over, and no further
- * batch is launched while the batches in flight do: on a large database each query then
- * runs alone at full speed, on a small one several share a launch.  A query that alone
- * exceeds the budget completes with SW_ENOMEM.
- * All searches use `matrix`, `gap_open` and `gap_extend` (validated as for sw_search).
- * The database must outlive the server.
+ * sw_server_create starts a worker thread that serves queries submitted with
+ * sw_server_submit, in one of two modes chosen from the database:
+ *
+ *   Session mode, for a database whose groups of 64 sequences fill the device's
+ *   persistent waves at least four times over and that holds no sequence above the
+ *   intra-task threshold (SW_KNOB_INTRA_MIN_LEN), when the session's device scratch fits
+ *   the free device memory and `mem_budget_bytes` (if > 0): one persistent kernel launch
+ *   serves every query admitted while it runs.  Queued queries become records (one
+ *   query, or two of similar length sharing the lanes of the two-query strip loop when
+ *   `max_batch` >= 2) that are appended to the running launch's work list, so a query
+ *   that arrives while others are on the device joins the same launch right behind them.
+ *   A record is published when the device is about to run out of published work, with
+ *   at most 4 x `slots` records in flight; the budget also bounds the host rows that
+ *   receive the scores.  The launch ends once the server is idle; a query longer than
+ *   16,384 residues, or one with a score at the int16 ceiling (Section 4.2), is
+ *   searched (again) by the standard path, exactly, after the launch has drained.
+ *
+ *   Batch mode, otherwise: `slots` (1..16) stream slots each own a device workspace;
+ *   whenever a slot is free, every queued query it can admit (at most `max_batch`,
+ *   1..4096, and only while the device bytes of the batches in flight fit the budget and
+ *   the free device memory) is launched as one batched search, so requests that arrive
+ *   while others are on the GPU run next to them.  A batch stops growing once its
+ *   inter-task work items fill every wave slot of the device four times over, and no
+ *   further batch is launched while the batches in flight do.
+ *
+ * A query that alone exceeds the budget completes with SW_ENOMEM.  All searches use
+ * `matrix`, `gap_open` and `gap_extend` (validated as for sw_search).  The database must
+ * outlive the server.  While a session launch runs, other searches on the same device
+ * wait for free compute units, i.e. until the server is idle.
  *
  * sw_server_submit copies the query (validated as for sw_search) and returns a ticket;
  * `scores_out` (host, int32[sw_db_size(db)]) must stay valid until sw_server_wait for
  * that ticket returns, and is fully written when the request completes.
  * sw_server_wait blocks until the request completes and returns its status (SW_OK or a
- * negative code); latency_ms (submission to completion) and queue_ms (submission to
- * launch) are filled if non-NULL.  Each ticket can be waited on once.
- * sw_server_stats reports the number of batched launches, the largest number of
- * batches in flight at once and the number of refused requests.
- * sw_server_free drains the queue, waits for the batches in flight and releases the
- * server.  Scores are identical to those of sw_search for the same query.
+ * negative code, SW_EDEVICE when a wait on the device timed out); latency_ms (submission
+ * to completion) and queue_ms (submission to launch or publication) are filled if
+ * non-NULL.  Each ticket can be waited on once.
+ * sw_server_stats reports the number of kernel launches (batches, or session launches),
+ * the largest number of batches or records in flight at once and the number of refused
+ * requests.  sw_server_free drains the queue, waits for the work in flight and releases
+ * the server.  Scores are identical to those of sw_search for the same query.
  */
 typedef struct sw_server sw_server;
 int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
@@ -200,7 +217,7 @@ int sw_server_stats(sw_server *server, int64_t *launches, int64_t *max_in_flight
 void sw_server_free(sw_server *server);
 
 /*
- * sw_server_counters -- the server's counters, written to values[0 .. min(n, 7)):
+ * sw_server_counters -- the server's counters, written to values[0 .. min(n, 9)):
  *   SW_SC_LAUNCHES      kernel launches (batch mode: batched searches; session mode:
  *                       session launches, each serving every query admitted while it ran)
  *   SW_SC_MAX_IN_FLIGHT largest number of batches (batch mode) or records (session mode)
@@ -211,6 +228,8 @@ void sw_server_free(sw_server *server);
  *   SW_SC_PAIRED        of those, records holding two queries
  *   SW_SC_EXACT_RUNS    queries served by the standard search path (a score at the int16
  *                       ceiling, or a query longer than a session takes)
+ *   SW_SC_WAVES         persistent waves of a session launch (0 in batch mode)
+ *   SW_SC_COPY_US       host microseconds spent copying session scores to the callers
  * Errors: SW_EINVAL (NULL server or values, n < 0).
  */
 #define SW_SC_LAUNCHES       0
@@ -220,7 +239,9 @@ void sw_server_free(sw_server *server);
 #define SW_SC_RECORDS        4
 #define SW_SC_PAIRED         5
 #define SW_SC_EXACT_RUNS     6
-#define SW_SERVER_NCOUNTERS  7
+#define SW_SC_WAVES          7
+#define SW_SC_COPY_US        8
+#define SW_SERVER_NCOUNTERS  9
 int sw_server_counters(sw_server *server, int64_t *values, int32_t n);
 
 /*
@@ -269,6 +290,32 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
                           double *total_ms);
 
 /*
+ * sw_search_stats -- how the latest search enqueued on the handle was laid out, written
+ * to values[0 .. min(n, 9)) (algorithmic cells count query rows x unpadded residues):
+ *   SW_ST_CELLS_INTER16  cells of the packed-int16 inter-task launch
+ *   SW_ST_CELLS_INTRA32  int32 cells of the main intra-task launch
+ *   SW_ST_CELLS_INTRA16  cells of its two-pairs-per-wave (packed int16) items
+ *   SW_ST_CELLS_CRIT     cells of the critical-pair launch (finer bands)
+ *   SW_ST_INTRA_ROWS     query rows per lane of the main intra-task launch
+ *   SW_ST_MAIN_WAVES     waves per workgroup of that launch
+ *   SW_ST_ROUTED_GROUPS  database groups routed to the intra-task kernel
+ *   SW_ST_STRIP_ROWS     strip rows of the inter-task launch
+ *   SW_ST_QUERY_PAIRS    1 if the inter-task launch ran two queries per lane
+ * Errors: SW_ENODB, SW_EINVAL (NULL values or n < 0).
+ */
+#define SW_ST_CELLS_INTER16   0
+#define SW_ST_CELLS_INTRA32   1
+#define SW_ST_CELLS_INTRA16   2
+#define SW_ST_CELLS_CRIT      3
+#define SW_ST_INTRA_ROWS      4
+#define SW_ST_MAIN_WAVES      5
+#define SW_ST_ROUTED_GROUPS   6
+#define SW_ST_STRIP_ROWS      7
+#define SW_ST_QUERY_PAIRS     8
+#define SW_SEARCH_NSTATS      9
+int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
+
+/*
  * Tuning and debug knobs (process-wide; read at the next search):
  *   SW_KNOB_INTRA_MIN_LEN  database sequences longer than this go to the intra-task
  *                          kernel (read at sw_db_load; default 8192);
@@ -307,6 +354,11 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *                          (two per compute unit); 0 (default) = 4 when the search is
  *                          estimated throughput-bound, 8 when the longest pair's
  *                          pipeline bounds it.  Scores are the same.
+ *   SW_KNOB_PRIO_COLS      inter-task work items (and serving-session items) of database
+ *                          groups at least this many columns wide run at raised wave
+ *                          priority on their SIMDs (0 = automatic: the width at which one
+ *                          wave's item takes a quarter of the launch; a value above every
+ *                          group's width turns it off).  Scores are the same.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -321,6 +373,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_KNOB_SPIN_LIMIT     11
 #define SW_KNOB_QUERY_PAIRS    12
 #define SW_KNOB_MAIN_WAVES     13
+#define SW_KNOB_PRIO_COLS      14
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

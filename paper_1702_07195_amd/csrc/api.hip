@@ -38,6 +38,18 @@ std::atomic<int64_t> g_knob_intra_pairs{1};
 std::atomic<int64_t> g_knob_spin_limit{0};
 std::atomic<int64_t> g_knob_query_pairs{1};
 std::atomic<int64_t> g_knob_main_waves{0};
+std::atomic<int64_t> g_knob_prio_cols{0};
+
+// Group width from which an inter-task item runs at raised wave priority: a wave sweeping
+// a group of ncols columns spends about 64 * ncols * waves / residues of the launch's
+// time on it (waves sharing the chip evenly), so items past a quarter of the launch start
+// first and get their SIMD's issue slots first, which keeps them off the critical path.
+int32_t prio_cols_for(int64_t residues, int64_t waves) {
+  const int64_t forced = g_knob_prio_cols.load();
+  if (forced > 0) return (int32_t)std::min<int64_t>(forced, INT32_MAX);
+  const int64_t c = residues / std::max<int64_t>(1, 256 * waves);
+  return (int32_t)std::min<int64_t>(std::max<int64_t>(c, 64), INT32_MAX);
+}
 
 struct HipFail {
   hipError_t err;
@@ -113,6 +125,8 @@ struct sw_db {
   std::vector<int32_t> hperm;       // host copy: sorted position -> caller index
   std::vector<int32_t> hlens;       // host copy: sorted position -> length
   int64_t short_residues = 0;       // residues in groups
+  std::vector<int64_t> group_res;   // residues in groups [0, g), g = 0 .. ngroups
+  int64_t last_stats[SW_SEARCH_NSTATS] = {};  // sw_search_stats of the latest search (under mu)
   std::mutex mu;
   std::vector<Workspace *> pool;
   uint64_t pool_uses = 0;
@@ -377,6 +391,7 @@ struct Plan {
   int64_t qp16_elems = 0, qp8_elems = 0;
   std::vector<QueryPair> pairs;  // two-query inter-task kernel (empty: k_inter16)
   int64_t qp2_elems = 0;         // dwords of the pair profiles
+  int64_t stats[SW_SEARCH_NSTATS] = {};  // see sw_search_stats
 };
 
 // Enqueue one (possibly batched) search on `s`.  Queries are host memory; scores go to
@@ -664,6 +679,34 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
 
   const int64_t nitems16 = (int64_t)ninter * nunits;
   p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
+  {
+    // algorithmic cells (query rows x unpadded residues) of each launch
+    int64_t sum_all = 0;
+    for (int64_t q = 0; q < nq; ++q) sum_all += lens[q];
+    auto rows_of = [&](const PairItem &it, int R) {
+      const int64_t m = lens[(size_t)it.query];
+      return std::min<int64_t>(m, (int64_t)it.band1 * 64 * R) - (int64_t)it.band0 * 64 * R;
+    };
+    int64_t c32 = 0, c16 = 0, ccrit = 0;
+    for (size_t k = 0; k < p.longitems.size(); ++k) {
+      const PairItem &it = p.longitems[k];
+      if (p.second[k].len >= 0)
+        c16 += (int64_t)(it.len + p.second[k].len) * lens[(size_t)it.query];
+      else
+        c32 += (int64_t)it.len * rows_of(it, p.R);
+    }
+    for (const PairItem &it : p.crititems) ccrit += (int64_t)it.len * rows_of(it, kCritR);
+    int64_t *st = p.stats;
+    st[SW_ST_CELLS_INTER16] = sum_all * db->group_res[(size_t)ninter];
+    st[SW_ST_CELLS_INTRA32] = c32;
+    st[SW_ST_CELLS_INTRA16] = c16;
+    st[SW_ST_CELLS_CRIT] = ccrit;
+    st[SW_ST_INTRA_ROWS] = p.R;
+    st[SW_ST_MAIN_WAVES] = p.main_waves;
+    st[SW_ST_ROUTED_GROUPS] = db->ngroups - ninter;
+    st[SW_ST_STRIP_ROWS] = p.T;
+    st[SW_ST_QUERY_PAIRS] = q2 ? 1 : 0;
+  }
   // Two waves per SIMD: one persistent 8-wave workgroup per compute unit, or two 4-wave
   // ones.  The kernel's per-step profile gathers touch one cache line per lane, and a
   // second resident 8-wave workgroup per CU (four waves per SIMD) measured slower and
@@ -876,6 +919,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.bnd_slot_words = (int64_t)bnd16_slot;
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
+      ia.prio_cols = prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
       hip_check(launch_inter16q2(ia, p.T, p.grid16, s));
     } else {
       InterArgs ia;
@@ -897,6 +941,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.bnd_slot_words = (int64_t)bnd16_slot;
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
+      ia.prio_cols = prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
       hip_check(launch_inter16(ia, p.T, p.grid16, s));
     }
     if (timed && p.grid16 > 0) {
@@ -942,6 +987,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   }
   if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
   if (p.grid_crit > 0) hip_check(hipStreamWaitEvent(s, w->join_crit, 0));
+  std::lock_guard<std::mutex> lk(db->mu);
+  std::memcpy(db->last_stats, p.stats, sizeof(p.stats));
 }
 
 int64_t total_of(const int64_t *offsets, int64_t n) { return offsets[n]; }
@@ -987,6 +1034,7 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       if (value != 0 && value != 4 && value != 8) return SW_EINVAL;
       g_knob_main_waves = value;
       return SW_OK;
+    case SW_KNOB_PRIO_COLS: if (value < 0) return SW_EINVAL; g_knob_prio_cols = value; return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -1006,6 +1054,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_SPIN_LIMIT: return g_knob_spin_limit.load();
     case SW_KNOB_QUERY_PAIRS: return g_knob_query_pairs.load();
     case SW_KNOB_MAIN_WAVES: return g_knob_main_waves.load();
+    case SW_KNOB_PRIO_COLS: return g_knob_prio_cols.load();
     default: return SW_EINVAL;
   }
 }
@@ -1068,6 +1117,12 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
     }
     db->ngroups = (int32_t)groups.size();
     for (int64_t p = 0; p < n_short; ++p) db->short_residues += len_of(order[p]);
+    db->group_res.assign(groups.size() + 1, 0);
+    for (size_t g = 0; g < groups.size(); ++g) {
+      int64_t r = 0;
+      for (int32_t l = 0; l < groups[g].count; ++l) r += len_of(order[groups[g].first + l]);
+      db->group_res[g + 1] = db->group_res[g] + r;
+    }
     std::vector<int32_t> lens((size_t)std::max<int64_t>(1, n_short));
     for (int64_t p = 0; p < n_short; ++p) lens[p] = (int32_t)len_of(order[p]);
     for (int64_t p = n_seqs - 1; p >= n_short; --p) {  // longest first
@@ -1316,6 +1371,15 @@ SW_API int sw_timing_read_kernel(const sw_db *cdb, int32_t kernel, int64_t *laun
   return SW_OK;
 }
 
+SW_API int sw_search_stats(const sw_db *cdb, int64_t *values, int32_t n) {
+  if (!cdb) return SW_ENODB;
+  if (!values || n < 0) return SW_EINVAL;
+  sw_db *db = const_cast<sw_db *>(cdb);
+  std::lock_guard<std::mutex> lk(db->mu);
+  for (int32_t k = 0; k < n && k < SW_SEARCH_NSTATS; ++k) values[k] = db->last_stats[k];
+  return SW_OK;
+}
+
 SW_API int sw_timing_read(const sw_db *db, int64_t *launches, double *total_ms) {
   return sw_timing_read_kernel(db, SW_KERNEL_INTER16, launches, total_ms);
 }
@@ -1460,6 +1524,9 @@ struct SessionRecord {
   int32_t slot = 0;
   ServerRequest *qa = nullptr, *qb = nullptr;
   int32_t row_a = -1, row_b = -1;
+  int32_t bits = 0;       // saturation bits, once complete
+  bool copying = false;   // complete on the device, rows being copied to the host
+  hipEvent_t copied = nullptr;
 };
 
 double now_s() {
@@ -1494,6 +1561,7 @@ constexpr int kServeQcap = ((kServeMaxQuery + 2 * kServeT1 + 63) / 64) * 64 + 64
 constexpr double kServeLinger = 0.002;  // idle seconds before a session is closed
 constexpr double kServePairSpeed = 1.10;  // two-query strips vs one-query strips, per row
 constexpr int64_t kServeTimeoutS = 30;   // a session wave waits at most this long for work
+constexpr size_t kServePairQueue = 4;    // queued requests from which records take pairs
 
 }  // namespace
 
@@ -1513,6 +1581,7 @@ struct sw_server {
   std::thread worker;
   int64_t launches = 0, max_in_flight = 0, refused = 0;
   int64_t records = 0, paired = 0, exact_runs = 0;
+  double copy_s = 0;  // host time spent copying session scores to the callers
 
   // batch mode
   int64_t fill_items = 0;  // inter-task work items that keep every wave slot busy
@@ -1529,8 +1598,11 @@ struct sw_server {
   int32_t published = 0;    // records published in the running launch
   double idle_since = 0;
   int64_t timeout_ticks = 0;
-  CoherentBuf hrec, hq, hscores, hbell;  // records, query staging, score rows, doorbell + flags
-  DevBuf dmatrix, dctr, qcache, bnd;
+  CoherentBuf hrec, hq, hbell;  // records, query staging, doorbell + flags
+  DevBuf dmatrix, dctr, qcache, bnd, dscores;
+  HostBuf hscores;               // pinned rows the scores are copied into
+  hipStream_t cstream = nullptr; // copies of complete records' rows
+  std::vector<hipEvent_t> free_events;
   std::vector<int32_t> free_rows;
   std::deque<SessionRecord> inflight;
   std::vector<ServerRequest *> exact_queue;  // requests waiting for the standard path
@@ -1659,13 +1731,25 @@ bool batch_step(sw_server *sv, int in_flight, size_t mem_in_flight, int64_t item
 
 // ---- session mode
 
+constexpr int kServePollers = 8;  // session workgroups that read the doorbell
+
 int32_t *bell(sw_server *sv) { return (int32_t *)sv->hbell.ptr; }
+int32_t *progress(sw_server *sv) { return (int32_t *)sv->hbell.ptr + 16; }  // kServePollers
 int32_t *complete_flags(sw_server *sv) { return (int32_t *)sv->hbell.ptr + 64; }
 int32_t *sat_flags(sw_server *sv) { return (int32_t *)sv->hbell.ptr + 64 + sv->nrec; }
 
-size_t session_device_bytes(const sw_db *db, int grid, int nrec) {
+// Items claimed so far in the running launch, as last reported by the polling waves.
+int64_t claimed_items(sw_server *sv) {
+  int64_t c = 0;
+  for (int k = 0; k < kServePollers; ++k)
+    c = std::max<int64_t>(c, __atomic_load_n(progress(sv) + k, __ATOMIC_RELAXED));
+  return c;
+}
+
+size_t session_device_bytes(const sw_db *db, int grid, int nrec, int nrows) {
   return (size_t)grid * db->max_ncols * 128 * 4 + (size_t)grid * 2 * kServeQcap +
-         (size_t)(64 + 2 * nrec) * 4 + (size_t)kCodes * kCodes * 4;
+         (size_t)(64 + 2 * nrec) * 4 + (size_t)kCodes * kCodes * 4 +
+         (size_t)nrows * db->n_seqs * 4;
 }
 
 // Allocate the session's buffers (device scratch, coherent host memory for records,
@@ -1675,7 +1759,8 @@ void session_setup(sw_server *sv) {
   sv->nrec = std::max(4, 2 * sv->max_records);
   sv->hrec.alloc((size_t)sv->nrec * sizeof(ServeRecord));
   sv->hq.alloc((size_t)sv->nrec * 2 * kServeQcap);
-  sv->hscores.alloc((size_t)sv->nrows * db->n_seqs * 4);
+  grow_host(sv->hscores, (size_t)sv->nrows * db->n_seqs * 4);
+  grow(sv->dscores, (size_t)sv->nrows * db->n_seqs * 4);
   sv->hbell.alloc((size_t)(64 + 2 * sv->nrec) * 4);
   grow(sv->dmatrix, (size_t)db->alphabet * db->alphabet * 4);
   hip_check(hipMemcpy(sv->dmatrix.ptr, sv->matrix.data(), sv->matrix.size() * 4,
@@ -1684,7 +1769,13 @@ void session_setup(sw_server *sv) {
   grow(sv->qcache, (size_t)sv->grid * 2 * kServeQcap);
   grow(sv->bnd, (size_t)sv->grid * db->max_ncols * 128 * 4);
   hip_check(hipStreamCreateWithFlags(&sv->sstream, hipStreamNonBlocking));
+  hip_check(hipStreamCreateWithFlags(&sv->cstream, hipStreamNonBlocking));
   hip_check(hipEventCreateWithFlags(&sv->sended, hipEventDisableTiming));
+  for (int32_t k = 0; k < sv->nrec; ++k) {
+    hipEvent_t e = nullptr;
+    hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    sv->free_events.push_back(e);
+  }
   int khz = 0;
   hip_check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, db->device));
   sv->timeout_ticks = (int64_t)std::max(khz, 1) * 1000 * kServeTimeoutS;
@@ -1693,12 +1784,19 @@ void session_setup(sw_server *sv) {
 
 void session_release(sw_server *sv) {
   if (sv->sstream) (void)hipStreamSynchronize(sv->sstream);
+  if (sv->cstream) (void)hipStreamSynchronize(sv->cstream);
   if (sv->sended) (void)hipEventDestroy(sv->sended);
+  for (SessionRecord &sr : sv->inflight)
+    if (sr.copied) sv->free_events.push_back(sr.copied);
+  for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
+  sv->free_events.clear();
   if (sv->sstream) (void)hipStreamDestroy(sv->sstream);
+  if (sv->cstream) (void)hipStreamDestroy(sv->cstream);
   sv->sended = nullptr;
-  sv->sstream = nullptr;
-  for (DevBuf *b : {&sv->dmatrix, &sv->dctr, &sv->qcache, &sv->bnd}) b->release();
-  for (CoherentBuf *b : {&sv->hrec, &sv->hq, &sv->hscores, &sv->hbell}) b->release();
+  sv->sstream = sv->cstream = nullptr;
+  for (DevBuf *b : {&sv->dmatrix, &sv->dctr, &sv->qcache, &sv->bnd, &sv->dscores}) b->release();
+  for (CoherentBuf *b : {&sv->hrec, &sv->hq, &sv->hbell}) b->release();
+  sv->hscores.release();
 }
 
 // Start a session launch (the previous one has ended).  Throws HipFail.
@@ -1706,6 +1804,7 @@ void session_open(sw_server *sv) {
   sw_db *db = sv->db;
   std::memset(complete_flags(sv), 0, (size_t)sv->nrec * 4);
   std::memset(sat_flags(sv), 0, (size_t)sv->nrec * 4);
+  std::memset(progress(sv), 0, (size_t)kServePollers * 4);
   __atomic_store_n(bell(sv), 0, __ATOMIC_RELEASE);
   hip_check(hipMemsetAsync(sv->dctr.ptr, 0, sv->dctr.bytes, sv->sstream));
   int32_t *c = (int32_t *)sv->dctr.ptr;
@@ -1722,10 +1821,11 @@ void session_open(sw_server *sv) {
   a.qcap = kServeQcap;
   a.records = (const ServeRecord *)sv->hrec.dev;
   a.qstage = (const uint8_t *)sv->hq.dev;
-  a.hscores = (int32_t *)sv->hscores.dev;
+  a.scores = (int32_t *)sv->dscores.ptr;
   a.doorbell = dev_of(sv->hbell, bell(sv));
   a.complete = dev_of(sv->hbell, complete_flags(sv));
   a.hsat = dev_of(sv->hbell, sat_flags(sv));
+  a.hprog = dev_of(sv->hbell, progress(sv));
   a.mirror = c + 0;
   a.claim = c + 1;
   a.error = c + 2;
@@ -1734,8 +1834,8 @@ void session_open(sw_server *sv) {
   a.qcache = (uint8_t *)sv->qcache.ptr;
   a.bnd = (uint32_t *)sv->bnd.ptr;
   a.bnd_slot_words = (int64_t)db->max_ncols * 128;
-  a.npoll = std::min(sv->grid, 8);
-  a.pad = 0;
+  a.npoll = std::min(sv->grid, kServePollers);
+  a.prio_cols = prio_cols_for(db->short_residues, sv->grid);
   a.timeout_ticks = sv->timeout_ticks;
   hip_check(launch_serve(a, sv->grid, sv->sstream));
   hip_check(hipEventRecord(sv->sended, sv->sstream));
@@ -1801,31 +1901,68 @@ void session_publish(sw_server *sv, ServerRequest *qa, ServerRequest *qb) {
   sv->max_in_flight = std::max<int64_t>(sv->max_in_flight, (int64_t)sv->inflight.size());
 }
 
-// Hand over completed records (scores already in host memory).
+// Completed records: copy their rows to pinned host memory (a DMA copy beside the
+// running kernel), then to the callers.  Records may complete out of order.  Throws
+// HipFail.
 void session_collect(sw_server *sv) {
   const size_t n = (size_t)sv->db->n_seqs;
-  while (!sv->inflight.empty()) {
-    SessionRecord &sr = sv->inflight.front();
-    if (__atomic_load_n(complete_flags(sv) + sr.slot, __ATOMIC_ACQUIRE) != sr.r + 1) break;
-    const int32_t bits = __atomic_load_n(sat_flags(sv) + sr.slot, __ATOMIC_ACQUIRE);
-    const int32_t *rows = (const int32_t *)sv->hscores.ptr;
+  for (auto it = sv->inflight.begin(); it != sv->inflight.end();) {
+    SessionRecord &sr = *it;
     ServerRequest *qs[2] = {sr.qa, sr.qb};
     const int32_t row[2] = {sr.row_a, sr.row_b};
+    if (!sr.copying) {
+      if (__atomic_load_n(complete_flags(sv) + sr.slot, __ATOMIC_ACQUIRE) != sr.r + 1) {
+        ++it;
+        continue;
+      }
+      sr.bits = __atomic_load_n(sat_flags(sv) + sr.slot, __ATOMIC_ACQUIRE);
+      for (int h = 0; h < 2; ++h)
+        if (qs[h] && !(sr.bits & (1 << h)))
+          hip_check(hipMemcpyAsync((int32_t *)sv->hscores.ptr + (size_t)row[h] * n,
+                                   (const int32_t *)sv->dscores.ptr + (size_t)row[h] * n, n * 4,
+                                   hipMemcpyDeviceToHost, sv->cstream));
+      sr.copied = sv->free_events.back();
+      sv->free_events.pop_back();
+      hip_check(hipEventRecord(sr.copied, sv->cstream));
+      sr.copying = true;
+    }
+    if (hipEventQuery(sr.copied) != hipSuccess) {
+      ++it;
+      continue;
+    }
+    const int32_t *rows = (const int32_t *)sv->hscores.ptr;
     for (int h = 0; h < 2; ++h) {
       if (!qs[h]) continue;
-      if (bits & (1 << h)) {
+      if (sr.bits & (1 << h)) {
         // a score at the int16 ceiling: the whole query is searched again exactly
         qs[h]->exact = true;
         sv->exact_queue.push_back(qs[h]);
         continue;
       }
+      const double t0 = now_s();
       if (n && qs[h]->scores_out) std::memcpy(qs[h]->scores_out, rows + (size_t)row[h] * n, n * 4);
+      sv->copy_s += now_s() - t0;
       finish_request(sv, qs[h], SW_OK);
     }
+    sv->free_events.push_back(sr.copied);
     sv->free_rows.push_back(sr.row_a);
     if (sr.row_b >= 0) sv->free_rows.push_back(sr.row_b);
-    sv->inflight.pop_front();
+    it = sv->inflight.erase(it);
   }
+}
+
+// Fail every record in flight with `status` (after the copy stream has drained).
+void session_fail(sw_server *sv, int status) {
+  if (sv->inflight.empty()) return;
+  (void)hipStreamSynchronize(sv->cstream);
+  for (SessionRecord &sr : sv->inflight) {
+    if (sr.qa) finish_request(sv, sr.qa, status);
+    if (sr.qb) finish_request(sv, sr.qb, status);
+    if (sr.copied) sv->free_events.push_back(sr.copied);
+    sv->free_rows.push_back(sr.row_a);
+    if (sr.row_b >= 0) sv->free_rows.push_back(sr.row_b);
+  }
+  sv->inflight.clear();
 }
 
 // The standard search of one request, blocking, with the server lock released.
@@ -1843,17 +1980,22 @@ void run_exact(sw_server *sv, std::unique_lock<std::mutex> &lk, ServerRequest *r
 
 // One pass of the session-mode worker (lock held); returns false when it should wait.
 bool session_step(sw_server *sv, std::unique_lock<std::mutex> &lk) {
-  if (sv->open) session_collect(sv);
-  // a launch that has ended: every record it took is complete unless a wait timed out
-  if (sv->open && hipEventQuery(sv->sended) == hipSuccess) {
+  try {
     session_collect(sv);
-    for (SessionRecord &sr : sv->inflight) {
-      if (sr.qa) finish_request(sv, sr.qa, SW_EDEVICE);
-      if (sr.qb) finish_request(sv, sr.qb, SW_EDEVICE);
-      sv->free_rows.push_back(sr.row_a);
-      if (sr.row_b >= 0) sv->free_rows.push_back(sr.row_b);
+  } catch (const HipFail &f) {
+    session_fail(sv, map_hip(f.err));
+    return true;
+  }
+  // A launch that has ended: every record it took is complete (its rows copied once the
+  // copy stream is done) unless a wait timed out.
+  if (sv->open && hipEventQuery(sv->sended) == hipSuccess) {
+    (void)hipStreamSynchronize(sv->cstream);
+    try {
+      session_collect(sv);
+    } catch (const HipFail &f) {
+      session_fail(sv, map_hip(f.err));
     }
-    sv->inflight.clear();
+    session_fail(sv, SW_EDEVICE);  // records that never completed
     sv->open = false;
     sv->closing = false;
     return true;
@@ -1876,11 +2018,16 @@ bool session_step(sw_server *sv, std::unique_lock<std::mutex> &lk) {
     session_close(sv);
     return false;
   }
-  // admit: keep at most max_records records in flight, so that requests wait here, where
-  // two of similar length can still share a record, rather than on the device
+  // Admit: publish a record only when the device is about to run out of published work
+  // (fewer than half a record's items left unclaimed), so that requests wait here, where
+  // two of similar length can still share a record, rather than on the device.  A
+  // record's longest groups can keep it on the device well after its items are all
+  // claimed, so several records may be in flight (at most max_records).
   bool did = false;
   while (!sv->queue.empty() && (int32_t)sv->inflight.size() < sv->max_records &&
-         sv->free_rows.size() >= 1) {
+         sv->free_rows.size() >= 1 &&
+         (!sv->open || sv->inflight.empty() ||
+          (int64_t)sv->published * sv->db->ngroups - claimed_items(sv) < sv->db->ngroups / 2)) {
     ServerRequest *qa = sv->queue.front();
     if (qa->query.empty()) {
       sv->queue.pop_front();
@@ -1896,10 +2043,13 @@ bool session_step(sw_server *sv, std::unique_lock<std::mutex> &lk) {
       sv->exact_queue.push_back(qa);
       return true;
     }
-    // the queued request of the most similar length, if sharing lanes pays
+    // The queued request of the most similar length, if sharing lanes pays.  A pair takes
+    // about 1.8 times as long as one of its queries, so queries are paired only when
+    // requests are piling up (several waiting besides this one): under light load each
+    // runs alone, at its lowest latency.
     ServerRequest *qb = nullptr;
     size_t qb_at = 0;
-    if (sv->max_batch >= 2 && sv->free_rows.size() >= 2) {
+    if (sv->max_batch >= 2 && sv->free_rows.size() >= 2 && sv->queue.size() >= kServePairQueue) {
       const size_t look = std::min<size_t>(sv->queue.size(), 64);
       int64_t best = -1;
       for (size_t k = 1; k < look; ++k) {
@@ -2009,19 +2159,21 @@ SW_API int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open,
     // needs the intra-task kernel; its device scratch must fit the free memory and the
     // budget, which also bounds the score rows.
     sv->grid = std::max(1, serve_max_blocks_per_cu()) * std::max(1, db->num_cu);
-    sv->max_records = std::max(2, (int)slots);
+    sv->max_records = std::max(4, 4 * (int)slots);
     sv->nrows = 2 * sv->max_records;
-    const size_t dev_bytes = session_device_bytes(db, sv->grid, std::max(4, 2 * sv->max_records));
+    // score rows: two per record in flight, fewer if the budget says so (at least two)
     const size_t row_bytes = (size_t)db->n_seqs * 4;
+    const int nrec = std::max(4, 2 * sv->max_records);
+    const size_t fixed = session_device_bytes(db, sv->grid, nrec, 0);
+    if (mem_budget_bytes > 0 && (int64_t)fixed < mem_budget_bytes)
+      sv->nrows = (int32_t)std::max<int64_t>(
+          2, std::min<int64_t>(sv->nrows, (mem_budget_bytes - (int64_t)fixed) / (int64_t)row_bytes));
+    const size_t dev_bytes = fixed + (size_t)sv->nrows * row_bytes;
     const bool fits = dev_bytes + ((size_t)1 << 30) < device_free_bytes() &&
-                      (mem_budget_bytes == 0 ||
-                       (int64_t)(dev_bytes + 2 * row_bytes) <= mem_budget_bytes);
+                      (mem_budget_bytes == 0 || (int64_t)dev_bytes <= mem_budget_bytes);
     sv->session_mode = db->longs.empty() && db->n_seqs > 0 &&
                        (int64_t)db->ngroups >= 4LL * sv->grid && fits;
     if (sv->session_mode) {
-      if (mem_budget_bytes > 0)
-        sv->nrows = (int32_t)std::max<int64_t>(
-            2, std::min<int64_t>(sv->nrows, (mem_budget_bytes - (int64_t)dev_bytes) / (int64_t)row_bytes));
       session_setup(sv);
     } else {
       sv->slots.resize((size_t)slots);
@@ -2105,7 +2257,8 @@ SW_API int sw_server_counters(sw_server *sv, int64_t *values, int32_t n) {
   std::lock_guard<std::mutex> lk(sv->mu);
   const int64_t v[SW_SERVER_NCOUNTERS] = {sv->launches, sv->max_in_flight, sv->refused,
                                           sv->session_mode ? 1 : 0, sv->records, sv->paired,
-                                          sv->exact_runs};
+                                          sv->exact_runs, sv->session_mode ? sv->grid : 0,
+                                          (int64_t)(sv->copy_s * 1e6)};
   for (int32_t k = 0; k < n && k < SW_SERVER_NCOUNTERS; ++k) values[k] = v[k];
   return SW_OK;
 }

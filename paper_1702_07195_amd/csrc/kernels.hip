@@ -337,7 +337,12 @@ void k_inter16(InterArgs a) {
         *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
       }
     };
+    // the widest groups are claimed first and each is one wave's work for most of the
+    // launch: they run at raised priority on their SIMDs, so they end with the rest
+    const bool prio = gd.ncols >= a.prio_cols;
+    if (prio) __builtin_amdgcn_s_setprio(2);
     const uint32_t vmax = inter16_strips<T>(lds, res, gd.ncols, bnd, qd.nstrips, goe2, ge2, stage);
+    if (prio) __builtin_amdgcn_s_setprio(0);
     const int lo = (int)(int16_t)(vmax & 0xffffu);
     const int hi = (int)(int16_t)(vmax >> 16);
     const int sc = lo > hi ? lo : hi;
@@ -1156,8 +1161,11 @@ void k_inter16q2(Inter2Args a) {
         *reinterpret_cast<uint4 *>(lds + code * RS + k * 16) = src[c];
       }
     };
+    const bool prio = gd.ncols >= a.prio_cols;  // as in k_inter16
+    if (prio) __builtin_amdgcn_s_setprio(2);
     const uint32_t vmax =
         inter16q2_strips<T>(lds, res, gd.ncols, bnd, pr.nstrips, goe2, ge2, stage);
+    if (prio) __builtin_amdgcn_s_setprio(0);
     if (lane < gd.count) {
       const int p = gd.first + lane;
       const int orig = a.perm[p];
@@ -1220,13 +1228,14 @@ hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s)
 // doorbell (2 * records published, plus 1 once no more will come).  A wave that claims
 // an item of a record not yet published waits: workgroups [0, npoll) read the doorbell
 // over the bus and raise a device-memory mirror of it, the others read the mirror, with
-// a growing sleep between reads.  Nothing but this kernel runs on the device while a
-// session is open, so the waves build each strip's profile slice themselves, in LDS,
-// from the query residues (copied once per record into a per-wave cache) and the
-// substitution matrix (kept in LDS), and write scores straight into host memory.  The
-// wave that finishes a record's last item publishes its completion (and whether any
-// score reached the int16 ceiling, Section 4.2, in which case the host recomputes that
-// query exactly) with a system-scope release.
+// a growing sleep between reads.  No other kernel can run beside the session's waves,
+// so the waves build each strip's profile slice themselves, in LDS, from the query
+// residues (copied once per record into a per-wave cache) and the substitution matrix
+// (kept in LDS), and write scores through the caches into device memory.  The wave that
+// finishes a record's last item publishes its completion (and whether any score reached
+// the int16 ceiling, Section 4.2, in which case the host recomputes that query exactly)
+// with a system-scope release; the host then copies the rows out (a DMA copy, which runs
+// beside the kernel).
 
 // Claim the next item and wait until its record is published.  Lane 0 only.  Returns
 // the item, or -1 once the session is closed before the item's record came, or when the
@@ -1235,14 +1244,17 @@ __device__ int serve_claim(const ServeArgs &a) {
   const int item = atomicAdd(a.claim, 1);
   const int need = item / a.ngroups + 1;  // records that must be published
   const bool poller = (int)blockIdx.x < a.npoll;
+  // the polling waves also tell the host how far the claims have got, which it uses to
+  // publish a record only when the device is about to run out of published work
+  if (poller)
+    __hip_atomic_store(a.hprog + blockIdx.x, item, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   const int64_t t0 = wall_clock64();
   int backoff = 1;
   for (;;) {
     int v;
     if (poller) {
       v = __hip_atomic_load(a.doorbell, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      __hip_atomic_fetch_max(a.mirror, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(a.mirror, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       v = __hip_atomic_load(a.mirror, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1266,14 +1278,14 @@ void k_serve(ServeArgs a) {
                                                                      : Inter16q2Lds<T2>::bytes;
   static_assert(2 * T1 <= 64 && T2 <= 64, "a strip's residues fit one 64-byte row");
   __shared__ __attribute__((aligned(16))) uint8_t lds[LB];
-  __shared__ int16_t smat[kCodes * kCodes];  // [query code][database code]
+  __shared__ int8_t smat[kCodes * kCodes];  // [query code][database code]; |entries| <= 127
   __shared__ __attribute__((aligned(16))) uint8_t sres[2][64];  // residues of one strip
   __shared__ int s_item;
   const int lane = threadIdx.x;
   for (int e = lane; e < kCodes * kCodes; e += 64) {
     const int d = e >> 5, c = e & 31;
-    smat[e] = (int16_t)((d < a.alphabet && c < a.alphabet) ? a.matrix[d * a.alphabet + c]
-                                                           : kPadScore);
+    smat[e] = (int8_t)((d < a.alphabet && c < a.alphabet) ? a.matrix[d * a.alphabet + c]
+                                                          : kPadScore);
   }
   uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
   uint8_t *qc = a.qcache + (int64_t)blockIdx.x * 2 * a.qcap;
@@ -1289,7 +1301,8 @@ void k_serve(ServeArgs a) {
     __syncthreads();
     const int item = s_item;
     if (item < 0) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the record was written before the doorbell
+    // (no cache maintenance per item: what the host wrote before the doorbell, the
+    // record and its queries, is read below with loads that bypass the caches)
     const int r = item / a.ngroups;
     const int g = a.ngroups - 1 - (item - r * a.ngroups);
     const int slot = r % a.nrec;
@@ -1320,13 +1333,18 @@ void k_serve(ServeArgs a) {
         dst[k] = __hip_atomic_load(src + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       for (int k = lane; k < nbq; k += 64)
         dst[qw + k] = __hip_atomic_load(src + qw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      // the copy must be visible to every lane's later reads of the cache
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      // the copy must be visible to every lane's later reads of the cache (one wave, one
+      // compute unit: a workgroup-scope fence)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       cur = r;
     }
     const GroupDesc gd = a.groups[g];
     const uint32_t *res = reinterpret_cast<const uint32_t *>(a.packed + gd.base) + lane;
+    // a record's widest groups, each one wave's work for much of the record's time, run at
+    // raised priority on their SIMDs (as in k_inter16)
+    const bool prio = gd.ncols >= a.prio_cols;
+    if (prio) __builtin_amdgcn_s_setprio(2);
     uint32_t vmax;
     if (kind == 1) {
       // strip s: rows [s * 2T1, (s + 1) * 2T1) of query a, as int16 row pairs per code
@@ -1340,8 +1358,8 @@ void k_serve(ServeArgs a) {
 #pragma unroll
         for (int w = lane; w < DW; w += 64) {
           const int code = w / (ROWS / 2), rp = w - code * (ROWS / 2);
-          const uint32_t lo = (uint16_t)smat[sres[0][2 * rp] * kCodes + code];
-          const uint32_t hi = (uint16_t)smat[sres[0][2 * rp + 1] * kCodes + code];
+          const uint32_t lo = (uint16_t)(int16_t)smat[sres[0][2 * rp] * kCodes + code];
+          const uint32_t hi = (uint16_t)(int16_t)smat[sres[0][2 * rp + 1] * kCodes + code];
           *reinterpret_cast<uint32_t *>(lds + code * RS1 + 4 * rp) = lo | (hi << 16);
         }
       };
@@ -1361,36 +1379,46 @@ void k_serve(ServeArgs a) {
 #pragma unroll
         for (int w = lane; w < DW; w += 64) {
           const int code = w / T2, rr = w - code * T2;
-          const uint32_t lo = (uint16_t)smat[sres[0][rr] * kCodes + code];
-          const uint32_t hi = (uint16_t)smat[sres[1][rr] * kCodes + code];
+          const uint32_t lo = (uint16_t)(int16_t)smat[sres[0][rr] * kCodes + code];
+          const uint32_t hi = (uint16_t)(int16_t)smat[sres[1][rr] * kCodes + code];
           *reinterpret_cast<uint32_t *>(lds + code * RS2 + 4 * rr) = lo | (hi << 16);
         }
       };
       vmax = inter16q2_strips<T2>(lds, res, gd.ncols, bnd, nstrips, goe2, ge2, stage);
     }
+    if (prio) __builtin_amdgcn_s_setprio(0);
+    // Scores go to device memory with stores that write through the caches; the wave waits
+    // until they are done before it counts the item, so a release (which would write back
+    // the whole L2 after every item) is needed only once per record, by the last wave.
+    // (Scattered 4-byte stores straight into host memory cost about a tenth of the
+    // throughput; the host copies a complete record's rows out instead.)
     int sat = 0;
     if (lane < gd.count) {
       const int orig = a.perm[gd.first + lane];
-      if (kind == 1) {
-        a.hscores[out_a + orig] = (int)vmax;
-        sat = (int)vmax >= kSat16 ? 1 : 0;
-      } else {
-        const int sa = (int)(int16_t)(vmax & 0xffffu), sb = (int)(int16_t)(vmax >> 16);
-        a.hscores[out_a + orig] = sa;
-        sat = sa >= kSat16 ? 1 : 0;
-        if (out_b >= 0) {
-          a.hscores[out_b + orig] = sb;
-          sat |= sb >= kSat16 ? 2 : 0;
-        }
+      int sa = (int)vmax, sb = 0;
+      if (kind != 1) {
+        sa = (int)(int16_t)(vmax & 0xffffu);
+        sb = (int)(int16_t)(vmax >> 16);
+      }
+      __hip_atomic_store(a.scores + out_a + orig, sa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      sat = sa >= kSat16 ? 1 : 0;
+      if (kind != 1 && out_b >= 0) {
+        __hip_atomic_store(a.scores + out_b + orig, sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        sat |= sb >= kSat16 ? 2 : 0;
       }
     }
-    // saturation bits of the wave, then the item count of the record; the wave that
-    // finishes the record's last item reports it to the host
+    __builtin_amdgcn_s_waitcnt(0);
+    // saturation bits of the wave, then the item count of the record (each atomic
+    // completes before the next is issued); the wave that finishes the record's last item
+    // reports it to the host
     for (int off = 32; off > 0; off >>= 1) sat |= __shfl_xor(sat, off);
     if (lane == 0) {
-      if (sat) __hip_atomic_fetch_or(a.satf + slot, sat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int old = __hip_atomic_fetch_add(a.done + slot, 1, __ATOMIC_ACQ_REL,
-                                             __HIP_MEMORY_SCOPE_SYSTEM);
+      if (sat) {
+        __hip_atomic_fetch_or(a.satf + slot, sat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+      const int old = __hip_atomic_fetch_add(a.done + slot, 1, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
       if (old == a.ngroups - 1) {
         const int bits = __hip_atomic_load(a.satf + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(a.satf + slot, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -89,6 +89,7 @@ struct InterArgs {
   int64_t bnd_slot_words;    // dwords per slot
   int32_t recompute_all;
   int32_t nitems;            // ngroups * nqueries
+  int32_t prio_cols;         // items of groups at least this wide run at raised wave priority
 };
 
 // Two queries sharing the lanes of the two-query inter-task kernel (batched searches).
@@ -117,6 +118,7 @@ struct Inter2Args {
   int64_t bnd_slot_words;    // dwords per slot (>= 128 * widest group's columns)
   int32_t recompute_all;
   int32_t nitems;            // ngroups * npairs
+  int32_t prio_cols;         // items of groups at least this wide run at raised wave priority
 };
 
 struct IntraArgs {
@@ -191,7 +193,7 @@ struct PackArgs {
 
 // One admitted unit of work, in host memory (record r lives in slot r % nrec).
 struct ServeRecord {
-  int64_t out_a;     // element offset of query a's score row in the host score arena
+  int64_t out_a;     // element offset of query a's score row in the score arena
   int64_t out_b;     // query b's row, or -1 (one query per lane)
   int32_t ma, mb;    // query lengths (mb = 0 without query b)
   int32_t kind;      // 1: one query per lane (strips of 2 * T1 rows); 2: two per lane (T2 rows)
@@ -211,11 +213,13 @@ struct ServeArgs {
   const ServeRecord *records;   // host, nrec records
   const uint8_t *qstage;        // host, per slot: query a at [0, qcap), query b at [qcap, 2 qcap),
                                 // each padded with kPadCode to a multiple of 64 bytes
-  int32_t *hscores;             // host, score rows
+  int32_t *scores;              // device, score rows (written through to memory: the host
+                                // copies a record's rows out once it is complete)
   const int32_t *doorbell;      // host: 2 * (records published) + (1 once closed)
   int32_t *complete;            // host, per slot: r + 1 once record r is complete
   int32_t *hsat;                // host, per slot: saturation bits of the completed record
                                 // (1: query a, 2: query b), written before `complete`
+  int32_t *hprog;               // host, per polling workgroup: the last item it claimed
   int32_t *mirror;              // device: largest doorbell value a polling wave has seen
   int32_t *claim;               // device: next work item
   int32_t *done;                // device, per slot: items finished
@@ -226,7 +230,7 @@ struct ServeArgs {
   int64_t bnd_slot_words;       // dwords per slot (>= 128 * widest group's columns)
   int32_t npoll;                // workgroups [0, npoll) read the host doorbell; the others
                                 // read its device mirror
-  int32_t pad;
+  int32_t prio_cols;            // items of groups at least this wide run at raised wave priority
   int64_t timeout_ticks;        // wall-clock ticks a wave waits for work before giving up
 };
 

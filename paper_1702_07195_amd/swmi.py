@@ -38,6 +38,7 @@ SW_KNOB_INTRA_PAIRS = 10
 SW_KNOB_SPIN_LIMIT = 11
 SW_KNOB_QUERY_PAIRS = 12
 SW_KNOB_MAIN_WAVES = 13
+SW_KNOB_PRIO_COLS = 14
 
 # Every entry point declared in include/swmi.h.
 SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_async",
@@ -45,7 +46,21 @@ SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_asy
            "sw_timing_read_kernel", "sw_set_knob", "sw_get_knob", "sw_plan_create",
            "sw_plan_launch", "sw_plan_free", "sw_server_create", "sw_server_submit",
            "sw_server_wait", "sw_server_stats", "sw_server_counters", "sw_server_free",
-           "sw_topk")
+           "sw_topk", "sw_search_stats")
+
+# sw_search_stats indices
+SW_ST_CELLS_INTER16 = 0
+SW_ST_CELLS_INTRA32 = 1
+SW_ST_CELLS_INTRA16 = 2
+SW_ST_CELLS_CRIT = 3
+SW_ST_INTRA_ROWS = 4
+SW_ST_MAIN_WAVES = 5
+SW_ST_ROUTED_GROUPS = 6
+SW_ST_STRIP_ROWS = 7
+SW_ST_QUERY_PAIRS = 8
+SW_SEARCH_NSTATS = 9
+SW_ST_NAMES = ("cells_inter16", "cells_intra32", "cells_intra16", "cells_crit", "intra_rows",
+               "main_waves", "routed_groups", "strip_rows", "query_pairs")
 
 # sw_server_counters indices
 SW_SC_LAUNCHES = 0
@@ -55,9 +70,11 @@ SW_SC_SESSION_MODE = 3
 SW_SC_RECORDS = 4
 SW_SC_PAIRED = 5
 SW_SC_EXACT_RUNS = 6
-SW_SERVER_NCOUNTERS = 7
+SW_SC_WAVES = 7
+SW_SC_COPY_US = 8
+SW_SERVER_NCOUNTERS = 9
 SW_SC_NAMES = ("launches", "max_in_flight", "refused", "session_mode", "records", "paired",
-               "exact_runs")
+               "exact_runs", "waves", "copy_us")
 
 SW_KERNEL_INTER16 = 0
 SW_KERNEL_INTRA_LONG = 1
@@ -140,6 +157,8 @@ def lib():
         L.sw_server_free.argtypes = [_vp]
         L.sw_topk.restype = ctypes.c_int
         L.sw_topk.argtypes = [_vp, _vp, ctypes.c_int32, _i32p, _i32p, _i32p, _vp]
+        L.sw_search_stats.restype = ctypes.c_int
+        L.sw_search_stats.argtypes = [_vp, _i64p, ctypes.c_int32]
         L.sw_set_knob.restype = ctypes.c_int
         L.sw_set_knob.argtypes = [ctypes.c_int32, ctypes.c_int64]
         L.sw_get_knob.restype = ctypes.c_int64
@@ -314,6 +333,13 @@ class SwDb:
                            ctypes.byref(nh), _vp(sptr))
         _check(rc, "sw_topk")
         return idx[:nh.value], sc[:nh.value]
+
+    def stats(self) -> dict:
+        """sw_search_stats of the latest search on this handle, by name."""
+        v = np.zeros(len(SW_ST_NAMES), dtype=np.int64)
+        _check(lib().sw_search_stats(self.handle, v.ctypes.data_as(_i64p), len(v)),
+               "sw_search_stats")
+        return {k: int(x) for k, x in zip(SW_ST_NAMES, v)}
 
     def timing_enable(self, on: bool = True):
         _check(lib().sw_timing_enable(self.handle, 1 if on else 0), "sw_timing_enable")
