@@ -264,6 +264,20 @@ int sw_server_counters(sw_server *server, int64_t *values, int32_t n);
 int sw_topk(const sw_db *db, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
             int32_t *hit_score, int32_t *n_hits, void *hip_stream);
 
+/*
+ * sw_topk_noalloc -- sw_topk for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, results and errors, with every scratch buffer of the selection in a fixed
+ * device array of the library (65 KiB per device, held until the process ends) instead
+ * of memory allocated on first use.  k above 4096 (the array's limit) is rejected with
+ * SW_EINVAL.  Calls on one device share that device's array: they are serialised inside
+ * the library, and work that overlaps on the device from outside it (another process's
+ * copy of the library excepted) would race; the selection state is cleared at the start
+ * of every call.
+ */
+int sw_topk_noalloc(const sw_db *db, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
+                    int32_t *hit_score, int32_t *n_hits, void *hip_stream);
+
 /* Static message for an error code. */
 const char *sw_strerror(int code);
 

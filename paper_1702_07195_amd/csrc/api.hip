@@ -143,6 +143,8 @@ struct sw_db {
   double timing_ms[3] = {0.0, 0.0, 0.0};
 };
 
+int swmi::db_device(const sw_db *db) { return db->device; }
+
 namespace {
 
 int map_hip(hipError_t e) {

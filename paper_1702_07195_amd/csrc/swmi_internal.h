@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct sw_db;
+
 namespace swmi {
 
 // Residue code reserved for padding.  Its substitution score against every query
@@ -265,6 +267,9 @@ hipError_t launch_serve(const ServeArgs &a, int grid, hipStream_t s);
 int serve_max_blocks_per_cu();
 constexpr int kServeT1 = 24;  // strip half-height of one-query records
 constexpr int kServeT2 = 28;  // strip height of two-query records
+
+// Device a loaded database lives on (api.hip; the handle is opaque elsewhere).
+int db_device(const struct ::sw_db *db);
 
 // Strip heights compiled for the inter-task kernel, and band rows per lane for the
 // intra-task kernel.

@@ -1,6 +1,9 @@
 // Sorting stage of a search on gfx950: the k best hits of a score array, selected and
 // sorted on the device.
 #include <algorithm>
+#include <mutex>
+
+#include "../../include/swmi.h"
 
 #include "swmi_internal.h"
 
@@ -111,4 +114,78 @@ hipError_t launch_topk(const TopkArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------ top-k without allocation
+// sw_topk_noalloc: the same selection with its scratch (selection state, digit histogram,
+// collected keys, results) in a file-scope device array instead of memory the library
+// allocates, for callers that cannot allocate.  Every call on a device uses that device's
+// copy of the array; calls are serialised per device, and the state and histogram are
+// cleared by k_topk_init at the start of every call.
+constexpr size_t kTopkOffHist = 64;
+constexpr size_t kTopkOffList = kTopkOffHist + 256 * sizeof(uint32_t);
+constexpr size_t kTopkOffIdx = kTopkOffList + (size_t)kTopkMax * sizeof(uint64_t);
+constexpr size_t kTopkOffScore = kTopkOffIdx + (size_t)kTopkMax * sizeof(int32_t);
+constexpr size_t kTopkScratchBytes = kTopkOffScore + (size_t)kTopkMax * sizeof(int32_t);
+static_assert(sizeof(TopkState) <= kTopkOffHist, "state fits its slot");
+
+static __device__ __align__(256) uint8_t scratch[kTopkScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};     // scratch's device address, per device
+std::mutex g_scratch_use[kMaxDevices];     // one call at a time per device
+}  // namespace
+
+// The device address of `scratch` on the current device, looked up once per device.
+static hipError_t scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return hipSuccess;
+}
+
 }  // namespace swmi
+
+extern "C" __attribute__((visibility("default")))
+int sw_topk_noalloc(const sw_db *db, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
+                    int32_t *hit_score, int32_t *n_hits, void *hip_stream) {
+  using namespace swmi;
+  if (!db) return SW_ENODB;
+  if (k < 1 || k > kTopkMax || !n_hits || !hit_index || !hit_score) return SW_EINVAL;
+  const int64_t n = sw_db_size(db);
+  if (n < 0) return SW_ENODB;
+  if (n > 0 && !scores_dev) return SW_EINVAL;
+  const int32_t kk = (int32_t)std::min<int64_t>(k, n);
+  *n_hits = 0;
+  if (kk == 0) return SW_OK;
+  // the database's device, made current (its copy of the array is the one used)
+  const int device = db_device(db);
+  if (device < 0 || device >= kMaxDevices || hipSetDevice(device) != hipSuccess)
+    return SW_EDEVICE;
+  void *base_ptr = nullptr;
+  if (scratch_address(device, &base_ptr) != hipSuccess) return SW_EDEVICE;
+  std::lock_guard<std::mutex> use(g_scratch_use[device]);
+  uint8_t *base = (uint8_t *)base_ptr;
+  TopkArgs a;
+  a.scores = scores_dev;
+  a.n = n;
+  a.k = kk;
+  a.state = (TopkState *)base;
+  a.hist = (uint32_t *)(base + kTopkOffHist);
+  a.list = (uint64_t *)(base + kTopkOffList);
+  a.hit_index = (int32_t *)(base + kTopkOffIdx);
+  a.hit_score = (int32_t *)(base + kTopkOffScore);
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (launch_topk(a, s) != hipSuccess) return SW_EDEVICE;
+  if (hipMemcpyAsync(hit_index, a.hit_index, (size_t)kk * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(hit_score, a.hit_score, (size_t)kk * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SW_EDEVICE;
+  *n_hits = kk;
+  return SW_OK;
+}

@@ -46,7 +46,7 @@ SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_asy
            "sw_timing_read_kernel", "sw_set_knob", "sw_get_knob", "sw_plan_create",
            "sw_plan_launch", "sw_plan_free", "sw_server_create", "sw_server_submit",
            "sw_server_wait", "sw_server_stats", "sw_server_counters", "sw_server_free",
-           "sw_topk", "sw_search_stats")
+           "sw_topk", "sw_search_stats", "sw_topk_noalloc")
 
 # sw_search_stats indices
 SW_ST_CELLS_INTER16 = 0
@@ -157,6 +157,8 @@ def lib():
         L.sw_server_free.argtypes = [_vp]
         L.sw_topk.restype = ctypes.c_int
         L.sw_topk.argtypes = [_vp, _vp, ctypes.c_int32, _i32p, _i32p, _i32p, _vp]
+        L.sw_topk_noalloc.restype = ctypes.c_int
+        L.sw_topk_noalloc.argtypes = [_vp, _vp, ctypes.c_int32, _i32p, _i32p, _i32p, _vp]
         L.sw_search_stats.restype = ctypes.c_int
         L.sw_search_stats.argtypes = [_vp, _i64p, ctypes.c_int32]
         L.sw_set_knob.restype = ctypes.c_int
