@@ -1,7 +1,8 @@
 """Build step for the HIP libraries (gfx950), run by ``__graft_entry__.build``.
 
-Compiles the ``csrc/*.hip`` sources with hipcc into ``libswmi.so``, which exports the C
-ABI of ``include/swmi.h``, and ``csrc/calib.hip`` alone into ``libswmi_calib.so`` (the
+Compiles the ``csrc/*.hip`` sources with hipcc, and the host-only ``csrc/*.cpp`` (the
+search planner) with g++, into ``libswmi.so``, which exports the C ABI of
+``include/swmi.h``, and ``csrc/calib.hip`` alone into ``libswmi_calib.so`` (the
 VALU calibration of ``include/swmi_calib.h``).  The libraries are written next to this
 file so that they travel with the source tree.
 """
@@ -33,9 +34,19 @@ def sources():
     return sorted(s for s in glob.glob(os.path.join(HERE, "csrc", "*.hip")) if s != CALIB_SRC)
 
 
+def host_sources():
+    """Host-only C++ (the search planner), compiled by the host compiler."""
+    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
+
+
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-Wall", "-Wextra",
+              "-I", os.path.join(ROOT, "include")]
+
+
 def _link(objs, lib, verbose):
     tmp = lib + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Wl,--no-undefined", *objs,
+           "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, capture_output=not verbose)
@@ -55,7 +66,17 @@ def build(verbose: bool = False, extra=None) -> str:
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
         objs.append(obj)
-    _link(objs[:-1], LIB, verbose)
+    host_objs = []
+    for src in host_sources():
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = ["g++", *HOST_FLAGS, "-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"g++ failed for {src}:\n{r.stderr}")
+        host_objs.append(obj)
+    _link(objs[:-1] + host_objs, LIB, verbose)
     _link(objs[-1:], CALIB_LIB, verbose)
     return LIB
 

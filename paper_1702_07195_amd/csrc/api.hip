@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/swmi.h"
+#include "planner.h"
 #include "swmi_internal.h"
 
 #define SW_API extern "C" __attribute__((visibility("default")))
@@ -115,11 +116,6 @@ struct sw_db {
   int32_t max_len = 0;        // longest sequence overall
   int64_t residues = 0;       // unpadded residue total
   DevBuf packed, groups, perm, lens;
-  struct LongSeq {
-    int64_t base;
-    int32_t len;
-    int32_t orig;
-  };
   std::vector<LongSeq> longs;  // sorted by decreasing length
   std::vector<GroupDesc> hgroups;   // host copy of the group table
   std::vector<int32_t> hperm;       // host copy: sorted position -> caller index
@@ -149,6 +145,28 @@ namespace {
 
 int map_hip(hipError_t e) {
   return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SW_ENOMEM : SW_EDEVICE;
+}
+
+// Runs the body of an entry point: no exception crosses the C ABI (a HIP failure maps to
+// its code, an allocation failure to SW_ENOMEM, anything else, such as std::system_error
+// from a lock or a thread, to SW_EDEVICE).
+template <class F> int abi_guard(F &&body) noexcept {
+  try {
+    return body();
+  } catch (const HipFail &f) {
+    return map_hip(f.err);
+  } catch (const std::bad_alloc &) {
+    return SW_ENOMEM;
+  } catch (...) {
+    return SW_EDEVICE;
+  }
+}
+
+template <class F> void abi_guard_void(F &&body) noexcept {
+  try {
+    body();
+  } catch (...) {
+  }
 }
 
 void grow(DevBuf &b, size_t bytes) {
@@ -264,137 +282,52 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t m) {
   return SW_OK;
 }
 
-// Rows per lane of the intra-task kernel for one search.  Its band is 64R query rows,
-// and a step (one anti-diagonal of a band) issues about 7.5 R + 14 instructions: the
-// lane's per-step overhead (residue and boundary shifts, the profile request) is paid
-// once per R rows, so over many bands R = 16 issues the fewest instructions per cell.
-// But a pair of n columns is swept in about n steps whatever R, its bands pipelined
-// kIntraLag chunks of 64 steps apart, so with few bands the step time of the longest
-// pair sets the search's critical path, and shorter steps win.  For each R in
-// {16, 8, 4, 2} the search time is estimated as the larger of
-//   - the throughput time: every intra-task pair's bands of 64R rows at the kernel's
-//     rate, about 3.6e12 cells/s at R = 16 on MI355X, scaling as R / (7.5 R + 14); a
-//     query with more bands than a workgroup has waves is swept in several rounds, where
-//     short steps measured less efficient (0.77 at R = 8, 0.34 at R = 4, on a 35,000-row
-//     query; 0.15 assumed at R = 2), and R = 2 reached 0.45 of that rate even with few
-//     bands (a 1,000-row query over 6.4e6 residues), and
-//   - the longest pair's path: one band alone is one wave among two per SIMD, n + 63
-//     steps of 0.5 us x (7.5 R + 14) / 134 per band; several bands (a pair at least
-//     `wide_len` long) are a pipeline of waves alone on their SIMDs, 0.76 of that step,
-//     which at R > kCritR may run at kCritR rows in the critical-pair launch,
-// and the smallest estimate wins, a tie going to the larger R (R = 16 and 8 tie when
-// both leave the longest pairs to the critical-pair launch, and 16 measured faster
-// there).  R = 2 is weighed only when the path at R = 4 exceeds a millisecond: below
-// that, per-search costs the estimate leaves out dominate, and R = 2 measured no faster
-// (a 144-row query over 2,000 sequences of at most 2,000 residues).  (Measured on the
-// long-sequence mix, whose longest sequence has 35,000 residues: queries of 300 and
-// 1,000 residues ran 1.8 and 2.8 times faster at R = 4 than at the R an instruction
-// count alone picks.)
-int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
-             int64_t wide_len, int num_cu, bool *throughput_bound) {
-  auto step_scale = [](int R) { return (7.5 * R + 14.0) / (7.5 * 16 + 14.0); };
-  auto bands = [](int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); };
-  auto pipe = [&](int64_t m, int R) {  // a pipeline of waves alone on their SIMDs
-    const double chunks = (double)((n_max + 126) / 64 + (int64_t)kIntraLag * (bands(m, R) - 1));
-    return chunks * 64 * 0.76 * 0.5e-6 * step_scale(R);
-  };
-  // (throughput time, longest path) at R
-  auto estimate = [&](int R, double &thr, double &path) {
-    const double rate = 3.6e12 * (R / 16.0) / step_scale(R) * (std::max(1, num_cu) / 256.0);
-    const double eff_rounds = R == 16 ? 1.0 : (R == 8 ? 0.77 : (R == 4 ? 0.34 : 0.15));
-    const double eff_few = R == 2 ? 0.45 : 1.0;
-    thr = 0;
-    path = 0;
-    for (int64_t m : lens) {
-      if (m == 0) continue;
-      const int64_t b = bands(m, R);
-      thr += (double)b * 64 * R * intra_res / (rate * (b > kIntraWaves ? eff_rounds : eff_few));
-      double t;
-      if (b >= 2 && n_max >= wide_len) {
-        t = pipe(m, R);
-        if (R > kCritR) t = std::min(t, pipe(m, kCritR));
-      } else {
-        t = (double)b * (double)(n_max + 63) * 0.5e-6 * step_scale(R);
-      }
-      path = std::max(path, t);
-    }
-  };
-  int best = kIntraR;
-  const int64_t forced = g_knob_intra_rows.load();
-  if (forced == 2 || forced == 4 || forced == 8 || forced == 16) {
-    best = (int)forced;
-  } else if (n_max > 0 && intra_res > 0) {
-    double best_cost = 1e300, path4 = 0;
-    for (int R : {16, 8, 4, 2}) {
-      if (R == 2 && path4 < 1e-3) break;
-      double thr, path;
-      estimate(R, thr, path);
-      if (R == 4) path4 = path;
-      const double cost = std::max(thr, path);
-      if (cost < best_cost * 0.999) {
-        best_cost = cost;
-        best = R;
-      }
-    }
-  }
-  double thr = 0, path = 0;
-  if (n_max > 0 && intra_res > 0) estimate(best, thr, path);
-  *throughput_bound = thr >= 1.2 * path;
-  return best;
+// The knob values and kernel occupancies a search plans with.
+Knobs knob_snapshot() {
+  Knobs k;
+  k.strip_rows = g_knob_strip_rows.load();
+  k.grid_waves = g_knob_grid_waves.load();
+  k.route_len = g_knob_route_len.load();
+  k.wide_len = g_knob_wide_len.load();
+  k.max_segments = g_knob_max_segments.load();
+  k.intra_rows = g_knob_intra_rows.load();
+  k.intra_pairs = g_knob_intra_pairs.load();
+  k.query_pairs = g_knob_query_pairs.load();
+  k.main_waves = g_knob_main_waves.load();
+  k.mem_cap_mb = g_knob_mem_cap_mb.load();
+  return k;
 }
 
-// Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
-// by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
-// at three waves per SIMD and was fastest on the full-scale search).  The pair kernel
-// (`pairs`) also has T = 28, still at three waves per SIMD and 2% faster on the batched
-// search; its per-strip row count is T, and `lens` then holds twice each pair's rows.
-int choose_T(const std::vector<int64_t> &lens, bool pairs = false) {
-  const int64_t forced = g_knob_strip_rows.load();
-  if (forced > 0 && (pairs ? inter16q2_supported((int)forced) : inter16_supported((int)forced)))
-    return (int)forced;
-  struct Cand { int T; double speed; };
-  static const Cand single[] = {{24, 1.0}, {40, 0.985}, {32, 0.968}, {16, 0.89}};
-  static const Cand paired[] = {{28, 1.02}, {24, 1.0}, {40, 0.98}, {32, 0.962}, {16, 0.938}};
-  const Cand *cands = pairs ? paired : single;
-  const int ncand = pairs ? 5 : 4;
-  int best = 24;
-  double best_cost = 1e300;
-  for (int k = 0; k < ncand; ++k) {
-    const Cand &c = cands[k];
-    double cost = 0;
-    for (int64_t m : lens) cost += (double)((m + 2 * c.T - 1) / (2 * c.T)) * 2.0 * c.T;
-    cost /= c.speed;
-    if (cost < best_cost * 0.999) {
-      best_cost = cost;
-      best = c.T;
+const Occupancy &occupancy() {
+  static const Occupancy occ = [] {
+    Occupancy o;
+    for (int T = 1; T <= kMaxStripRows; ++T) {
+      if (inter16_supported(T)) o.inter16[T] = inter16_max_blocks_per_cu(T);
+      if (inter16q2_supported(T)) o.inter16q2[T] = inter16q2_max_blocks_per_cu(T);
     }
-  }
-  return best;
+    return o;
+  }();
+  return occ;
 }
 
-struct Plan {
-  int T = 32;
-  int R = kIntraR;               // rows per lane of the long-pair intra-task launch
-  int main_waves = kIntraWaves;  // waves per workgroup of that launch (8, or 4 at two per CU)
-  std::vector<int32_t> nbandsR;  // query bands of 64R rows
-  int64_t xbnd_elems = 0;  // int2 elements of the boundary rows between pair segments
-  int32_t nprog = 0;       // progress counters of those boundaries
-  int32_t ngroups_inter = 0;
-  int32_t n_wide = 0;
-  int64_t nduos = 0;  // two-pair items (their halves may be flagged for recompute)
-  int grid16 = 0;
-  int grid_long = 0;
-  int grid_re = 0;
-  std::vector<QueryDesc> qd;
-  std::vector<PairItem> longitems;
-  std::vector<PairItem> second;  // per long item: its second pair (two-pair items) or len -1
-  std::vector<PairItem> crititems;  // segments of critical pairs, in bands of 64 * R_CRIT rows
-  int grid_crit = 0;
-  int64_t qp16_elems = 0, qp8_elems = 0;
-  std::vector<QueryPair> pairs;  // two-query inter-task kernel (empty: k_inter16)
-  int64_t qp2_elems = 0;         // dwords of the pair profiles
-  int64_t stats[SW_SEARCH_NSTATS] = {};  // see sw_search_stats
-};
+DbView db_view(const sw_db *db) {
+  DbView v;
+  v.num_cu = db->num_cu;
+  v.alphabet = db->alphabet;
+  v.n_seqs = db->n_seqs;
+  v.ngroups = db->ngroups;
+  v.max_ncols = db->max_ncols;
+  v.max_len = db->max_len;
+  v.short_residues = db->short_residues;
+  v.packed_bytes = (int64_t)db->packed.bytes;
+  v.groups = db->hgroups.data();
+  v.perm = db->hperm.data();
+  v.lens = db->hlens.data();
+  v.group_res = db->group_res.data();
+  v.longs.p = db->longs.data();
+  v.longs.n = db->longs.size();
+  return v;
+}
 
 // Enqueue one (possibly batched) search on `s`.  Queries are host memory; scores go to
 // `scores_dev` (n_queries x n_seqs).  The caller owns `w` until `done` is recorded.
@@ -403,361 +336,24 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
                     int32_t *scores_dev, hipStream_t s, bool allow_timing = true) {
   // the caller has made db->device current (no device switch while a graph is captured)
   const int A = db->alphabet;
-  Plan p;
-  std::vector<int64_t> lens((size_t)nq);
-  for (int64_t q = 0; q < nq; ++q) lens[q] = qoff[q + 1] - qoff[q];
-  // inter-task items visit each group's queries longest first
-  std::vector<int32_t> qorder((size_t)nq);
-  std::iota(qorder.begin(), qorder.end(), 0);
-  std::stable_sort(qorder.begin(), qorder.end(),
-                   [&](int32_t x, int32_t y) { return lens[x] > lens[y]; });
-  // A batched search pairs its queries (longest first) in the two-query inter-task
-  // kernel, whose strips hold T rows of both; the strip height is chosen on the padded
-  // rows of the pairs.
-  const bool q2 = g_knob_query_pairs.load() != 0 && nq >= 2;
-  if (q2) {
-    std::vector<int64_t> pair_rows;
-    for (int64_t k = 0; k < nq; k += 2) {
-      QueryPair qp;
-      qp.qa = qorder[(size_t)k];
-      qp.qb = k + 1 < nq ? qorder[(size_t)k + 1] : -1;
-      qp.qp2 = 0;
-      qp.nstrips = 0;
-      qp.pad = 0;
-      p.pairs.push_back(qp);
-      pair_rows.push_back(2 * lens[(size_t)qp.qa]);  // ceil(2m / 2T) * 2T = 2T ceil(m / T)
-    }
-    p.T = choose_T(pair_rows, true);
-  } else {
-    p.T = choose_T(lens);
-  }
-  const int band = 64 * kIntraR;
-  p.qd.resize((size_t)nq);
-  for (int64_t q = 0; q < nq; ++q) {
-    QueryDesc &d = p.qd[q];
-    d.m = (int32_t)lens[q];
-    d.nstrips = q2 ? 0 : (int32_t)((lens[q] + 2 * p.T - 1) / (2 * p.T));
-    d.nbands = (int32_t)((lens[q] + band - 1) / band);
-    d.mrows = d.nbands * band;
-    d.qp16 = p.qp16_elems;
-    d.qp8 = p.qp8_elems;
-    d.out = q * db->n_seqs;
-    p.qp16_elems += (int64_t)d.nstrips * kCodes * 2 * p.T;
-    p.qp8_elems += (int64_t)kCodes * d.mrows;
-  }
-  for (QueryPair &qp : p.pairs) {
-    qp.nstrips = (int32_t)((lens[(size_t)qp.qa] + p.T - 1) / p.T);
-    qp.qp2 = p.qp2_elems;
-    p.qp2_elems += (int64_t)qp.nstrips * kCodes * p.T;
-  }
-  const int64_t nunits = q2 ? (int64_t)p.pairs.size() : nq;  // inter-task items per group
-  // launch geometry of the inter-task kernel
-  int per_cu = (int)g_knob_grid_waves.load();
-  if (per_cu <= 0)
-    per_cu = std::max(1, q2 ? inter16q2_max_blocks_per_cu(p.T) : inter16_max_blocks_per_cu(p.T));
-  const int64_t lanes = (int64_t)per_cu * db->num_cu * 64;
-
-  // Route the longest groups to the intra-task kernel.  One lane runs a whole alignment
-  // in the inter-task kernel, so a group of length L costs about L * m on one wave; keep
-  // L below twice the average number of residues per lane (weighted by the number of
-  // equally long queries), else that wave becomes the critical path.
-  // (paired queries: a lane runs both queries of a pair at once, so a pair counts once)
-  int64_t sum_m = 0, max_m = 1;
-  for (int64_t q = 0; q < nq; ++q) max_m = std::max(max_m, lens[q]);
-  if (q2)
-    for (const QueryPair &qp : p.pairs) sum_m += lens[(size_t)qp.qa];
-  else
-    for (int64_t q = 0; q < nq; ++q) sum_m += lens[q];
-  const double weight = (double)sum_m / (double)max_m;
-  int64_t route = (int64_t)(2.0 * (double)db->short_residues * weight / (double)lanes);
-  route = std::max<int64_t>(route, 64);
-  const int64_t forced_route = g_knob_route_len.load();
-  if (forced_route > 0) route = forced_route;
-  int32_t ninter = db->ngroups;
-  while (ninter > 0 && db->hgroups[ninter - 1].maxlen > route) --ninter;
-  p.ngroups_inter = ninter;
-
-  // rows per lane of the intra-task kernel, from the pairs it gets (long sequences and
-  // routed groups, the latter estimated at their longest sequence)
-  const int64_t wide_len = g_knob_wide_len.load() > 0 ? g_knob_wide_len.load()
-                                                      : (int64_t)64 * 6 * kIntraLag;
-  {
-    double intra_res = 0;
-    int64_t n_max = 0;
-    for (const auto &L : db->longs) {
-      intra_res += L.len;
-      n_max = std::max<int64_t>(n_max, L.len);
-    }
-    for (int32_t g = ninter; g < db->ngroups; ++g) {
-      intra_res += (double)db->hgroups[g].count * db->hgroups[g].maxlen;
-      n_max = std::max<int64_t>(n_max, db->hgroups[g].maxlen);
-    }
-    // A throughput-bound search (estimated throughput time at least 1.2 times the
-    // longest path) runs four-wave workgroups, two per CU: the same occupancy, and one
-    // fits beside a critical-pair workgroup (an 8-wave one does not).  Otherwise
-    // eight-wave workgroups give a pair's few band waves a SIMD each (the rest of the
-    // workgroup idles).  (Long-sequence mix on MI355X: 5478-residue query 14.7 -> 10.8
-    // ms with four-wave workgroups; a 2005-residue query, at a ratio of 1.1, 8.2 -> 9.3.)
-    bool throughput_bound = false;
-    p.R = choose_R(lens, intra_res, n_max, wide_len, db->num_cu, &throughput_bound);
-    const int64_t mw = g_knob_main_waves.load();
-    p.main_waves = (mw == 4 || mw == 8) ? (int)mw : (throughput_bound ? kNarrowWaves : kIntraWaves);
-  }
-  p.nbandsR.resize((size_t)nq);
-  for (int64_t q = 0; q < nq; ++q)
-    p.nbandsR[q] = (int32_t)((lens[q] + 64 * p.R - 1) / (64 * p.R));
-
-  // intra-task items: long sequences and the sequences of routed groups, for every query;
-  // "wide" (a whole workgroup per pair) when the pair has several bands and enough
-  // columns to fill the band pipeline, else "narrow" (one wave per pair); each part
-  // longest first
-  std::vector<std::pair<double, PairItem>> wide, narrow;
-  auto add_item = [&](int64_t base, int32_t cstride, int32_t len, int32_t orig, int64_t q) {
-    PairItem it;
-    it.base = base;
-    it.cstride = cstride;
-    it.len = len;
-    it.out = orig;
-    it.query = (int32_t)q;
-    it.band0 = 0;
-    it.band1 = p.nbandsR[q];
-    it.xin = it.xout = -1;
-    it.prog_in = it.prog_out = -1;
-    it.segment = 0;
-    it.nsegments = 1;
-    const double cost = (double)len * (double)lens[q];
-    const bool is_wide = len >= wide_len && p.nbandsR[q] >= 2;
-    (is_wide ? wide : narrow).emplace_back(cost, it);
-  };
-  for (int64_t q = 0; q < nq; ++q) {
-    if (lens[q] == 0) continue;
-    for (const auto &L : db->longs) add_item(L.base, 4, L.len, L.orig, q);
-    for (int32_t g = ninter; g < db->ngroups; ++g) {
-      const GroupDesc &gd = db->hgroups[g];
-      for (int32_t l = 0; l < gd.count; ++l)
-        add_item(gd.base + 4 * l, 256, db->hlens[gd.first + l], db->hperm[gd.first + l], q);
-    }
-  }
-  auto by_cost = [](const std::pair<double, PairItem> &x, const std::pair<double, PairItem> &y) {
-    return x.first > y.first;
-  };
-  std::stable_sort(wide.begin(), wide.end(), by_cost);
-  std::stable_sort(narrow.begin(), narrow.end(), by_cost);
-  // Critical path of the longest pairs.  A workgroup sweeps its bands in rounds of its
-  // W = p.main_waves waves, so a pair of nb bands takes about ceil(nb / W) sweeps of its
-  // columns; cut into segments of at most W consecutive bands on workgroups of
-  // their own, the bands form one pipeline (nc + kIntraLag * (nb - 1) chunks), and with at
-  // most 4 bands per segment each band's wave has a SIMD to itself.  A pair is split as
-  // little as keeps its estimated time within half the estimated time of the whole
-  // intra-task search (a pair may be claimed only after other work has run); 4-band
-  // segments, which leave half a compute unit idle, only when even the full pipeline
-  // would outlast the whole search.  Segments of a pair are consecutive in the list, so
-  // segment j is always claimed after segment j - 1 (the only one it waits for).
-  //   (one step of a wave with R = 16: about 0.5 us with two waves per SIMD, 0.25 us
-  //   alone; the kernel then sustains about 2.5e12 cells/s over the whole chip: MI355X
-  //   measurements; both scale with the instructions per step, 7.5 R + 14)
-  double intra_cells = 0;
-  for (auto &x : wide) intra_cells += x.first;
-  for (auto &x : narrow) intra_cells += x.first;
-  const double step_scale = (7.5 * p.R + 14.0) / (7.5 * 16 + 14.0);
-  const double t_search = intra_cells / (2.5e12 * (p.R / 16.0) / step_scale) *
-                          (256.0 / std::max(1, db->num_cu));
-  const double t_step = 0.5e-6 * step_scale;
-  const int64_t cap = g_knob_max_segments.load();
-  // Narrow pairs of the same query can run two per wave as one packed int16 item
-  // (consecutive in cost order, so of similar length).  Such an item does two pairs'
-  // cells per step at about 1.45 times the single step's time, which pays when the
-  // search is throughput-bound and hurts the critical path when it is not, so pairing
-  // is used only when there are at least two narrow items per wave slot, and only for
-  // items whose paired time stays under a quarter of the estimated search time.  Wide
-  // pairs stay single, in int32.  (Knob value 2 pairs every unsplit pair, wide ones
-  // included: a test setting.)
-  const int64_t pair_mode = g_knob_intra_pairs.load();
-  const bool pair_all = pair_mode == 2;
-  const bool pair_narrow = pair_mode == 1 &&
-                           narrow.size() >= 2 * (size_t)std::max(1, db->num_cu) * kIntraWaves;
-  const bool pair_wide = pair_mode == 1 && wide.size() >= 2 * (size_t)std::max(1, db->num_cu);
-  const bool pairs16 = pair_all || pair_narrow || pair_wide;
-  PairItem none;
-  std::memset(&none, 0, sizeof(none));
-  none.len = -1;
-  none.out = -1;
-  std::vector<int64_t> pending((size_t)nq, -1);  // index in longitems of an unpaired item
-  auto emit = [&](const PairItem &it, bool pairable) {
-    if (pairs16 && pairable) {
-      int64_t &pend = pending[(size_t)it.query];
-      if (pend >= 0) {
-        p.second[(size_t)pend] = it;
-        pend = -1;
-        ++p.nduos;
-        return;
-      }
-      pend = (int64_t)p.longitems.size();
-    }
-    p.longitems.push_back(it);
-    p.second.push_back(none);
-  };
-  for (auto &x : wide) {
-    const PairItem &it = x.second;
-    const int32_t nb = it.band1;
-    const int64_t nc = ((int64_t)it.len + 126) / 64;
-    const int64_t nce = std::max<int64_t>(nc, (int64_t)kIntraLag * p.main_waves);
-    const int64_t lastb = nb - 1;
-    const double whole = (double)((lastb / p.main_waves) * nce + kIntraLag * (lastb % p.main_waves) + nc);
-    const double piped = (double)(nc + (int64_t)kIntraLag * lastb);
-    const int32_t s8 = (nb + p.main_waves - 1) / p.main_waves, s4 = (nb + 3) / 4;
-    int32_t S = 1;
-    if (whole * 64 * t_step > 0.5 * t_search) S = piped * 64 * t_step <= t_search ? s8 : s4;
-    if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
-    S = std::max<int32_t>(1, std::min(S, nb));
-    if (S == 1) {
-      emit(it, pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
-      continue;
-    }
-    // A pair whose full pipeline would outlast the search sets its critical path; with
-    // bands of 64 * kCritR rows a step takes 7.5 kCritR + 14 instructions instead of
-    // 7.5 R + 14, over more, shorter bands, so such pairs get a launch of their own with
-    // that height (segments of kCritWaves bands, one wave per SIMD) when it shortens their
-    // pipeline.
-    // (A wave alone on its SIMD steps in about 0.76 of t_step: 0.38 us at R = 16 on
-    // MI355X, where latency keeps a step at about 1.7 times its instruction time.)
-    if (S == s4 && p.R > kCritR && g_knob_intra_rows.load() == 0 && cap == 0 &&
-        piped * 64 * 0.76 * t_step > 0.5 * t_search) {  // still critical with a SIMD per wave
-      const int32_t nbc = (int32_t)((lens[it.query] + 64 * kCritR - 1) / (64 * kCritR));
-      const double piped_c = (double)(nc + (int64_t)kIntraLag * (nbc - 1));
-      const double step_c = (7.5 * kCritR + 14.0) / (7.5 * p.R + 14.0);
-      if (piped_c * step_c < piped) {
-        const int32_t Sc = (nbc + kCritWaves - 1) / kCritWaves;
-        const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
-        for (int32_t j = 0; j < Sc; ++j) {
-          PairItem sg = it;
-          sg.band0 = (int32_t)((int64_t)nbc * j / Sc);
-          sg.band1 = (int32_t)((int64_t)nbc * (j + 1) / Sc);
-          sg.segment = j;
-          sg.nsegments = Sc;
-          if (j > 0) {
-            sg.xin = p.xbnd_elems - npad;
-            sg.prog_in = p.nprog - 1;
-          }
-          if (j + 1 < Sc) {
-            sg.xout = p.xbnd_elems;
-            sg.prog_out = p.nprog;
-            p.xbnd_elems += npad;
-            p.nprog += 1;
-          }
-          p.crititems.push_back(sg);
-        }
-        continue;
-      }
-    }
-    const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
-    for (int32_t j = 0; j < S; ++j) {
-      PairItem sg = it;
-      sg.band0 = (int32_t)((int64_t)nb * j / S);
-      sg.band1 = (int32_t)((int64_t)nb * (j + 1) / S);
-      sg.segment = j;
-      sg.nsegments = S;
-      if (j > 0) {
-        sg.xin = p.xbnd_elems - npad;
-        sg.prog_in = p.nprog - 1;
-      }
-      if (j + 1 < S) {
-        sg.xout = p.xbnd_elems;
-        sg.prog_out = p.nprog;
-        p.xbnd_elems += npad;
-        p.nprog += 1;
-      }
-      p.longitems.push_back(sg);
-      p.second.push_back(none);
-    }
-  }
-  p.n_wide = (int32_t)p.longitems.size();
-  std::fill(pending.begin(), pending.end(), -1);  // wide and narrow items are not mixed
-  for (auto &x : narrow) {
-    const PairItem &it = x.second;
-    const double single = (double)it.band1 * (double)((it.len + 126) / 64) * 64 * t_step;
-    emit(it, pair_all || (pair_narrow && 1.45 * single <= 0.25 * t_search));
-  }
-
-  const int64_t nitems16 = (int64_t)ninter * nunits;
-  p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db->num_cu);
-  {
-    // algorithmic cells (query rows x unpadded residues) of each launch
-    int64_t sum_all = 0;
-    for (int64_t q = 0; q < nq; ++q) sum_all += lens[q];
-    auto rows_of = [&](const PairItem &it, int R) {
-      const int64_t m = lens[(size_t)it.query];
-      return std::min<int64_t>(m, (int64_t)it.band1 * 64 * R) - (int64_t)it.band0 * 64 * R;
-    };
-    int64_t c32 = 0, c16 = 0, ccrit = 0;
-    for (size_t k = 0; k < p.longitems.size(); ++k) {
-      const PairItem &it = p.longitems[k];
-      if (p.second[k].len >= 0)
-        c16 += (int64_t)(it.len + p.second[k].len) * lens[(size_t)it.query];
-      else
-        c32 += (int64_t)it.len * rows_of(it, p.R);
-    }
-    for (const PairItem &it : p.crititems) ccrit += (int64_t)it.len * rows_of(it, kCritR);
-    int64_t *st = p.stats;
-    st[SW_ST_CELLS_INTER16] = sum_all * db->group_res[(size_t)ninter];
-    st[SW_ST_CELLS_INTRA32] = c32;
-    st[SW_ST_CELLS_INTRA16] = c16;
-    st[SW_ST_CELLS_CRIT] = ccrit;
-    st[SW_ST_INTRA_ROWS] = p.R;
-    st[SW_ST_MAIN_WAVES] = p.main_waves;
-    st[SW_ST_ROUTED_GROUPS] = db->ngroups - ninter;
-    st[SW_ST_STRIP_ROWS] = p.T;
-    st[SW_ST_QUERY_PAIRS] = q2 ? 1 : 0;
-  }
-  // Two waves per SIMD: one persistent 8-wave workgroup per compute unit, or two 4-wave
-  // ones.  The kernel's per-step profile gathers touch one cache line per lane, and a
-  // second resident 8-wave workgroup per CU (four waves per SIMD) measured slower and
-  // erratic on MI355X (86 ms vs 103-115 ms for a 35000-residue query over the
-  // long-sequence mix), not faster.
-  const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
-  // The critical pairs' launch (a workgroup of kCritWaves waves per CU, one band and one
-  // wave per SIMD) is enqueued first and gets its CUs first; the main launch still asks
-  // for one workgroup per CU, and the ones that find no free CU start as the critical
-  // workgroups finish.
-  p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(), std::max(1, db->num_cu));
-  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + p.main_waves - 1) / p.main_waves,
-                                       (int64_t)db->num_cu * (kIntraWaves / p.main_waves));
-  // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
-  // and nothing is launched when no kernel can append to it
-  const bool may_flag = (nitems16 > 0 && p.grid16 > 0) || p.nduos > 0;
-  p.grid_re = (may_flag && nq > 0) ? std::max(1, db->num_cu / 4) : 0;
-  const int grid32 = p.grid_long + p.grid_re + p.grid_crit;
-
-  // workspace sizes
-  const int64_t qbytes = qoff[nq];
-  const size_t bnd16_slot = (size_t)db->max_ncols * 64 * (q2 ? 2 : 1);  // dwords
-  const int bnd32_stride = ((db->max_len + 128 + 63) / 64) * 64;
-  const size_t bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * bnd32_stride;
-  // saturated pairs: any database sequence, from either kernel
-  const size_t need_flagged = (size_t)std::max<int64_t>(1, db->n_seqs * nq);
-  const int64_t cap_mb = g_knob_mem_cap_mb.load();
-  {
-    size_t need = (size_t)qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
-                  (size_t)p.qp16_elems * 2 + (size_t)p.qp2_elems * 4 + (size_t)p.qp8_elems +
-                  sizeof(Counters) + p.pairs.size() * sizeof(QueryPair) +
-                  need_flagged * sizeof(PairItem) +
-                  (2 * p.longitems.size() + p.crititems.size()) * sizeof(PairItem) +
-                  (size_t)p.grid16 * bnd16_slot * 4 + (size_t)grid32 * bnd32_slot * 8 +
-                  (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
-    if (cap_mb > 0 && (int64_t)(std::max(need, w->total_bytes()) >> 20) > cap_mb)
-      throw HipFail{hipErrorOutOfMemory};
-  }
+  const Knobs knobs = knob_snapshot();
+  const Plan p = make_plan(db_view(db), qoff, nq, knobs, occupancy());
+  const bool q2 = p.q2;
+  const int64_t nitems16 = p.nitems16;
+  const std::vector<int32_t> &qorder = p.qorder;
+  const int64_t qbytes = p.qbytes;
+  const size_t bnd16_slot = p.bnd16_slot, bnd32_slot = p.bnd32_slot;
+  const int bnd32_stride = p.bnd32_stride;
+  const int grid32 = p.grid32;
+  const size_t need_flagged = p.need_flagged;
+  if (knobs.mem_cap_mb > 0 &&
+      (int64_t)(std::max(p.need_bytes, w->total_bytes()) >> 20) > knobs.mem_cap_mb)
+    throw HipFail{hipErrorOutOfMemory};
   // small per-call inputs, staged through pinned memory (reused only after `done`) and
   // copied to the device in one transfer
-  const size_t off_qoff = ((size_t)qbytes + 63) & ~size_t(63);
-  const size_t off_qd = off_qoff + (((size_t)(nq + 1) * 8 + 63) & ~size_t(63));
-  const size_t off_mx = off_qd + ((nq * sizeof(QueryDesc) + 63) & ~size_t(63));
-  const size_t off_qo = off_mx + (((size_t)A * A * 4 + 63) & ~size_t(63));
-  const size_t off_li = off_qo + ((nq * sizeof(int32_t) + 63) & ~size_t(63));
-  const size_t off_se = off_li + ((p.longitems.size() * sizeof(PairItem) + 63) & ~size_t(63));
-  const size_t off_cr = off_se + ((p.second.size() * sizeof(PairItem) + 63) & ~size_t(63));
-  const size_t off_pr = off_cr + ((p.crititems.size() * sizeof(PairItem) + 63) & ~size_t(63));
-  const size_t stage_bytes = off_pr + p.pairs.size() * sizeof(QueryPair) + 64;
+  const size_t off_qoff = p.off_qoff, off_qd = p.off_qd, off_mx = p.off_mx, off_qo = p.off_qo,
+               off_li = p.off_li, off_se = p.off_se, off_cr = p.off_cr, off_pr = p.off_pr,
+               stage_bytes = p.stage_bytes;
   grow(w->inputs, stage_bytes);
   // (the int16 strip profiles of k_inter16, or the pair profiles of the two-query kernel)
   grow(w->qp16, (size_t)std::max<int64_t>({16, p.qp16_elems * 2, p.qp2_elems * 4}));
@@ -1063,152 +659,156 @@ SW_API int64_t sw_get_knob(int32_t knob) {
 
 SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs,
                       int32_t alphabet, sw_db **out) {
-  if (!out || !offsets || n_seqs < 0) return SW_EINVAL;
-  if (alphabet < 1 || alphabet > SW_MAX_ALPHABET) return SW_EINVAL;
-  if (n_seqs > INT32_MAX / 2) return SW_EINVAL;
-  if (offsets[0] != 0) return SW_EINVAL;
-  for (int64_t k = 0; k < n_seqs; ++k) {
-    if (offsets[k + 1] < offsets[k]) return SW_EINVAL;
-    if (offsets[k + 1] - offsets[k] > (int64_t)INT32_MAX / 2) return SW_EINVAL;
-  }
-  const int64_t total = total_of(offsets, n_seqs);
-  if (total > 0 && !residues) return SW_EINVAL;
-  for (int64_t i = 0; i < total; ++i)
-    if (residues[i] >= alphabet) return SW_EINVAL;
-
-  sw_db *db = new (std::nothrow) sw_db();
-  if (!db) return SW_ENOMEM;
-  void *d_raw = nullptr, *d_off = nullptr;
-  try {
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw HipFail{hipErrorNoDevice};
-    hip_check(hipGetDevice(&db->device));
-    hipDeviceProp_t prop;
-    hip_check(hipGetDeviceProperties(&prop, db->device));
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) throw HipFail{hipErrorNoBinaryForGpu};
-    db->num_cu = prop.multiProcessorCount;
-    db->n_seqs = n_seqs;
-    db->alphabet = alphabet;
-    db->residues = total;
-
-    // Section 4: sort by length (ascending, stable), route the longest sequences to the
-    // intra-task kernel, group the rest 64 at a time and pad each group to its longest.
-    std::vector<int32_t> order((size_t)n_seqs);
-    std::iota(order.begin(), order.end(), 0);
-    auto len_of = [&](int32_t k) { return offsets[k + 1] - offsets[k]; };
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t x, int32_t y) { return len_of(x) < len_of(y); });
-    const int64_t lmax = g_knob_intra_min_len.load();
-    int64_t n_short = 0;
-    while (n_short < n_seqs && len_of(order[n_short]) <= lmax) ++n_short;
-    db->n_short = n_short;
-    db->max_len = n_seqs ? (int32_t)len_of(order[n_seqs - 1]) : 0;
-
-    std::vector<GroupDesc> groups;
-    int64_t bytes = 0;
-    for (int64_t f = 0; f < n_short; f += kGroup) {
-      GroupDesc g;
-      g.first = (int32_t)f;
-      g.count = (int32_t)std::min<int64_t>(kGroup, n_short - f);
-      g.maxlen = (int32_t)len_of(order[f + g.count - 1]);
-      g.ncols = ((g.maxlen + 2 + 3) / 4) * 4;
-      g.base = bytes;
-      bytes += (int64_t)g.ncols * 64;
-      db->max_ncols = std::max(db->max_ncols, g.ncols);
-      groups.push_back(g);
+  return abi_guard([&]() -> int {
+    if (!out || !offsets || n_seqs < 0) return SW_EINVAL;
+    if (alphabet < 1 || alphabet > SW_MAX_ALPHABET) return SW_EINVAL;
+    if (n_seqs > INT32_MAX / 2) return SW_EINVAL;
+    if (offsets[0] != 0) return SW_EINVAL;
+    for (int64_t k = 0; k < n_seqs; ++k) {
+      if (offsets[k + 1] < offsets[k]) return SW_EINVAL;
+      if (offsets[k + 1] - offsets[k] > (int64_t)INT32_MAX / 2) return SW_EINVAL;
     }
-    db->ngroups = (int32_t)groups.size();
-    for (int64_t p = 0; p < n_short; ++p) db->short_residues += len_of(order[p]);
-    db->group_res.assign(groups.size() + 1, 0);
-    for (size_t g = 0; g < groups.size(); ++g) {
-      int64_t r = 0;
-      for (int32_t l = 0; l < groups[g].count; ++l) r += len_of(order[groups[g].first + l]);
-      db->group_res[g + 1] = db->group_res[g] + r;
-    }
-    std::vector<int32_t> lens((size_t)std::max<int64_t>(1, n_short));
-    for (int64_t p = 0; p < n_short; ++p) lens[p] = (int32_t)len_of(order[p]);
-    for (int64_t p = n_seqs - 1; p >= n_short; --p) {  // longest first
-      sw_db::LongSeq L;
-      L.base = bytes;
-      L.len = (int32_t)len_of(order[p]);
-      L.orig = order[p];
-      bytes += ((L.len + 4 + 3) / 4) * 4;
-      db->longs.push_back(L);
-    }
+    const int64_t total = total_of(offsets, n_seqs);
+    if (total > 0 && !residues) return SW_EINVAL;
+    for (int64_t i = 0; i < total; ++i)
+      if (residues[i] >= alphabet) return SW_EINVAL;
 
-    grow(db->packed, (size_t)std::max<int64_t>(bytes, 4));
-    grow(db->groups, std::max<size_t>(1, groups.size()) * sizeof(GroupDesc));
-    grow(db->perm, (size_t)std::max<int64_t>(1, n_seqs) * 4);
-    grow(db->lens, lens.size() * 4);
-    if (!groups.empty())
-      hip_check(hipMemcpy(db->groups.ptr, groups.data(), groups.size() * sizeof(GroupDesc),
-                          hipMemcpyHostToDevice));
-    if (n_seqs)
-      hip_check(hipMemcpy(db->perm.ptr, order.data(), (size_t)n_seqs * 4, hipMemcpyHostToDevice));
-    hip_check(hipMemcpy(db->lens.ptr, lens.data(), lens.size() * 4, hipMemcpyHostToDevice));
+    sw_db *db = new (std::nothrow) sw_db();
+    if (!db) return SW_ENOMEM;
+    void *d_raw = nullptr, *d_off = nullptr;
+    try {
+      int ndev = 0;
+      if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) throw HipFail{hipErrorNoDevice};
+      hip_check(hipGetDevice(&db->device));
+      hipDeviceProp_t prop;
+      hip_check(hipGetDeviceProperties(&prop, db->device));
+      if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) throw HipFail{hipErrorNoBinaryForGpu};
+      db->num_cu = prop.multiProcessorCount;
+      db->n_seqs = n_seqs;
+      db->alphabet = alphabet;
+      db->residues = total;
 
-    if (total > 0) {
-      hip_check(hipMalloc(&d_raw, (size_t)total));
-      hip_check(hipMalloc(&d_off, (size_t)(n_seqs + 1) * 8));
-      hip_check(hipMemcpy(d_raw, residues, (size_t)total, hipMemcpyHostToDevice));
-      hip_check(hipMemcpy(d_off, offsets, (size_t)(n_seqs + 1) * 8, hipMemcpyHostToDevice));
-      PackArgs pa;
-      pa.raw = (const uint8_t *)d_raw;
-      pa.offsets = (const int64_t *)d_off;
-      pa.perm = (const int32_t *)db->perm.ptr;
-      pa.groups = (const GroupDesc *)db->groups.ptr;
-      pa.ngroups = db->ngroups;
-      pa.packed = (uint8_t *)db->packed.ptr;
-      hip_check(launch_pack(pa, nullptr));
-      for (const auto &L : db->longs) {
-        const int64_t padded = ((L.len + 4 + 3) / 4) * 4;
-        hip_check(hipMemsetD8((hipDeviceptr_t)((uint8_t *)db->packed.ptr + L.base), kPadCode,
-                              (size_t)padded));
-        hip_check(hipMemcpy((uint8_t *)db->packed.ptr + L.base,
-                            (const uint8_t *)d_raw + offsets[L.orig], (size_t)L.len,
-                            hipMemcpyDeviceToDevice));
+      // Section 4: sort by length (ascending, stable), route the longest sequences to the
+      // intra-task kernel, group the rest 64 at a time and pad each group to its longest.
+      std::vector<int32_t> order((size_t)n_seqs);
+      std::iota(order.begin(), order.end(), 0);
+      auto len_of = [&](int32_t k) { return offsets[k + 1] - offsets[k]; };
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int32_t x, int32_t y) { return len_of(x) < len_of(y); });
+      const int64_t lmax = g_knob_intra_min_len.load();
+      int64_t n_short = 0;
+      while (n_short < n_seqs && len_of(order[n_short]) <= lmax) ++n_short;
+      db->n_short = n_short;
+      db->max_len = n_seqs ? (int32_t)len_of(order[n_seqs - 1]) : 0;
+
+      std::vector<GroupDesc> groups;
+      int64_t bytes = 0;
+      for (int64_t f = 0; f < n_short; f += kGroup) {
+        GroupDesc g;
+        g.first = (int32_t)f;
+        g.count = (int32_t)std::min<int64_t>(kGroup, n_short - f);
+        g.maxlen = (int32_t)len_of(order[f + g.count - 1]);
+        g.ncols = ((g.maxlen + 2 + 3) / 4) * 4;
+        g.base = bytes;
+        bytes += (int64_t)g.ncols * 64;
+        db->max_ncols = std::max(db->max_ncols, g.ncols);
+        groups.push_back(g);
       }
-      hip_check(hipDeviceSynchronize());
-      hip_check(hipFree(d_raw));
-      d_raw = nullptr;
-      hip_check(hipFree(d_off));
-      d_off = nullptr;
+      db->ngroups = (int32_t)groups.size();
+      for (int64_t p = 0; p < n_short; ++p) db->short_residues += len_of(order[p]);
+      db->group_res.assign(groups.size() + 1, 0);
+      for (size_t g = 0; g < groups.size(); ++g) {
+        int64_t r = 0;
+        for (int32_t l = 0; l < groups[g].count; ++l) r += len_of(order[groups[g].first + l]);
+        db->group_res[g + 1] = db->group_res[g] + r;
+      }
+      std::vector<int32_t> lens((size_t)std::max<int64_t>(1, n_short));
+      for (int64_t p = 0; p < n_short; ++p) lens[p] = (int32_t)len_of(order[p]);
+      for (int64_t p = n_seqs - 1; p >= n_short; --p) {  // longest first
+        LongSeq L;
+        L.base = bytes;
+        L.len = (int32_t)len_of(order[p]);
+        L.orig = order[p];
+        bytes += ((L.len + 4 + 3) / 4) * 4;
+        db->longs.push_back(L);
+      }
+
+      grow(db->packed, (size_t)std::max<int64_t>(bytes, 4));
+      grow(db->groups, std::max<size_t>(1, groups.size()) * sizeof(GroupDesc));
+      grow(db->perm, (size_t)std::max<int64_t>(1, n_seqs) * 4);
+      grow(db->lens, lens.size() * 4);
+      if (!groups.empty())
+        hip_check(hipMemcpy(db->groups.ptr, groups.data(), groups.size() * sizeof(GroupDesc),
+                            hipMemcpyHostToDevice));
+      if (n_seqs)
+        hip_check(hipMemcpy(db->perm.ptr, order.data(), (size_t)n_seqs * 4, hipMemcpyHostToDevice));
+      hip_check(hipMemcpy(db->lens.ptr, lens.data(), lens.size() * 4, hipMemcpyHostToDevice));
+
+      if (total > 0) {
+        hip_check(hipMalloc(&d_raw, (size_t)total));
+        hip_check(hipMalloc(&d_off, (size_t)(n_seqs + 1) * 8));
+        hip_check(hipMemcpy(d_raw, residues, (size_t)total, hipMemcpyHostToDevice));
+        hip_check(hipMemcpy(d_off, offsets, (size_t)(n_seqs + 1) * 8, hipMemcpyHostToDevice));
+        PackArgs pa;
+        pa.raw = (const uint8_t *)d_raw;
+        pa.offsets = (const int64_t *)d_off;
+        pa.perm = (const int32_t *)db->perm.ptr;
+        pa.groups = (const GroupDesc *)db->groups.ptr;
+        pa.ngroups = db->ngroups;
+        pa.packed = (uint8_t *)db->packed.ptr;
+        hip_check(launch_pack(pa, nullptr));
+        for (const auto &L : db->longs) {
+          const int64_t padded = ((L.len + 4 + 3) / 4) * 4;
+          hip_check(hipMemsetD8((hipDeviceptr_t)((uint8_t *)db->packed.ptr + L.base), kPadCode,
+                                (size_t)padded));
+          hip_check(hipMemcpy((uint8_t *)db->packed.ptr + L.base,
+                              (const uint8_t *)d_raw + offsets[L.orig], (size_t)L.len,
+                              hipMemcpyDeviceToDevice));
+        }
+        hip_check(hipDeviceSynchronize());
+        hip_check(hipFree(d_raw));
+        d_raw = nullptr;
+        hip_check(hipFree(d_off));
+        d_off = nullptr;
+      }
+      db->hgroups = std::move(groups);
+      db->hperm = std::move(order);
+      db->hlens = std::move(lens);
+    } catch (const HipFail &f) {
+      if (d_raw) (void)hipFree(d_raw);
+      if (d_off) (void)hipFree(d_off);
+      db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+      delete db;
+      return f.err == hipErrorNoDevice || f.err == hipErrorNoBinaryForGpu ? SW_EDEVICE
+                                                                        : map_hip(f.err);
+    } catch (const std::bad_alloc &) {
+      if (d_raw) (void)hipFree(d_raw);
+      if (d_off) (void)hipFree(d_off);
+      db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+      delete db;
+      return SW_ENOMEM;
     }
-    db->hgroups = std::move(groups);
-    db->hperm = std::move(order);
-    db->hlens = std::move(lens);
-  } catch (const HipFail &f) {
-    if (d_raw) (void)hipFree(d_raw);
-    if (d_off) (void)hipFree(d_off);
-    db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
-    delete db;
-    return f.err == hipErrorNoDevice || f.err == hipErrorNoBinaryForGpu ? SW_EDEVICE
-                                                                      : map_hip(f.err);
-  } catch (const std::bad_alloc &) {
-    if (d_raw) (void)hipFree(d_raw);
-    if (d_off) (void)hipFree(d_off);
-    db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
-    delete db;
-    return SW_ENOMEM;
-  }
-  *out = db;
-  return SW_OK;
+    *out = db;
+    return SW_OK;
+  });
 }
 
 SW_API int64_t sw_db_size(const sw_db *db) { return db ? db->n_seqs : SW_ENODB; }
 
 SW_API void sw_db_free(sw_db *db) {
-  if (!db) return;
-  (void)hipSetDevice(db->device);
-  for (Workspace *w : db->pool) destroy_workspace(w);
-  for (auto &e : db->timing_events) {
-    (void)hipEventDestroy(e.e0);
-    (void)hipEventDestroy(e.e1);
-  }
-  for (hipEvent_t e : db->spare_events) (void)hipEventDestroy(e);
-  db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
-  db->topk_scratch.release();
-  delete db;
+  abi_guard_void([&]() {
+    if (!db) return;
+    (void)hipSetDevice(db->device);
+    for (Workspace *w : db->pool) destroy_workspace(w);
+    for (auto &e : db->timing_events) {
+      (void)hipEventDestroy(e.e0);
+      (void)hipEventDestroy(e.e1);
+    }
+    for (hipEvent_t e : db->spare_events) (void)hipEventDestroy(e);
+    db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+    db->topk_scratch.release();
+    delete db;
+  });
 }
 
 namespace {
@@ -1298,92 +898,106 @@ int run_search(const sw_db *cdb, const uint8_t *queries, const int64_t *qoff, in
 SW_API int sw_search(const sw_db *db, const uint8_t *query, int32_t query_len,
                      const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
                      int32_t *scores_out) {
-  int rc = validate_search(db, matrix, gap_open, gap_extend);
-  if (rc) return rc;
-  if (!scores_out && db->n_seqs > 0) return SW_EINVAL;
-  if ((rc = validate_query(db, query, query_len))) return rc;
-  const int64_t qoff[2] = {0, query_len};
-  return run_search(db, query, qoff, 1, matrix, gap_open, gap_extend, scores_out, nullptr, nullptr);
+  return abi_guard([&]() -> int {
+    int rc = validate_search(db, matrix, gap_open, gap_extend);
+    if (rc) return rc;
+    if (!scores_out && db->n_seqs > 0) return SW_EINVAL;
+    if ((rc = validate_query(db, query, query_len))) return rc;
+    const int64_t qoff[2] = {0, query_len};
+    return run_search(db, query, qoff, 1, matrix, gap_open, gap_extend, scores_out, nullptr, nullptr);
+  });
 }
 
 SW_API int sw_search_async(const sw_db *db, const uint8_t *query, int32_t query_len,
                            const int32_t *matrix, int32_t gap_open, int32_t gap_extend,
                            int32_t *scores_dev, void *hip_stream) {
-  int rc = validate_search(db, matrix, gap_open, gap_extend);
-  if (rc) return rc;
-  if (!scores_dev && db->n_seqs > 0) return SW_EINVAL;
-  if ((rc = validate_query(db, query, query_len))) return rc;
-  if (db->n_seqs == 0) return SW_OK;
-  const int64_t qoff[2] = {0, query_len};
-  return run_search(db, query, qoff, 1, matrix, gap_open, gap_extend, nullptr, scores_dev,
-                    (hipStream_t)hip_stream);
+  return abi_guard([&]() -> int {
+    int rc = validate_search(db, matrix, gap_open, gap_extend);
+    if (rc) return rc;
+    if (!scores_dev && db->n_seqs > 0) return SW_EINVAL;
+    if ((rc = validate_query(db, query, query_len))) return rc;
+    if (db->n_seqs == 0) return SW_OK;
+    const int64_t qoff[2] = {0, query_len};
+    return run_search(db, query, qoff, 1, matrix, gap_open, gap_extend, nullptr, scores_dev,
+                      (hipStream_t)hip_stream);
+  });
 }
 
 SW_API int sw_search_batch(const sw_db *db, const uint8_t *queries, const int64_t *query_offsets,
                            int64_t n_queries, const int32_t *matrix, int32_t gap_open,
                            int32_t gap_extend, int32_t *scores_out) {
-  int rc = validate_search(db, matrix, gap_open, gap_extend);
-  if (rc) return rc;
-  if (n_queries < 0 || !query_offsets || query_offsets[0] != 0) return SW_EINVAL;
-  if (n_queries > 0 && db->n_seqs > 0 && !scores_out) return SW_EINVAL;
-  if ((double)n_queries * (double)db->n_seqs > 2.0e9) return SW_EINVAL;
-  for (int64_t q = 0; q < n_queries; ++q) {
-    if (query_offsets[q + 1] < query_offsets[q]) return SW_EINVAL;
-    const int64_t m = query_offsets[q + 1] - query_offsets[q];
-    if ((rc = validate_query(db, queries ? queries + query_offsets[q] : nullptr, m))) return rc;
-  }
-  return run_search(db, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
-                    scores_out, nullptr, nullptr);
+  return abi_guard([&]() -> int {
+    int rc = validate_search(db, matrix, gap_open, gap_extend);
+    if (rc) return rc;
+    if (n_queries < 0 || !query_offsets || query_offsets[0] != 0) return SW_EINVAL;
+    if (n_queries > 0 && db->n_seqs > 0 && !scores_out) return SW_EINVAL;
+    if ((double)n_queries * (double)db->n_seqs > 2.0e9) return SW_EINVAL;
+    for (int64_t q = 0; q < n_queries; ++q) {
+      if (query_offsets[q + 1] < query_offsets[q]) return SW_EINVAL;
+      const int64_t m = query_offsets[q + 1] - query_offsets[q];
+      if ((rc = validate_query(db, queries ? queries + query_offsets[q] : nullptr, m))) return rc;
+    }
+    return run_search(db, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
+                      scores_out, nullptr, nullptr);
+  });
 }
 
 SW_API int sw_timing_enable(sw_db *db, int32_t enable) {
-  if (!db) return SW_ENODB;
-  std::lock_guard<std::mutex> lk(db->mu);
-  db->timing = enable != 0;
-  for (int k = 0; k < 3; ++k) {
-    db->timing_launches[k] = 0;
-    db->timing_ms[k] = 0.0;
-  }
-  for (auto &e : db->timing_events) {  // recorded, possibly unfinished: not reused
-    (void)hipEventDestroy(e.e0);
-    (void)hipEventDestroy(e.e1);
-  }
-  db->timing_events.clear();
-  return SW_OK;
+  return abi_guard([&]() -> int {
+    if (!db) return SW_ENODB;
+    std::lock_guard<std::mutex> lk(db->mu);
+    db->timing = enable != 0;
+    for (int k = 0; k < 3; ++k) {
+      db->timing_launches[k] = 0;
+      db->timing_ms[k] = 0.0;
+    }
+    for (auto &e : db->timing_events) {  // recorded, possibly unfinished: not reused
+      (void)hipEventDestroy(e.e0);
+      (void)hipEventDestroy(e.e1);
+    }
+    db->timing_events.clear();
+    return SW_OK;
+  });
 }
 
 SW_API int sw_timing_read_kernel(const sw_db *cdb, int32_t kernel, int64_t *launches,
                                  double *total_ms) {
-  if (!cdb) return SW_ENODB;
-  if (!launches || !total_ms || kernel < 0 || kernel > 2) return SW_EINVAL;
-  sw_db *db = const_cast<sw_db *>(cdb);
-  std::lock_guard<std::mutex> lk(db->mu);
-  for (auto &e : db->timing_events) {
-    float ms = 0.f;
-    if (hipEventSynchronize(e.e1) != hipSuccess) return SW_EDEVICE;
-    if (hipEventElapsedTime(&ms, e.e0, e.e1) != hipSuccess) return SW_EDEVICE;
-    db->timing_launches[e.kind] += 1;
-    db->timing_ms[e.kind] += ms;
-    db->spare_events.push_back(e.e0);
-    db->spare_events.push_back(e.e1);
-  }
-  db->timing_events.clear();
-  *launches = db->timing_launches[kernel];
-  *total_ms = db->timing_ms[kernel];
-  return SW_OK;
+  return abi_guard([&]() -> int {
+    if (!cdb) return SW_ENODB;
+    if (!launches || !total_ms || kernel < 0 || kernel > 2) return SW_EINVAL;
+    sw_db *db = const_cast<sw_db *>(cdb);
+    std::lock_guard<std::mutex> lk(db->mu);
+    for (auto &e : db->timing_events) {
+      float ms = 0.f;
+      if (hipEventSynchronize(e.e1) != hipSuccess) return SW_EDEVICE;
+      if (hipEventElapsedTime(&ms, e.e0, e.e1) != hipSuccess) return SW_EDEVICE;
+      db->timing_launches[e.kind] += 1;
+      db->timing_ms[e.kind] += ms;
+      db->spare_events.push_back(e.e0);
+      db->spare_events.push_back(e.e1);
+    }
+    db->timing_events.clear();
+    *launches = db->timing_launches[kernel];
+    *total_ms = db->timing_ms[kernel];
+    return SW_OK;
+  });
 }
 
 SW_API int sw_search_stats(const sw_db *cdb, int64_t *values, int32_t n) {
-  if (!cdb) return SW_ENODB;
-  if (!values || n < 0) return SW_EINVAL;
-  sw_db *db = const_cast<sw_db *>(cdb);
-  std::lock_guard<std::mutex> lk(db->mu);
-  for (int32_t k = 0; k < n && k < SW_SEARCH_NSTATS; ++k) values[k] = db->last_stats[k];
-  return SW_OK;
+  return abi_guard([&]() -> int {
+    if (!cdb) return SW_ENODB;
+    if (!values || n < 0) return SW_EINVAL;
+    sw_db *db = const_cast<sw_db *>(cdb);
+    std::lock_guard<std::mutex> lk(db->mu);
+    for (int32_t k = 0; k < n && k < SW_SEARCH_NSTATS; ++k) values[k] = db->last_stats[k];
+    return SW_OK;
+  });
 }
 
 SW_API int sw_timing_read(const sw_db *db, int64_t *launches, double *total_ms) {
-  return sw_timing_read_kernel(db, SW_KERNEL_INTER16, launches, total_ms);
+  return abi_guard([&]() -> int {
+    return sw_timing_read_kernel(db, SW_KERNEL_INTER16, launches, total_ms);
+  });
 }
 
 // ------------------------------------------------------------------------ plans
@@ -1401,82 +1015,88 @@ struct sw_plan {
 SW_API int sw_plan_create(const sw_db *cdb, const uint8_t *queries, const int64_t *query_offsets,
                           int64_t n_queries, const int32_t *matrix, int32_t gap_open,
                           int32_t gap_extend, int32_t *scores_dev, sw_plan **out) {
-  int rc = validate_search(cdb, matrix, gap_open, gap_extend);
-  if (rc) return rc;
-  if (!out || !query_offsets || n_queries < 1 || query_offsets[0] != 0) return SW_EINVAL;
-  if (!scores_dev && cdb->n_seqs > 0) return SW_EINVAL;
-  if ((double)n_queries * (double)cdb->n_seqs > 2.0e9) return SW_EINVAL;
-  for (int64_t q = 0; q < n_queries; ++q) {
-    if (query_offsets[q + 1] < query_offsets[q]) return SW_EINVAL;
-    const int64_t m = query_offsets[q + 1] - query_offsets[q];
-    if ((rc = validate_query(cdb, queries ? queries + query_offsets[q] : nullptr, m))) return rc;
-  }
-  sw_db *db = const_cast<sw_db *>(cdb);
-  sw_plan *plan = new (std::nothrow) sw_plan();
-  if (!plan) return SW_ENOMEM;
-  plan->db = db;
-  hipStream_t cap = nullptr;
-  try {
-    hip_check(hipSetDevice(db->device));
-    plan->w = new_workspace();
-    Workspace *w = plan->w;
-    if (db->n_seqs > 0) {
-      // eager run: allocates and fills every buffer
-      enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
-                     scores_dev, w->own, false);
-      hip_check(hipStreamSynchronize(w->own));
-      hip_check(hipStreamSynchronize(w->aux));
-      hip_check(hipStreamSynchronize(w->crit));
-      // capture the same launch sequence
-      hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-      hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-      try {
-        enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
-                       scores_dev, cap, false);
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(cap, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      hip_check(hipStreamEndCapture(cap, &plan->graph));
-      hip_check(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
-      hip_check(hipStreamDestroy(cap));
-      cap = nullptr;
+  return abi_guard([&]() -> int {
+    int rc = validate_search(cdb, matrix, gap_open, gap_extend);
+    if (rc) return rc;
+    if (!out || !query_offsets || n_queries < 1 || query_offsets[0] != 0) return SW_EINVAL;
+    if (!scores_dev && cdb->n_seqs > 0) return SW_EINVAL;
+    if ((double)n_queries * (double)cdb->n_seqs > 2.0e9) return SW_EINVAL;
+    for (int64_t q = 0; q < n_queries; ++q) {
+      if (query_offsets[q + 1] < query_offsets[q]) return SW_EINVAL;
+      const int64_t m = query_offsets[q + 1] - query_offsets[q];
+      if ((rc = validate_query(cdb, queries ? queries + query_offsets[q] : nullptr, m))) return rc;
     }
-  } catch (const HipFail &f) {
-    if (cap) (void)hipStreamDestroy(cap);
+    sw_db *db = const_cast<sw_db *>(cdb);
+    sw_plan *plan = new (std::nothrow) sw_plan();
+    if (!plan) return SW_ENOMEM;
+    plan->db = db;
+    hipStream_t cap = nullptr;
+    try {
+      hip_check(hipSetDevice(db->device));
+      plan->w = new_workspace();
+      Workspace *w = plan->w;
+      if (db->n_seqs > 0) {
+        // eager run: allocates and fills every buffer
+        enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
+                       scores_dev, w->own, false);
+        hip_check(hipStreamSynchronize(w->own));
+        hip_check(hipStreamSynchronize(w->aux));
+        hip_check(hipStreamSynchronize(w->crit));
+        // capture the same launch sequence
+        hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        try {
+          enqueue_search(db, w, queries, query_offsets, n_queries, matrix, gap_open, gap_extend,
+                         scores_dev, cap, false);
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(cap, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        hip_check(hipStreamEndCapture(cap, &plan->graph));
+        hip_check(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+        hip_check(hipStreamDestroy(cap));
+        cap = nullptr;
+      }
+    } catch (const HipFail &f) {
+      if (cap) (void)hipStreamDestroy(cap);
+      if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+      if (plan->graph) (void)hipGraphDestroy(plan->graph);
+      if (plan->w) destroy_workspace(plan->w);
+      delete plan;
+      return map_hip(f.err);
+    } catch (const std::bad_alloc &) {
+      if (cap) (void)hipStreamDestroy(cap);
+      if (plan->w) destroy_workspace(plan->w);
+      delete plan;
+      return SW_ENOMEM;
+    }
+    *out = plan;
+    return SW_OK;
+  });
+}
+
+SW_API int sw_plan_launch(sw_plan *plan, void *hip_stream) {
+  return abi_guard([&]() -> int {
+    if (!plan) return SW_EINVAL;
+    if (!plan->exec) return SW_OK;  // empty database: nothing to do
+    if (hipSetDevice(plan->db->device) != hipSuccess) return SW_EDEVICE;
+    const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
+    return e == hipSuccess ? SW_OK : map_hip(e);
+  });
+}
+
+SW_API void sw_plan_free(sw_plan *plan) {
+  abi_guard_void([&]() {
+    if (!plan) return;
+    (void)hipSetDevice(plan->db->device);
+    (void)hipDeviceSynchronize();
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->w) destroy_workspace(plan->w);
     delete plan;
-    return map_hip(f.err);
-  } catch (const std::bad_alloc &) {
-    if (cap) (void)hipStreamDestroy(cap);
-    if (plan->w) destroy_workspace(plan->w);
-    delete plan;
-    return SW_ENOMEM;
-  }
-  *out = plan;
-  return SW_OK;
-}
-
-SW_API int sw_plan_launch(sw_plan *plan, void *hip_stream) {
-  if (!plan) return SW_EINVAL;
-  if (!plan->exec) return SW_OK;  // empty database: nothing to do
-  if (hipSetDevice(plan->db->device) != hipSuccess) return SW_EDEVICE;
-  const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)hip_stream);
-  return e == hipSuccess ? SW_OK : map_hip(e);
-}
-
-SW_API void sw_plan_free(sw_plan *plan) {
-  if (!plan) return;
-  (void)hipSetDevice(plan->db->device);
-  (void)hipDeviceSynchronize();
-  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
-  if (plan->graph) (void)hipGraphDestroy(plan->graph);
-  if (plan->w) destroy_workspace(plan->w);
-  delete plan;
+  });
 }
 
 // ------------------------------------------------------------------------ serving
@@ -2140,180 +1760,194 @@ void server_destroy(sw_server *sv) {
 SW_API int sw_server_create(sw_db *db, const int32_t *matrix, int32_t gap_open,
                             int32_t gap_extend, int32_t slots, int32_t max_batch,
                             int64_t mem_budget_bytes, sw_server **out) {
-  int rc = validate_search(db, matrix, gap_open, gap_extend);
-  if (rc) return rc;
-  if (!out || slots < 1 || slots > 16 || max_batch < 1 || max_batch > 4096 ||
-      mem_budget_bytes < 0)
-    return SW_EINVAL;
-  sw_server *sv = new (std::nothrow) sw_server();
-  if (!sv) return SW_ENOMEM;
-  try {
-    sv->db = db;
-    sv->matrix.assign(matrix, matrix + (size_t)db->alphabet * db->alphabet);
-    sv->gap_open = gap_open;
-    sv->gap_extend = gap_extend;
-    sv->max_batch = max_batch;
-    sv->mem_budget = mem_budget_bytes;
-    hip_check(hipSetDevice(db->device));
-    const int per_cu = std::max(1, inter16_max_blocks_per_cu(24));
-    sv->fill_items = 4LL * per_cu * std::max(1, db->num_cu);
-    // Session mode when every record fills the device four times over and no sequence
-    // needs the intra-task kernel; its device scratch must fit the free memory and the
-    // budget, which also bounds the score rows.
-    sv->grid = std::max(1, serve_max_blocks_per_cu()) * std::max(1, db->num_cu);
-    sv->max_records = std::max(4, 4 * (int)slots);
-    sv->nrows = 2 * sv->max_records;
-    // score rows: two per record in flight, fewer if the budget says so (at least two)
-    const size_t row_bytes = (size_t)db->n_seqs * 4;
-    const int nrec = std::max(4, 2 * sv->max_records);
-    const size_t fixed = session_device_bytes(db, sv->grid, nrec, 0);
-    if (mem_budget_bytes > 0 && (int64_t)fixed < mem_budget_bytes)
-      sv->nrows = (int32_t)std::max<int64_t>(
-          2, std::min<int64_t>(sv->nrows, (mem_budget_bytes - (int64_t)fixed) / (int64_t)row_bytes));
-    const size_t dev_bytes = fixed + (size_t)sv->nrows * row_bytes;
-    const bool fits = dev_bytes + ((size_t)1 << 30) < device_free_bytes() &&
-                      (mem_budget_bytes == 0 || (int64_t)dev_bytes <= mem_budget_bytes);
-    sv->session_mode = db->longs.empty() && db->n_seqs > 0 &&
-                       (int64_t)db->ngroups >= 4LL * sv->grid && fits;
-    if (sv->session_mode) {
-      session_setup(sv);
-    } else {
-      sv->slots.resize((size_t)slots);
-      for (ServerSlot &sl : sv->slots) {
-        sl.w = new_workspace();
-        hip_check(hipEventCreateWithFlags(&sl.finished, hipEventDisableTiming));
+  return abi_guard([&]() -> int {
+    int rc = validate_search(db, matrix, gap_open, gap_extend);
+    if (rc) return rc;
+    if (!out || slots < 1 || slots > 16 || max_batch < 1 || max_batch > 4096 ||
+        mem_budget_bytes < 0)
+      return SW_EINVAL;
+    sw_server *sv = new (std::nothrow) sw_server();
+    if (!sv) return SW_ENOMEM;
+    try {
+      sv->db = db;
+      sv->matrix.assign(matrix, matrix + (size_t)db->alphabet * db->alphabet);
+      sv->gap_open = gap_open;
+      sv->gap_extend = gap_extend;
+      sv->max_batch = max_batch;
+      sv->mem_budget = mem_budget_bytes;
+      hip_check(hipSetDevice(db->device));
+      const int per_cu = std::max(1, inter16_max_blocks_per_cu(24));
+      sv->fill_items = 4LL * per_cu * std::max(1, db->num_cu);
+      // Session mode when every record fills the device four times over and no sequence
+      // needs the intra-task kernel; its device scratch must fit the free memory and the
+      // budget, which also bounds the score rows.
+      sv->grid = std::max(1, serve_max_blocks_per_cu()) * std::max(1, db->num_cu);
+      sv->max_records = std::max(4, 4 * (int)slots);
+      sv->nrows = 2 * sv->max_records;
+      // score rows: two per record in flight, fewer if the budget says so (at least two)
+      const size_t row_bytes = (size_t)db->n_seqs * 4;
+      const int nrec = std::max(4, 2 * sv->max_records);
+      const size_t fixed = session_device_bytes(db, sv->grid, nrec, 0);
+      if (mem_budget_bytes > 0 && (int64_t)fixed < mem_budget_bytes)
+        sv->nrows = (int32_t)std::max<int64_t>(
+            2, std::min<int64_t>(sv->nrows, (mem_budget_bytes - (int64_t)fixed) / (int64_t)row_bytes));
+      const size_t dev_bytes = fixed + (size_t)sv->nrows * row_bytes;
+      const bool fits = dev_bytes + ((size_t)1 << 30) < device_free_bytes() &&
+                        (mem_budget_bytes == 0 || (int64_t)dev_bytes <= mem_budget_bytes);
+      sv->session_mode = db->longs.empty() && db->n_seqs > 0 &&
+                         (int64_t)db->ngroups >= 4LL * sv->grid && fits;
+      if (sv->session_mode) {
+        session_setup(sv);
+      } else {
+        sv->slots.resize((size_t)slots);
+        for (ServerSlot &sl : sv->slots) {
+          sl.w = new_workspace();
+          hip_check(hipEventCreateWithFlags(&sl.finished, hipEventDisableTiming));
+        }
       }
+      sv->worker = std::thread(server_loop, sv);
+    } catch (const HipFail &f) {
+      server_destroy(sv);
+      return map_hip(f.err);
+    } catch (const std::bad_alloc &) {
+      server_destroy(sv);
+      return SW_ENOMEM;
+    } catch (...) {  // std::system_error from the worker thread
+      server_destroy(sv);
+      return SW_EDEVICE;
     }
-    sv->worker = std::thread(server_loop, sv);
-  } catch (const HipFail &f) {
-    server_destroy(sv);
-    return map_hip(f.err);
-  } catch (const std::bad_alloc &) {
-    server_destroy(sv);
-    return SW_ENOMEM;
-  } catch (...) {  // std::system_error from the worker thread
-    server_destroy(sv);
-    return SW_EDEVICE;
-  }
-  *out = sv;
-  return SW_OK;
+    *out = sv;
+    return SW_OK;
+  });
 }
 
 SW_API int sw_server_submit(sw_server *sv, const uint8_t *query, int32_t query_len,
                             int32_t *scores_out, uint64_t *ticket) {
-  if (!sv || !ticket) return SW_EINVAL;
-  if (!scores_out && sv->db->n_seqs > 0) return SW_EINVAL;
-  int rc = validate_query(sv->db, query, query_len);
-  if (rc) return rc;
-  ServerRequest *r = new (std::nothrow) ServerRequest();
-  if (!r) return SW_ENOMEM;
-  try {
-    r->query.assign(query, query + query_len);
-    r->scores_out = scores_out;
-    r->t_submit = now_s();
-    std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stop) {
+  return abi_guard([&]() -> int {
+    if (!sv || !ticket) return SW_EINVAL;
+    if (!scores_out && sv->db->n_seqs > 0) return SW_EINVAL;
+    int rc = validate_query(sv->db, query, query_len);
+    if (rc) return rc;
+    ServerRequest *r = new (std::nothrow) ServerRequest();
+    if (!r) return SW_ENOMEM;
+    try {
+      r->query.assign(query, query + query_len);
+      r->scores_out = scores_out;
+      r->t_submit = now_s();
+      std::lock_guard<std::mutex> lk(sv->mu);
+      if (sv->stop) {
+        delete r;
+        return SW_EINVAL;
+      }
+      r->ticket = sv->next_ticket++;
+      sv->requests[r->ticket] = r;
+      sv->queue.push_back(r);
+      *ticket = r->ticket;
+    } catch (...) {  // std::bad_alloc
       delete r;
-      return SW_EINVAL;
+      return SW_ENOMEM;
     }
-    r->ticket = sv->next_ticket++;
-    sv->requests[r->ticket] = r;
-    sv->queue.push_back(r);
-    *ticket = r->ticket;
-  } catch (...) {  // std::bad_alloc
-    delete r;
-    return SW_ENOMEM;
-  }
-  sv->cv.notify_one();
-  return SW_OK;
+    sv->cv.notify_one();
+    return SW_OK;
+  });
 }
 
 SW_API int sw_server_wait(sw_server *sv, uint64_t ticket, double *latency_ms,
                           double *queue_ms) {
-  if (!sv) return SW_EINVAL;
-  std::unique_lock<std::mutex> lk(sv->mu);
-  auto it = sv->requests.find(ticket);
-  if (it == sv->requests.end()) return SW_EINVAL;
-  ServerRequest *r = it->second;
-  sv->done_cv.wait(lk, [&] { return r->status != 1; });
-  const int status = r->status;
-  if (latency_ms) *latency_ms = (r->t_done - r->t_submit) * 1e3;
-  if (queue_ms) *queue_ms = (r->t_start > 0 ? r->t_start - r->t_submit : 0.0) * 1e3;
-  sv->requests.erase(it);
-  delete r;
-  return status;
+  return abi_guard([&]() -> int {
+    if (!sv) return SW_EINVAL;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->requests.find(ticket);
+    if (it == sv->requests.end()) return SW_EINVAL;
+    ServerRequest *r = it->second;
+    sv->done_cv.wait(lk, [&] { return r->status != 1; });
+    const int status = r->status;
+    if (latency_ms) *latency_ms = (r->t_done - r->t_submit) * 1e3;
+    if (queue_ms) *queue_ms = (r->t_start > 0 ? r->t_start - r->t_submit : 0.0) * 1e3;
+    sv->requests.erase(it);
+    delete r;
+    return status;
+  });
 }
 
 SW_API int sw_server_stats(sw_server *sv, int64_t *launches, int64_t *max_in_flight,
                            int64_t *refused) {
-  if (!sv) return SW_EINVAL;
-  std::lock_guard<std::mutex> lk(sv->mu);
-  if (launches) *launches = sv->launches;
-  if (max_in_flight) *max_in_flight = sv->max_in_flight;
-  if (refused) *refused = sv->refused;
-  return SW_OK;
+  return abi_guard([&]() -> int {
+    if (!sv) return SW_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (launches) *launches = sv->launches;
+    if (max_in_flight) *max_in_flight = sv->max_in_flight;
+    if (refused) *refused = sv->refused;
+    return SW_OK;
+  });
 }
 
 SW_API int sw_server_counters(sw_server *sv, int64_t *values, int32_t n) {
-  if (!sv || !values || n < 0) return SW_EINVAL;
-  std::lock_guard<std::mutex> lk(sv->mu);
-  const int64_t v[SW_SERVER_NCOUNTERS] = {sv->launches, sv->max_in_flight, sv->refused,
-                                          sv->session_mode ? 1 : 0, sv->records, sv->paired,
-                                          sv->exact_runs, sv->session_mode ? sv->grid : 0,
-                                          (int64_t)(sv->copy_s * 1e6)};
-  for (int32_t k = 0; k < n && k < SW_SERVER_NCOUNTERS; ++k) values[k] = v[k];
-  return SW_OK;
+  return abi_guard([&]() -> int {
+    if (!sv || !values || n < 0) return SW_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const int64_t v[SW_SERVER_NCOUNTERS] = {sv->launches, sv->max_in_flight, sv->refused,
+                                            sv->session_mode ? 1 : 0, sv->records, sv->paired,
+                                            sv->exact_runs, sv->session_mode ? sv->grid : 0,
+                                            (int64_t)(sv->copy_s * 1e6)};
+    for (int32_t k = 0; k < n && k < SW_SERVER_NCOUNTERS; ++k) values[k] = v[k];
+    return SW_OK;
+  });
 }
 
 SW_API void sw_server_free(sw_server *sv) {
-  if (!sv) return;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sv->stop = true;
-  }
-  sv->cv.notify_all();
-  if (sv->worker.joinable()) sv->worker.join();
-  (void)hipSetDevice(sv->db->device);
-  server_destroy(sv);
+  abi_guard_void([&]() {
+    if (!sv) return;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stop = true;
+    }
+    sv->cv.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    (void)hipSetDevice(sv->db->device);
+    server_destroy(sv);
+  });
 }
 
 // ------------------------------------------------------------------------ sorting stage
 SW_API int sw_topk(const sw_db *cdb, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
                    int32_t *hit_score, int32_t *n_hits, void *hip_stream) {
-  if (!cdb) return SW_ENODB;
-  if (k < 1 || k > kTopkMax || !n_hits || !hit_index || !hit_score) return SW_EINVAL;
-  sw_db *db = const_cast<sw_db *>(cdb);
-  const int64_t n = db->n_seqs;
-  if (n > 0 && !scores_dev) return SW_EINVAL;
-  const int32_t kk = (int32_t)std::min<int64_t>(k, n);
-  *n_hits = 0;
-  if (kk == 0) return SW_OK;
-  std::lock_guard<std::mutex> lk(db->topk_mu);
-  try {
-    hip_check(hipSetDevice(db->device));
-    const size_t off_hist = 64, off_list = off_hist + 256 * 4, off_idx = off_list + kTopkMax * 8,
-                 off_sc = off_idx + kTopkMax * 4, total = off_sc + kTopkMax * 4;
-    grow(db->topk_scratch, total);
-    uint8_t *base = (uint8_t *)db->topk_scratch.ptr;
-    TopkArgs a;
-    a.scores = scores_dev;
-    a.n = n;
-    a.k = kk;
-    a.state = (TopkState *)base;
-    a.hist = (uint32_t *)(base + off_hist);
-    a.list = (uint64_t *)(base + off_list);
-    a.hit_index = (int32_t *)(base + off_idx);
-    a.hit_score = (int32_t *)(base + off_sc);
-    hipStream_t s = (hipStream_t)hip_stream;
-    hip_check(launch_topk(a, s));
-    hip_check(hipMemcpyAsync(hit_index, a.hit_index, (size_t)kk * 4, hipMemcpyDeviceToHost, s));
-    hip_check(hipMemcpyAsync(hit_score, a.hit_score, (size_t)kk * 4, hipMemcpyDeviceToHost, s));
-    hip_check(hipStreamSynchronize(s));
-  } catch (const HipFail &f) {
-    return map_hip(f.err);
-  } catch (const std::bad_alloc &) {
-    return SW_ENOMEM;
-  }
-  *n_hits = kk;
-  return SW_OK;
+  return abi_guard([&]() -> int {
+    if (!cdb) return SW_ENODB;
+    if (k < 1 || k > kTopkMax || !n_hits || !hit_index || !hit_score) return SW_EINVAL;
+    sw_db *db = const_cast<sw_db *>(cdb);
+    const int64_t n = db->n_seqs;
+    if (n > 0 && !scores_dev) return SW_EINVAL;
+    const int32_t kk = (int32_t)std::min<int64_t>(k, n);
+    *n_hits = 0;
+    if (kk == 0) return SW_OK;
+    std::lock_guard<std::mutex> lk(db->topk_mu);
+    try {
+      hip_check(hipSetDevice(db->device));
+      const size_t off_hist = 64, off_list = off_hist + 256 * 4, off_idx = off_list + kTopkMax * 8,
+                   off_sc = off_idx + kTopkMax * 4, total = off_sc + kTopkMax * 4;
+      grow(db->topk_scratch, total);
+      uint8_t *base = (uint8_t *)db->topk_scratch.ptr;
+      TopkArgs a;
+      a.scores = scores_dev;
+      a.n = n;
+      a.k = kk;
+      a.state = (TopkState *)base;
+      a.hist = (uint32_t *)(base + off_hist);
+      a.list = (uint64_t *)(base + off_list);
+      a.hit_index = (int32_t *)(base + off_idx);
+      a.hit_score = (int32_t *)(base + off_sc);
+      hipStream_t s = (hipStream_t)hip_stream;
+      hip_check(launch_topk(a, s));
+      hip_check(hipMemcpyAsync(hit_index, a.hit_index, (size_t)kk * 4, hipMemcpyDeviceToHost, s));
+      hip_check(hipMemcpyAsync(hit_score, a.hit_score, (size_t)kk * 4, hipMemcpyDeviceToHost, s));
+      hip_check(hipStreamSynchronize(s));
+    } catch (const HipFail &f) {
+      return map_hip(f.err);
+    } catch (const std::bad_alloc &) {
+      return SW_ENOMEM;
+    }
+    *n_hits = kk;
+    return SW_OK;
+  });
 }

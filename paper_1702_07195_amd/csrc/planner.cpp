@@ -1,0 +1,490 @@
+// Host-side planning of a search: strip height, routing of long groups to the intra-task
+// kernel, rows per lane, intra-task work items (split pairs, critical pairs, two-pair
+// items), launch geometry, workspace sizes and the staging layout.  Pure host code (no
+// HIP calls): the library calls it before every launch sequence, and a CPU test builds
+// it on its own, with address and undefined-behaviour sanitizers, to check that every
+// (query, sequence) pair is covered exactly once, that split pairs chain only backwards
+// and that every offset fits its buffer.
+#include "planner.h"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <utility>
+
+namespace swmi {
+
+namespace {
+
+// Rows per lane of the intra-task kernel for one search.  Its band is 64R query rows,
+// and a step (one anti-diagonal of a band) issues about 7.5 R + 14 instructions: the
+// lane's per-step overhead (residue and boundary shifts, the profile request) is paid
+// once per R rows, so over many bands R = 16 issues the fewest instructions per cell.
+// But a pair of n columns is swept in about n steps whatever R, its bands pipelined
+// kIntraLag chunks of 64 steps apart, so with few bands the step time of the longest
+// pair sets the search's critical path, and shorter steps win.  For each R in
+// {16, 8, 4, 2} the search time is estimated as the larger of
+//   - the throughput time: every intra-task pair's bands of 64R rows at the kernel's
+//     rate, about 3.6e12 cells/s at R = 16 on MI355X, scaling as R / (7.5 R + 14); a
+//     query with more bands than a workgroup has waves is swept in several rounds, where
+//     short steps measured less efficient (0.77 at R = 8, 0.34 at R = 4, on a 35,000-row
+//     query; 0.15 assumed at R = 2), and R = 2 reached 0.45 of that rate even with few
+//     bands (a 1,000-row query over 6.4e6 residues), and
+//   - the longest pair's path: one band alone is one wave among two per SIMD, n + 63
+//     steps of 0.5 us x (7.5 R + 14) / 134 per band; several bands (a pair at least
+//     `wide_len` long) are a pipeline of waves alone on their SIMDs, 0.76 of that step,
+//     which at R > kCritR may run at kCritR rows in the critical-pair launch,
+// and the smallest estimate wins, a tie going to the larger R (R = 16 and 8 tie when
+// both leave the longest pairs to the critical-pair launch, and 16 measured faster
+// there).  R = 2 is weighed only when the path at R = 4 exceeds a millisecond: below
+// that, per-search costs the estimate leaves out dominate, and R = 2 measured no faster
+// (a 144-row query over 2,000 sequences of at most 2,000 residues).  (Measured on the
+// long-sequence mix, whose longest sequence has 35,000 residues: queries of 300 and
+// 1,000 residues ran 1.8 and 2.8 times faster at R = 4 than at the R an instruction
+// count alone picks.)
+int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
+             int64_t wide_len, int num_cu, const Knobs &k, bool *throughput_bound) {
+  auto step_scale = [](int R) { return (7.5 * R + 14.0) / (7.5 * 16 + 14.0); };
+  auto bands = [](int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); };
+  auto pipe = [&](int64_t m, int R) {  // a pipeline of waves alone on their SIMDs
+    const double chunks = (double)((n_max + 126) / 64 + (int64_t)kIntraLag * (bands(m, R) - 1));
+    return chunks * 64 * 0.76 * 0.5e-6 * step_scale(R);
+  };
+  // (throughput time, longest path) at R
+  auto estimate = [&](int R, double &thr, double &path) {
+    const double rate = 3.6e12 * (R / 16.0) / step_scale(R) * (std::max(1, num_cu) / 256.0);
+    const double eff_rounds = R == 16 ? 1.0 : (R == 8 ? 0.77 : (R == 4 ? 0.34 : 0.15));
+    const double eff_few = R == 2 ? 0.45 : 1.0;
+    thr = 0;
+    path = 0;
+    for (int64_t m : lens) {
+      if (m == 0) continue;
+      const int64_t b = bands(m, R);
+      thr += (double)b * 64 * R * intra_res / (rate * (b > kIntraWaves ? eff_rounds : eff_few));
+      double t;
+      if (b >= 2 && n_max >= wide_len) {
+        t = pipe(m, R);
+        if (R > kCritR) t = std::min(t, pipe(m, kCritR));
+      } else {
+        t = (double)b * (double)(n_max + 63) * 0.5e-6 * step_scale(R);
+      }
+      path = std::max(path, t);
+    }
+  };
+  int best = kIntraR;
+  const int64_t forced = k.intra_rows;
+  if (forced == 2 || forced == 4 || forced == 8 || forced == 16) {
+    best = (int)forced;
+  } else if (n_max > 0 && intra_res > 0) {
+    double best_cost = 1e300, path4 = 0;
+    for (int R : {16, 8, 4, 2}) {
+      if (R == 2 && path4 < 1e-3) break;
+      double thr, path;
+      estimate(R, thr, path);
+      if (R == 4) path4 = path;
+      const double cost = std::max(thr, path);
+      if (cost < best_cost * 0.999) {
+        best_cost = cost;
+        best = R;
+      }
+    }
+  }
+  double thr = 0, path = 0;
+  if (n_max > 0 && intra_res > 0) estimate(best, thr, path);
+  *throughput_bound = thr >= 1.2 * path;
+  return best;
+}
+
+// Strip half-height T for the inter-task kernel: the fewest padded query rows, weighted
+// by the measured relative per-cell speed of each compiled height on gfx950 (T = 24 runs
+// at three waves per SIMD and was fastest on the full-scale search).  The pair kernel
+// (`pairs`) also has T = 28, still at three waves per SIMD and 2% faster on the batched
+// search; its per-strip row count is T, and `lens` then holds twice each pair's rows.
+int choose_T(const std::vector<int64_t> &lens, const Knobs &k, const Occupancy &occ,
+             bool pairs = false) {
+  const int64_t forced = k.strip_rows;
+  if (forced > 0 && forced <= kMaxStripRows &&
+      (pairs ? occ.inter16q2[forced] : occ.inter16[forced]) > 0)
+    return (int)forced;
+  struct Cand { int T; double speed; };
+  static const Cand single[] = {{24, 1.0}, {40, 0.985}, {32, 0.968}, {16, 0.89}};
+  static const Cand paired[] = {{28, 1.02}, {24, 1.0}, {40, 0.98}, {32, 0.962}, {16, 0.938}};
+  const Cand *cands = pairs ? paired : single;
+  const int ncand = pairs ? 5 : 4;
+  int best = 24;
+  double best_cost = 1e300;
+  for (int k = 0; k < ncand; ++k) {
+    const Cand &c = cands[k];
+    double cost = 0;
+    for (int64_t m : lens) cost += (double)((m + 2 * c.T - 1) / (2 * c.T)) * 2.0 * c.T;
+    cost /= c.speed;
+    if (cost < best_cost * 0.999) {
+      best_cost = cost;
+      best = c.T;
+    }
+  }
+  return best;
+}
+
+}  // namespace
+
+Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k,
+               const Occupancy &occ) {
+  Plan p;
+  const int A = db.alphabet;
+  std::vector<int64_t> &lens = p.lens;
+  lens.resize((size_t)nq);
+  for (int64_t q = 0; q < nq; ++q) lens[q] = qoff[q + 1] - qoff[q];
+  // inter-task items visit each group's queries longest first
+  std::vector<int32_t> &qorder = p.qorder;
+  qorder.resize((size_t)nq);
+  std::iota(qorder.begin(), qorder.end(), 0);
+  std::stable_sort(qorder.begin(), qorder.end(),
+                   [&](int32_t x, int32_t y) { return lens[x] > lens[y]; });
+  // A batched search pairs its queries (longest first) in the two-query inter-task
+  // kernel, whose strips hold T rows of both; the strip height is chosen on the padded
+  // rows of the pairs.
+  const bool q2 = p.q2 = k.query_pairs != 0 && nq >= 2;
+  if (q2) {
+    std::vector<int64_t> pair_rows;
+    for (int64_t k = 0; k < nq; k += 2) {
+      QueryPair qp;
+      qp.qa = qorder[(size_t)k];
+      qp.qb = k + 1 < nq ? qorder[(size_t)k + 1] : -1;
+      qp.qp2 = 0;
+      qp.nstrips = 0;
+      qp.pad = 0;
+      p.pairs.push_back(qp);
+      pair_rows.push_back(2 * lens[(size_t)qp.qa]);  // ceil(2m / 2T) * 2T = 2T ceil(m / T)
+    }
+    p.T = choose_T(pair_rows, k, occ, true);
+  } else {
+    p.T = choose_T(lens, k, occ);
+  }
+  const int band = 64 * kIntraR;
+  p.qd.resize((size_t)nq);
+  for (int64_t q = 0; q < nq; ++q) {
+    QueryDesc &d = p.qd[q];
+    d.m = (int32_t)lens[q];
+    d.nstrips = q2 ? 0 : (int32_t)((lens[q] + 2 * p.T - 1) / (2 * p.T));
+    d.nbands = (int32_t)((lens[q] + band - 1) / band);
+    d.mrows = d.nbands * band;
+    d.qp16 = p.qp16_elems;
+    d.qp8 = p.qp8_elems;
+    d.out = q * db.n_seqs;
+    p.qp16_elems += (int64_t)d.nstrips * kCodes * 2 * p.T;
+    p.qp8_elems += (int64_t)kCodes * d.mrows;
+  }
+  for (QueryPair &qp : p.pairs) {
+    qp.nstrips = (int32_t)((lens[(size_t)qp.qa] + p.T - 1) / p.T);
+    qp.qp2 = p.qp2_elems;
+    p.qp2_elems += (int64_t)qp.nstrips * kCodes * p.T;
+  }
+  const int64_t nunits = q2 ? (int64_t)p.pairs.size() : nq;  // inter-task items per group
+  // launch geometry of the inter-task kernel
+  int per_cu = (int)k.grid_waves;
+  if (per_cu <= 0)
+    per_cu = std::max(1, q2 ? occ.inter16q2[p.T] : occ.inter16[p.T]);
+  p.per_cu = per_cu;
+  const int64_t lanes = (int64_t)per_cu * db.num_cu * 64;
+
+  // Route the longest groups to the intra-task kernel.  One lane runs a whole alignment
+  // in the inter-task kernel, so a group of length L costs about L * m on one wave; keep
+  // L below twice the average number of residues per lane (weighted by the number of
+  // equally long queries), else that wave becomes the critical path.
+  // (paired queries: a lane runs both queries of a pair at once, so a pair counts once)
+  int64_t sum_m = 0, max_m = 1;
+  for (int64_t q = 0; q < nq; ++q) max_m = std::max(max_m, lens[q]);
+  if (q2)
+    for (const QueryPair &qp : p.pairs) sum_m += lens[(size_t)qp.qa];
+  else
+    for (int64_t q = 0; q < nq; ++q) sum_m += lens[q];
+  const double weight = (double)sum_m / (double)max_m;
+  int64_t route = (int64_t)(2.0 * (double)db.short_residues * weight / (double)lanes);
+  route = std::max<int64_t>(route, 64);
+  const int64_t forced_route = k.route_len;
+  if (forced_route > 0) route = forced_route;
+  int32_t ninter = db.ngroups;
+  while (ninter > 0 && db.groups[ninter - 1].maxlen > route) --ninter;
+  p.ngroups_inter = ninter;
+
+  // rows per lane of the intra-task kernel, from the pairs it gets (long sequences and
+  // routed groups, the latter estimated at their longest sequence)
+  const int64_t wide_len = k.wide_len > 0 ? k.wide_len
+                                                      : (int64_t)64 * 6 * kIntraLag;
+  {
+    double intra_res = 0;
+    int64_t n_max = 0;
+    for (const auto &L : db.longs) {
+      intra_res += L.len;
+      n_max = std::max<int64_t>(n_max, L.len);
+    }
+    for (int32_t g = ninter; g < db.ngroups; ++g) {
+      intra_res += (double)db.groups[g].count * db.groups[g].maxlen;
+      n_max = std::max<int64_t>(n_max, db.groups[g].maxlen);
+    }
+    // A throughput-bound search (estimated throughput time at least 1.2 times the
+    // longest path) runs four-wave workgroups, two per CU: the same occupancy, and one
+    // fits beside a critical-pair workgroup (an 8-wave one does not).  Otherwise
+    // eight-wave workgroups give a pair's few band waves a SIMD each (the rest of the
+    // workgroup idles).  (Long-sequence mix on MI355X: 5478-residue query 14.7 -> 10.8
+    // ms with four-wave workgroups; a 2005-residue query, at a ratio of 1.1, 8.2 -> 9.3.)
+    bool throughput_bound = false;
+    p.R = choose_R(lens, intra_res, n_max, wide_len, db.num_cu, k, &throughput_bound);
+    const int64_t mw = k.main_waves;
+    p.main_waves = (mw == 4 || mw == 8) ? (int)mw : (throughput_bound ? kNarrowWaves : kIntraWaves);
+  }
+  p.nbandsR.resize((size_t)nq);
+  for (int64_t q = 0; q < nq; ++q)
+    p.nbandsR[q] = (int32_t)((lens[q] + 64 * p.R - 1) / (64 * p.R));
+
+  // intra-task items: long sequences and the sequences of routed groups, for every query;
+  // "wide" (a whole workgroup per pair) when the pair has several bands and enough
+  // columns to fill the band pipeline, else "narrow" (one wave per pair); each part
+  // longest first
+  std::vector<std::pair<double, PairItem>> wide, narrow;
+  auto add_item = [&](int64_t base, int32_t cstride, int32_t len, int32_t orig, int64_t q) {
+    PairItem it;
+    it.base = base;
+    it.cstride = cstride;
+    it.len = len;
+    it.out = orig;
+    it.query = (int32_t)q;
+    it.band0 = 0;
+    it.band1 = p.nbandsR[q];
+    it.xin = it.xout = -1;
+    it.prog_in = it.prog_out = -1;
+    it.segment = 0;
+    it.nsegments = 1;
+    const double cost = (double)len * (double)lens[q];
+    const bool is_wide = len >= wide_len && p.nbandsR[q] >= 2;
+    (is_wide ? wide : narrow).emplace_back(cost, it);
+  };
+  for (int64_t q = 0; q < nq; ++q) {
+    if (lens[q] == 0) continue;
+    for (const auto &L : db.longs) add_item(L.base, 4, L.len, L.orig, q);
+    for (int32_t g = ninter; g < db.ngroups; ++g) {
+      const GroupDesc &gd = db.groups[g];
+      for (int32_t l = 0; l < gd.count; ++l)
+        add_item(gd.base + 4 * l, 256, db.lens[gd.first + l], db.perm[gd.first + l], q);
+    }
+  }
+  auto by_cost = [](const std::pair<double, PairItem> &x, const std::pair<double, PairItem> &y) {
+    return x.first > y.first;
+  };
+  std::stable_sort(wide.begin(), wide.end(), by_cost);
+  std::stable_sort(narrow.begin(), narrow.end(), by_cost);
+  // Critical path of the longest pairs.  A workgroup sweeps its bands in rounds of its
+  // W = p.main_waves waves, so a pair of nb bands takes about ceil(nb / W) sweeps of its
+  // columns; cut into segments of at most W consecutive bands on workgroups of
+  // their own, the bands form one pipeline (nc + kIntraLag * (nb - 1) chunks), and with at
+  // most 4 bands per segment each band's wave has a SIMD to itself.  A pair is split as
+  // little as keeps its estimated time within half the estimated time of the whole
+  // intra-task search (a pair may be claimed only after other work has run); 4-band
+  // segments, which leave half a compute unit idle, only when even the full pipeline
+  // would outlast the whole search.  Segments of a pair are consecutive in the list, so
+  // segment j is always claimed after segment j - 1 (the only one it waits for).
+  //   (one step of a wave with R = 16: about 0.5 us with two waves per SIMD, 0.25 us
+  //   alone; the kernel then sustains about 2.5e12 cells/s over the whole chip: MI355X
+  //   measurements; both scale with the instructions per step, 7.5 R + 14)
+  double intra_cells = 0;
+  for (auto &x : wide) intra_cells += x.first;
+  for (auto &x : narrow) intra_cells += x.first;
+  const double step_scale = (7.5 * p.R + 14.0) / (7.5 * 16 + 14.0);
+  const double t_search = intra_cells / (2.5e12 * (p.R / 16.0) / step_scale) *
+                          (256.0 / std::max(1, db.num_cu));
+  const double t_step = 0.5e-6 * step_scale;
+  const int64_t cap = k.max_segments;
+  // Narrow pairs of the same query can run two per wave as one packed int16 item
+  // (consecutive in cost order, so of similar length).  Such an item does two pairs'
+  // cells per step at about 1.45 times the single step's time, which pays when the
+  // search is throughput-bound and hurts the critical path when it is not, so pairing
+  // is used only when there are at least two narrow items per wave slot, and only for
+  // items whose paired time stays under a quarter of the estimated search time.  Wide
+  // pairs stay single, in int32.  (Knob value 2 pairs every unsplit pair, wide ones
+  // included: a test setting.)
+  const int64_t pair_mode = k.intra_pairs;
+  const bool pair_all = pair_mode == 2;
+  const bool pair_narrow = pair_mode == 1 &&
+                           narrow.size() >= 2 * (size_t)std::max(1, db.num_cu) * kIntraWaves;
+  const bool pair_wide = pair_mode == 1 && wide.size() >= 2 * (size_t)std::max(1, db.num_cu);
+  const bool pairs16 = pair_all || pair_narrow || pair_wide;
+  PairItem none;
+  std::memset(&none, 0, sizeof(none));
+  none.len = -1;
+  none.out = -1;
+  std::vector<int64_t> pending((size_t)nq, -1);  // index in longitems of an unpaired item
+  auto emit = [&](const PairItem &it, bool pairable) {
+    if (pairs16 && pairable) {
+      int64_t &pend = pending[(size_t)it.query];
+      if (pend >= 0) {
+        p.second[(size_t)pend] = it;
+        pend = -1;
+        ++p.nduos;
+        return;
+      }
+      pend = (int64_t)p.longitems.size();
+    }
+    p.longitems.push_back(it);
+    p.second.push_back(none);
+  };
+  for (auto &x : wide) {
+    const PairItem &it = x.second;
+    const int32_t nb = it.band1;
+    const int64_t nc = ((int64_t)it.len + 126) / 64;
+    const int64_t nce = std::max<int64_t>(nc, (int64_t)kIntraLag * p.main_waves);
+    const int64_t lastb = nb - 1;
+    const double whole = (double)((lastb / p.main_waves) * nce + kIntraLag * (lastb % p.main_waves) + nc);
+    const double piped = (double)(nc + (int64_t)kIntraLag * lastb);
+    const int32_t s8 = (nb + p.main_waves - 1) / p.main_waves, s4 = (nb + 3) / 4;
+    int32_t S = 1;
+    if (whole * 64 * t_step > 0.5 * t_search) S = piped * 64 * t_step <= t_search ? s8 : s4;
+    if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
+    S = std::max<int32_t>(1, std::min(S, nb));
+    if (S == 1) {
+      emit(it, pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
+      continue;
+    }
+    // A pair whose full pipeline would outlast the search sets its critical path; with
+    // bands of 64 * kCritR rows a step takes 7.5 kCritR + 14 instructions instead of
+    // 7.5 R + 14, over more, shorter bands, so such pairs get a launch of their own with
+    // that height (segments of kCritWaves bands, one wave per SIMD) when it shortens their
+    // pipeline.
+    // (A wave alone on its SIMD steps in about 0.76 of t_step: 0.38 us at R = 16 on
+    // MI355X, where latency keeps a step at about 1.7 times its instruction time.)
+    if (S == s4 && p.R > kCritR && k.intra_rows == 0 && cap == 0 &&
+        piped * 64 * 0.76 * t_step > 0.5 * t_search) {  // still critical with a SIMD per wave
+      const int32_t nbc = (int32_t)((lens[it.query] + 64 * kCritR - 1) / (64 * kCritR));
+      const double piped_c = (double)(nc + (int64_t)kIntraLag * (nbc - 1));
+      const double step_c = (7.5 * kCritR + 14.0) / (7.5 * p.R + 14.0);
+      if (piped_c * step_c < piped) {
+        const int32_t Sc = (nbc + kCritWaves - 1) / kCritWaves;
+        const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
+        for (int32_t j = 0; j < Sc; ++j) {
+          PairItem sg = it;
+          sg.band0 = (int32_t)((int64_t)nbc * j / Sc);
+          sg.band1 = (int32_t)((int64_t)nbc * (j + 1) / Sc);
+          sg.segment = j;
+          sg.nsegments = Sc;
+          if (j > 0) {
+            sg.xin = p.xbnd_elems - npad;
+            sg.prog_in = p.nprog - 1;
+          }
+          if (j + 1 < Sc) {
+            sg.xout = p.xbnd_elems;
+            sg.prog_out = p.nprog;
+            p.xbnd_elems += npad;
+            p.nprog += 1;
+          }
+          p.crititems.push_back(sg);
+        }
+        continue;
+      }
+    }
+    const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
+    for (int32_t j = 0; j < S; ++j) {
+      PairItem sg = it;
+      sg.band0 = (int32_t)((int64_t)nb * j / S);
+      sg.band1 = (int32_t)((int64_t)nb * (j + 1) / S);
+      sg.segment = j;
+      sg.nsegments = S;
+      if (j > 0) {
+        sg.xin = p.xbnd_elems - npad;
+        sg.prog_in = p.nprog - 1;
+      }
+      if (j + 1 < S) {
+        sg.xout = p.xbnd_elems;
+        sg.prog_out = p.nprog;
+        p.xbnd_elems += npad;
+        p.nprog += 1;
+      }
+      p.longitems.push_back(sg);
+      p.second.push_back(none);
+    }
+  }
+  p.n_wide = (int32_t)p.longitems.size();
+  std::fill(pending.begin(), pending.end(), -1);  // wide and narrow items are not mixed
+  for (auto &x : narrow) {
+    const PairItem &it = x.second;
+    const double single = (double)it.band1 * (double)((it.len + 126) / 64) * 64 * t_step;
+    emit(it, pair_all || (pair_narrow && 1.45 * single <= 0.25 * t_search));
+  }
+
+  const int64_t nitems16 = p.nitems16 = (int64_t)ninter * nunits;
+  p.grid16 = (int)std::min<int64_t>(nitems16, (int64_t)per_cu * db.num_cu);
+  {
+    // algorithmic cells (query rows x unpadded residues) of each launch
+    int64_t sum_all = 0;
+    for (int64_t q = 0; q < nq; ++q) sum_all += lens[q];
+    auto rows_of = [&](const PairItem &it, int R) {
+      const int64_t m = lens[(size_t)it.query];
+      return std::min<int64_t>(m, (int64_t)it.band1 * 64 * R) - (int64_t)it.band0 * 64 * R;
+    };
+    int64_t c32 = 0, c16 = 0, ccrit = 0;
+    for (size_t k = 0; k < p.longitems.size(); ++k) {
+      const PairItem &it = p.longitems[k];
+      if (p.second[k].len >= 0)
+        c16 += (int64_t)(it.len + p.second[k].len) * lens[(size_t)it.query];
+      else
+        c32 += (int64_t)it.len * rows_of(it, p.R);
+    }
+    for (const PairItem &it : p.crititems) ccrit += (int64_t)it.len * rows_of(it, kCritR);
+    int64_t *st = p.stats;
+    st[SW_ST_CELLS_INTER16] = sum_all * db.group_res[(size_t)ninter];
+    st[SW_ST_CELLS_INTRA32] = c32;
+    st[SW_ST_CELLS_INTRA16] = c16;
+    st[SW_ST_CELLS_CRIT] = ccrit;
+    st[SW_ST_INTRA_ROWS] = p.R;
+    st[SW_ST_MAIN_WAVES] = p.main_waves;
+    st[SW_ST_ROUTED_GROUPS] = db.ngroups - ninter;
+    st[SW_ST_STRIP_ROWS] = p.T;
+    st[SW_ST_QUERY_PAIRS] = q2 ? 1 : 0;
+  }
+  // Two waves per SIMD: one persistent 8-wave workgroup per compute unit, or two 4-wave
+  // ones.  The kernel's per-step profile gathers touch one cache line per lane, and a
+  // second resident 8-wave workgroup per CU (four waves per SIMD) measured slower and
+  // erratic on MI355X (86 ms vs 103-115 ms for a 35000-residue query over the
+  // long-sequence mix), not faster.
+  const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
+  // The critical pairs' launch (a workgroup of kCritWaves waves per CU, one band and one
+  // wave per SIMD) is enqueued first and gets its CUs first; the main launch still asks
+  // for one workgroup per CU, and the ones that find no free CU start as the critical
+  // workgroups finish.
+  p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(), std::max(1, db.num_cu));
+  p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + p.main_waves - 1) / p.main_waves,
+                                       (int64_t)db.num_cu * (kIntraWaves / p.main_waves));
+  // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
+  // and nothing is launched when no kernel can append to it
+  const bool may_flag = (nitems16 > 0 && p.grid16 > 0) || p.nduos > 0;
+  p.grid_re = (may_flag && nq > 0) ? std::max(1, db.num_cu / 4) : 0;
+  p.grid32 = p.grid_long + p.grid_re + p.grid_crit;
+
+  // workspace sizes
+  p.qbytes = qoff[nq];
+  p.bnd16_slot = (size_t)db.max_ncols * 64 * (q2 ? 2 : 1);  // dwords
+  p.bnd32_stride = ((db.max_len + 128 + 63) / 64) * 64;
+  p.bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * p.bnd32_stride;
+  // saturated pairs: any database sequence, from either kernel
+  p.need_flagged = (size_t)std::max<int64_t>(1, db.n_seqs * nq);
+  p.need_bytes = (size_t)p.qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
+                 (size_t)p.qp16_elems * 2 + (size_t)p.qp2_elems * 4 + (size_t)p.qp8_elems +
+                 sizeof(Counters) + p.pairs.size() * sizeof(QueryPair) +
+                 p.need_flagged * sizeof(PairItem) +
+                 (2 * p.longitems.size() + p.crititems.size()) * sizeof(PairItem) +
+                 (size_t)p.grid16 * p.bnd16_slot * 4 + (size_t)p.grid32 * p.bnd32_slot * 8 +
+                 (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
+  // small per-call inputs, staged in one block (64-byte aligned parts)
+  auto up = [](size_t x) { return (x + 63) & ~size_t(63); };
+  p.off_qoff = up((size_t)p.qbytes);
+  p.off_qd = p.off_qoff + up((size_t)(nq + 1) * 8);
+  p.off_mx = p.off_qd + up(nq * sizeof(QueryDesc));
+  p.off_qo = p.off_mx + up((size_t)A * A * 4);
+  p.off_li = p.off_qo + up(nq * sizeof(int32_t));
+  p.off_se = p.off_li + up(p.longitems.size() * sizeof(PairItem));
+  p.off_cr = p.off_se + up(p.second.size() * sizeof(PairItem));
+  p.off_pr = p.off_cr + up(p.crititems.size() * sizeof(PairItem));
+  p.stage_bytes = p.off_pr + p.pairs.size() * sizeof(QueryPair) + 64;
+  return p;
+}
+
+}  // namespace swmi

@@ -149,27 +149,10 @@ static hipError_t scratch_address(int device, void **out) {
   return hipSuccess;
 }
 
-}  // namespace swmi
-
-extern "C" __attribute__((visibility("default")))
-int sw_topk_noalloc(const sw_db *db, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
-                    int32_t *hit_score, int32_t *n_hits, void *hip_stream) {
-  using namespace swmi;
-  if (!db) return SW_ENODB;
-  if (k < 1 || k > kTopkMax || !n_hits || !hit_index || !hit_score) return SW_EINVAL;
-  const int64_t n = sw_db_size(db);
-  if (n < 0) return SW_ENODB;
-  if (n > 0 && !scores_dev) return SW_EINVAL;
-  const int32_t kk = (int32_t)std::min<int64_t>(k, n);
-  *n_hits = 0;
-  if (kk == 0) return SW_OK;
-  // the database's device, made current (its copy of the array is the one used)
-  const int device = db_device(db);
-  if (device < 0 || device >= kMaxDevices || hipSetDevice(device) != hipSuccess)
-    return SW_EDEVICE;
-  void *base_ptr = nullptr;
-  if (scratch_address(device, &base_ptr) != hipSuccess) return SW_EDEVICE;
-  std::lock_guard<std::mutex> use(g_scratch_use[device]);
+// The selection of sw_topk_noalloc, in the device's copy of `scratch` (base_ptr).
+static int topk_in_scratch(const sw_db *, const int32_t *scores_dev, int64_t n, int32_t kk,
+                           void *base_ptr, int32_t *hit_index, int32_t *hit_score,
+                           int32_t *n_hits, void *hip_stream) {
   uint8_t *base = (uint8_t *)base_ptr;
   TopkArgs a;
   a.scores = scores_dev;
@@ -189,3 +172,33 @@ int sw_topk_noalloc(const sw_db *db, const int32_t *scores_dev, int32_t k, int32
   *n_hits = kk;
   return SW_OK;
 }
+
+}  // namespace swmi
+
+extern "C" __attribute__((visibility("default")))
+int sw_topk_noalloc(const sw_db *db, const int32_t *scores_dev, int32_t k, int32_t *hit_index,
+                    int32_t *hit_score, int32_t *n_hits, void *hip_stream) {
+  using namespace swmi;
+  if (!db) return SW_ENODB;
+  if (k < 1 || k > kTopkMax || !n_hits || !hit_index || !hit_score) return SW_EINVAL;
+  const int64_t n = sw_db_size(db);
+  if (n < 0) return SW_ENODB;
+  if (n > 0 && !scores_dev) return SW_EINVAL;
+  const int32_t kk = (int32_t)std::min<int64_t>(k, n);
+  *n_hits = 0;
+  if (kk == 0) return SW_OK;
+  // the database's device, made current (its copy of the array is the one used)
+  const int device = db_device(db);
+  if (device < 0 || device >= kMaxDevices || hipSetDevice(device) != hipSuccess)
+    return SW_EDEVICE;
+  void *base_ptr = nullptr;
+  try {  // (a lock can throw std::system_error; nothing may cross the C ABI)
+    if (scratch_address(device, &base_ptr) != hipSuccess) return SW_EDEVICE;
+    std::lock_guard<std::mutex> use(g_scratch_use[device]);
+    return topk_in_scratch(db, scores_dev, n, kk, base_ptr, hit_index, hit_score, n_hits,
+                           hip_stream);
+  } catch (...) {
+    return SW_EDEVICE;
+  }
+}
+
