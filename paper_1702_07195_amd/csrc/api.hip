@@ -40,6 +40,7 @@ std::atomic<int64_t> g_knob_spin_limit{0};
 std::atomic<int64_t> g_knob_query_pairs{1};
 std::atomic<int64_t> g_knob_main_waves{0};
 std::atomic<int64_t> g_knob_prio_cols{0};
+std::atomic<int64_t> g_knob_flag_cap{0};
 
 // Group width from which an inter-task item runs at raised wave priority: a wave sweeping
 // a group of ncols columns spends about 64 * ncols * waves / residues of the launch's
@@ -115,8 +116,8 @@ struct sw_db {
   int32_t max_ncols = 0;      // widest group (columns incl. padding)
   int32_t max_len = 0;        // longest sequence overall
   int64_t residues = 0;       // unpadded residue total
-  DevBuf packed, groups, perm, lens;
-  std::vector<LongSeq> longs;  // sorted by decreasing length
+  DevBuf packed, groups, perm, lens, dlongs;
+  std::vector<LongSeq> longs;  // sorted by decreasing length (device copy: dlongs)
   std::vector<GroupDesc> hgroups;   // host copy of the group table
   std::vector<int32_t> hperm;       // host copy: sorted position -> caller index
   std::vector<int32_t> hlens;       // host copy: sorted position -> length
@@ -295,6 +296,7 @@ Knobs knob_snapshot() {
   k.query_pairs = g_knob_query_pairs.load();
   k.main_waves = g_knob_main_waves.load();
   k.mem_cap_mb = g_knob_mem_cap_mb.load();
+  k.flag_cap = g_knob_flag_cap.load();
   return k;
 }
 
@@ -453,6 +455,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ca.flagged = nullptr;
     ca.flag_count = nullptr;
     ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
+    ca.flag_cap = (int32_t)need_flagged;
     hip_check(launch_intra32(ca, kCritR, kCritWaves, p.grid_crit, w->crit));
     hip_check(hipEventRecord(w->join_crit, w->crit));
   }
@@ -484,6 +487,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.flagged = (PairItem *)w->flagged.ptr;
     ia.flag_count = &ctr->flagged;
     ia.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
+    ia.flag_cap = (int32_t)need_flagged;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
     hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, w->aux));
@@ -518,6 +522,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
       ia.prio_cols = prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
+      ia.flag_cap = (int32_t)need_flagged;
       hip_check(launch_inter16q2(ia, p.T, p.grid16, s));
     } else {
       InterArgs ia;
@@ -540,6 +545,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
       ia.prio_cols = prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
+      ia.flag_cap = (int32_t)need_flagged;
       hip_check(launch_inter16(ia, p.T, p.grid16, s));
     }
     if (timed && p.grid16 > 0) {
@@ -576,11 +582,27 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.flagged = nullptr;
     ra.flag_count = nullptr;
     ra.spin_limit = kSpinLimit;
+    ra.flag_cap = (int32_t)need_flagged;
     if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
     hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
     if (timed && p.grid_re > 0) {
       hip_check(hipEventRecord(w->t1[2], s));
       w->timed[2] = true;
+    }
+    // pairs that did not fit the recompute list (nothing to do unless it overflowed)
+    if (p.grid_re > 0) {
+      RescanArgs rs;
+      rs.ia = ra;
+      rs.groups = (const GroupDesc *)db->groups.ptr;
+      rs.ngroups = db->ngroups;
+      rs.perm = (const int32_t *)db->perm.ptr;
+      rs.lens = (const int32_t *)db->lens.ptr;
+      rs.longs = (const LongSeq *)db->dlongs.ptr;
+      rs.nlongs = (int32_t)db->longs.size();
+      rs.nqueries = (int32_t)nq;
+      rs.count = &ctr->flagged;
+      rs.next = &ctr->rescan_next;
+      hip_check(launch_rescan(rs, p.grid_re * kIntraWaves, s));
     }
   }
   if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
@@ -633,6 +655,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       g_knob_main_waves = value;
       return SW_OK;
     case SW_KNOB_PRIO_COLS: if (value < 0) return SW_EINVAL; g_knob_prio_cols = value; return SW_OK;
+    case SW_KNOB_FLAG_CAP:
+      if (value < 0 || value > INT32_MAX) return SW_EINVAL;
+      g_knob_flag_cap = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -653,6 +679,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_QUERY_PAIRS: return g_knob_query_pairs.load();
     case SW_KNOB_MAIN_WAVES: return g_knob_main_waves.load();
     case SW_KNOB_PRIO_COLS: return g_knob_prio_cols.load();
+    case SW_KNOB_FLAG_CAP: return g_knob_flag_cap.load();
     default: return SW_EINVAL;
   }
 }
@@ -742,6 +769,10 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
                             hipMemcpyHostToDevice));
       if (n_seqs)
         hip_check(hipMemcpy(db->perm.ptr, order.data(), (size_t)n_seqs * 4, hipMemcpyHostToDevice));
+      grow(db->dlongs, std::max<size_t>(1, db->longs.size()) * sizeof(LongSeq));
+      if (!db->longs.empty())
+        hip_check(hipMemcpy(db->dlongs.ptr, db->longs.data(), db->longs.size() * sizeof(LongSeq),
+                            hipMemcpyHostToDevice));
       hip_check(hipMemcpy(db->lens.ptr, lens.data(), lens.size() * 4, hipMemcpyHostToDevice));
 
       if (total > 0) {
@@ -778,6 +809,7 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
       if (d_raw) (void)hipFree(d_raw);
       if (d_off) (void)hipFree(d_off);
       db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+      db->dlongs.release();
       delete db;
       return f.err == hipErrorNoDevice || f.err == hipErrorNoBinaryForGpu ? SW_EDEVICE
                                                                         : map_hip(f.err);
@@ -785,6 +817,7 @@ SW_API int sw_db_load(const uint8_t *residues, const int64_t *offsets, int64_t n
       if (d_raw) (void)hipFree(d_raw);
       if (d_off) (void)hipFree(d_off);
       db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+      db->dlongs.release();
       delete db;
       return SW_ENOMEM;
     }
@@ -806,6 +839,7 @@ SW_API void sw_db_free(sw_db *db) {
     }
     for (hipEvent_t e : db->spare_events) (void)hipEventDestroy(e);
     db->packed.release(); db->groups.release(); db->perm.release(); db->lens.release();
+    db->dlongs.release();
     db->topk_scratch.release();
     delete db;
   });

@@ -351,19 +351,23 @@ void k_inter16(InterArgs a) {
       const int orig = a.perm[p];
       if (sc >= kSat16 || a.recompute_all) {
         const int k = atomicAdd(&a.ctr->flagged, 1);
-        PairItem it;
-        it.base = gd.base + 4 * lane;
-        it.cstride = 256;
-        it.len = a.lens[p];
-        it.out = orig;
-        it.query = qi;
-        it.band0 = 0;
-        it.band1 = qd.nbands;
-        it.xin = it.xout = -1;
-        it.prog_in = it.prog_out = -1;
-        it.segment = 0;
-        it.nsegments = 1;
-        a.flagged[k] = it;
+        if (k < a.flag_cap) {
+          PairItem it;
+          it.base = gd.base + 4 * lane;
+          it.cstride = 256;
+          it.len = a.lens[p];
+          it.out = orig;
+          it.query = qi;
+          it.band0 = 0;
+          it.band1 = qd.nbands;
+          it.xin = it.xout = -1;
+          it.prog_in = it.prog_out = -1;
+          it.segment = 0;
+          it.nsegments = 1;
+          a.flagged[k] = it;
+        } else {
+          a.scores[qd.out + orig] = kSat16;  // the list is full: k_rescan finds the mark
+        }
       } else {
         a.scores[qd.out + orig] = sc;
       }
@@ -725,7 +729,10 @@ __device__ __forceinline__ void finish_half(const IntraArgs &a, const PairItem &
     it.segment = 0;
     it.nsegments = 1;
     const int k = __builtin_amdgcn_readfirstlane(atomicAdd(a.flag_count, lane == 0 ? 1 : 0));
-    a.flagged[k] = it;
+    if (k < a.flag_cap)
+      a.flagged[k] = it;
+    else
+      a.scores[qd.out + p.out] = kSat16;  // the list is full: k_rescan finds the mark
   } else {
     a.scores[qd.out + p.out] = score;
   }
@@ -826,7 +833,9 @@ void k_intra32(IntraArgs a) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   int2 *slot = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_elems;
-  const int count = a.count_dev ? *a.count_dev : a.count;
+  // (the recompute list: the kernels count every pair they tried to append, and only the
+  // first flag_cap are in the list; the others are left to k_rescan)
+  const int count = a.count_dev ? min(*a.count_dev, a.flag_cap) : a.count;
   const int n_wide = a.n_wide < count ? a.n_wide : count;
 
   for (;;) {
@@ -949,6 +958,81 @@ hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStr
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------ recompute-list overflow
+// The recompute list holds a bounded number of pairs.  When more pairs saturate (or all
+// are forced through the recompute), the kernels mark the pairs they could not append
+// with the score kSat16, which no exact int16 result below the ceiling takes, and this
+// pass finds and recomputes them in int32.  A wave claims 64 sequences of one query at a
+// time (a group, or up to 64 long sequences), and sweeps each marked one alone, as a
+// narrow pair of the intra-task kernel.  It returns at once when the list did not
+// overflow.  Single-wave workgroups; wave b uses band ring b % 8 of slot b / 8.
+__global__ __launch_bounds__(64) void k_rescan(RescanArgs a) {
+  if (*a.count <= a.ia.flag_cap) return;
+  const int lane = threadIdx.x;
+  int2 *ring = a.ia.bnd + (int64_t)(blockIdx.x / kIntraWaves) * a.ia.bnd_slot_elems +
+               (int64_t)(blockIdx.x % kIntraWaves) * 2 * a.ia.bnd_stride;
+  const int per_query = a.ngroups + (a.nlongs + 63) / 64;
+  const int total = per_query * a.nqueries;
+  for (;;) {
+    const int claimed = atomicAdd(a.next, lane == 0 ? 1 : 0);
+    const int c = __builtin_amdgcn_readfirstlane(claimed);
+    if (c >= total) break;
+    const int q = c / per_query, j = c - q * per_query;
+    const QueryDesc qd = a.ia.queries[q];
+    PairItem it;
+    it.cstride = 256;
+    it.base = 0;
+    it.len = 0;
+    it.out = -1;
+    if (j < a.ngroups) {
+      const GroupDesc gd = a.groups[j];
+      if (lane < gd.count) {
+        const int p = gd.first + lane;
+        it.base = gd.base + 4 * lane;
+        it.len = a.lens[p];
+        it.out = a.perm[p];
+      }
+    } else {
+      const int li = (j - a.ngroups) * 64 + lane;
+      if (li < a.nlongs) {
+        const LongSeq L = a.longs[li];
+        it.base = L.base;
+        it.cstride = 4;
+        it.len = L.len;
+        it.out = L.orig;
+      }
+    }
+    const bool marked = it.out >= 0 && qd.m > 0 && a.ia.scores[qd.out + it.out] == kSat16;
+    uint64_t todo = __ballot(marked);
+    while (todo) {
+      const int src = __builtin_ffsll((long long)todo) - 1;
+      todo &= todo - 1;
+      PairItem pi;
+      pi.base = (int64_t)(((uint64_t)(uint32_t)__shfl((int)((uint64_t)it.base >> 32), src) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)it.base, src));
+      pi.cstride = __shfl(it.cstride, src);
+      pi.len = __shfl(it.len, src);
+      pi.out = __shfl(it.out, src);
+      pi.query = q;
+      pi.band0 = 0;
+      pi.band1 = qd.nbands;
+      pi.xin = pi.xout = -1;
+      pi.prog_in = pi.prog_out = -1;
+      pi.segment = 0;
+      pi.nsegments = 1;
+      int32_t vmax = intra_pair<kIntraR, 1>(a.ia, pi, qd, 0, ring);
+      for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
+      a.ia.scores[qd.out + pi.out] = vmax;
+    }
+  }
+}
+
+hipError_t launch_rescan(const RescanArgs &a, int grid, hipStream_t s) {
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rescan, dim3(grid), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------ inter-task, two queries
 // Batched searches (several queries against the same database): the inter-task DP of
 // k_inter16 with the two int16 halves of every register given to two different queries
@@ -1000,6 +1084,10 @@ __device__ __forceinline__ void inter2_finish(const Inter2Args &a, int q, int sc
   const QueryDesc qd = a.queries[q];
   if (sc >= kSat16 || a.recompute_all) {
     const int k = atomicAdd(&a.ctr->flagged, 1);
+    if (k >= a.flag_cap) {
+      a.scores[qd.out + orig] = kSat16;  // the list is full: k_rescan finds the mark
+      return;
+    }
     PairItem it;
     it.base = gd.base + 4 * lane;
     it.cstride = 256;

@@ -464,8 +464,10 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   p.bnd16_slot = (size_t)db.max_ncols * 64 * (q2 ? 2 : 1);  // dwords
   p.bnd32_stride = ((db.max_len + 128 + 63) / 64) * 64;
   p.bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * p.bnd32_stride;
-  // saturated pairs: any database sequence, from either kernel
-  p.need_flagged = (size_t)std::max<int64_t>(1, db.n_seqs * nq);
+  // saturated pairs: any database sequence, from either kernel, up to the list's capacity
+  // (the pairs beyond it are marked in the scores and found by the overflow pass)
+  const int64_t list_cap = k.flag_cap > 0 ? k.flag_cap : kFlagCap;
+  p.need_flagged = (size_t)std::max<int64_t>(1, std::min<int64_t>(db.n_seqs * nq, list_cap));
   p.need_bytes = (size_t)p.qbytes + 64 + (nq + 1) * 8 + nq * sizeof(QueryDesc) + A * A * 4 +
                  (size_t)p.qp16_elems * 2 + (size_t)p.qp2_elems * 4 + (size_t)p.qp8_elems +
                  sizeof(Counters) + p.pairs.size() * sizeof(QueryPair) +

@@ -22,14 +22,6 @@ template <class T> struct Span {
   const T &operator[](size_t i) const { return p[i]; }
 };
 
-// A sequence kept out of the groups (longer than the intra-task threshold), stored
-// contiguously in the packed buffer at `base`.
-struct LongSeq {
-  int64_t base;
-  int32_t len;
-  int32_t orig;  // caller's index
-};
-
 // What the planner reads of a loaded database (the host copies sw_db_load keeps).
 struct DbView {
   int num_cu = 0;
@@ -50,8 +42,13 @@ struct DbView {
 // The knob values a search reads (see SW_KNOB_* in include/swmi.h).
 struct Knobs {
   int64_t strip_rows = 0, grid_waves = 0, route_len = 0, wide_len = 0, max_segments = 0,
-          intra_rows = 0, intra_pairs = 1, query_pairs = 1, main_waves = 0, mem_cap_mb = 0;
+          intra_rows = 0, intra_pairs = 1, query_pairs = 1, main_waves = 0, mem_cap_mb = 0,
+          flag_cap = 0;
 };
+
+// Recompute-list entries when SW_KNOB_FLAG_CAP is 0 (pairs beyond them are found by the
+// overflow pass).
+constexpr int64_t kFlagCap = 1 << 20;
 
 // Resident workgroups (one wave each) per compute unit of the inter-task kernels, by strip
 // height; 0 for a height that is not compiled.

@@ -30,6 +30,7 @@ struct InterArgs {
   int32_t recompute_all;
   int32_t nitems;            // ngroups * nqueries
   int32_t prio_cols;         // items of groups at least this wide run at raised wave priority
+  int32_t flag_cap;          // recompute-list entries; pairs beyond it are marked kSat16
 };
 
 struct Inter2Args {
@@ -51,6 +52,7 @@ struct Inter2Args {
   int32_t recompute_all;
   int32_t nitems;            // ngroups * npairs
   int32_t prio_cols;         // items of groups at least this wide run at raised wave priority
+  int32_t flag_cap;          // recompute-list entries; pairs beyond it are marked kSat16
 };
 
 struct IntraArgs {
@@ -78,6 +80,22 @@ struct IntraArgs {
   PairItem *flagged;         // recompute list for two-pair halves that may have saturated
   int32_t *flag_count;       // Counters::flagged
   int32_t spin_limit;        // polls before a wait between segments gives up (sets *error)
+  int32_t flag_cap;          // recompute-list entries; pairs beyond it are marked kSat16
+};
+
+// The pass over a recompute list that overflowed: every (query, sequence) whose score
+// holds the mark kSat16 is recomputed in int32.
+struct RescanArgs {
+  IntraArgs ia;              // pair sweeps (packed, profiles, penalties, scores, band rings)
+  const GroupDesc *groups;
+  int32_t ngroups;
+  const int32_t *perm;       // sorted position -> caller's index
+  const int32_t *lens;       // sorted position -> length
+  const LongSeq *longs;   // sequences kept out of the groups
+  int32_t nlongs;
+  int32_t nqueries;
+  const int32_t *count;      // Counters::flagged (entries the kernels tried to append)
+  int32_t *next;             // Counters::rescan_next
 };
 
 struct ProfileArgs {
@@ -177,6 +195,7 @@ hipError_t launch_profile2(const Profile2Args &a, hipStream_t s);
 hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s);
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s);
 hipError_t launch_serve(const ServeArgs &a, int grid, hipStream_t s);
+hipError_t launch_rescan(const RescanArgs &a, int grid, hipStream_t s);
 int serve_max_blocks_per_cu();
 
 // Device a loaded database lives on (api.hip; the handle is opaque elsewhere).

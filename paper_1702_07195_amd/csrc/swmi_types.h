@@ -45,6 +45,14 @@ struct PairItem {
   int32_t segment, nsegments;
 };
 
+// A sequence kept out of the groups (longer than the intra-task threshold), stored
+// contiguously in the packed buffer at `base`.
+struct LongSeq {
+  int64_t base;
+  int32_t len;
+  int32_t orig;  // caller's index
+};
+
 // Per-query data used by both kernels.
 struct QueryDesc {
   int64_t qp16;      // element offset of this query's strip profile in the int16 arena
@@ -67,7 +75,7 @@ struct Counters {
   int32_t error;          // set if a bounded wait between segments ran out
   int32_t crit_next;      // next wide item of the critical-pair list
   int32_t crit_narrow;    // (unused: that list has no narrow items)
-  int32_t pad;
+  int32_t rescan_next;    // next chunk of the pass over an overflowed recompute list
 };
 
 // Two queries sharing the lanes of the two-query inter-task kernel (batched searches).
