@@ -41,6 +41,7 @@ std::atomic<int64_t> g_knob_query_pairs{1};
 std::atomic<int64_t> g_knob_main_waves{0};
 std::atomic<int64_t> g_knob_prio_cols{0};
 std::atomic<int64_t> g_knob_flag_cap{0};
+std::atomic<int64_t> g_knob_crit_rows{0};
 
 // Group width from which an inter-task item runs at raised wave priority: a wave sweeping
 // a group of ncols columns spends about 64 * ncols * waves / residues of the launch's
@@ -297,6 +298,7 @@ Knobs knob_snapshot() {
   k.main_waves = g_knob_main_waves.load();
   k.mem_cap_mb = g_knob_mem_cap_mb.load();
   k.flag_cap = g_knob_flag_cap.load();
+  k.crit_rows = g_knob_crit_rows.load();
   return k;
 }
 
@@ -456,7 +458,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ca.flag_count = nullptr;
     ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
     ca.flag_cap = (int32_t)need_flagged;
-    hip_check(launch_intra32(ca, kCritR, kCritWaves, p.grid_crit, w->crit));
+    hip_check(launch_intra32(ca, p.crit_R, kCritWaves, p.grid_crit, w->crit));
     hip_check(hipEventRecord(w->join_crit, w->crit));
   }
   // long sequences: intra-task kernel on the auxiliary stream, concurrent with the sweep
@@ -659,6 +661,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       if (value < 0 || value > INT32_MAX) return SW_EINVAL;
       g_knob_flag_cap = value;
       return SW_OK;
+    case SW_KNOB_CRIT_ROWS:
+      if (value != 0 && value != 4 && value != 8) return SW_EINVAL;
+      g_knob_crit_rows = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -680,6 +686,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_MAIN_WAVES: return g_knob_main_waves.load();
     case SW_KNOB_PRIO_COLS: return g_knob_prio_cols.load();
     case SW_KNOB_FLAG_CAP: return g_knob_flag_cap.load();
+    case SW_KNOB_CRIT_ROWS: return g_knob_crit_rows.load();
     default: return SW_EINVAL;
   }
 }

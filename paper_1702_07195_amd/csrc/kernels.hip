@@ -669,8 +669,57 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
   L.rqB = rqB_next;
 }
 
-// Both pairs of a two-pair item swept by NW waves (the band pipeline of intra_pair; such
-// items are never split).  Returns this lane's packed running maximum.
+// Segments of a split pair hand the bottom row of their last band to the next segment
+// through a global buffer, column by column, with a progress counter.  The waiting side
+// polls relaxed and then takes one acquire fence (an acquire load per poll would
+// invalidate the cache on every iteration); the wait is bounded: after a.spin_limit polls,
+// or once any wait has given up, the error flag is set and the kernel runs to its end with
+// whatever the buffer holds.
+__device__ __forceinline__ void wait_columns(const IntraArgs &a, int prog, int need) {
+  int polls = 0;
+  while (__hip_atomic_load(a.xprog + prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    __builtin_amdgcn_s_sleep(4);
+    if (++polls > a.spin_limit) {
+      __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// Columns 0 .. done - 1 of a segment's bottom row are written (every lane stores the same
+// count, with release order).
+__device__ __forceinline__ void publish_columns(const IntraArgs &a, int prog, int done) {
+  __hip_atomic_store(a.xprog + prog, done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Segments of a split pair chain their maxima: each waits (bounded, as above) for the
+// previous segment's "finished" flag and takes the maximum so far; the last segment writes
+// the score.  Waits point only to earlier segments.  One thread of the workgroup.
+__device__ __forceinline__ int32_t wait_max(const IntraArgs &a, int prog) {
+  int polls = 0;
+  while (__hip_atomic_load(a.xfin + prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+    __builtin_amdgcn_s_sleep(4);
+    if (++polls > a.spin_limit) {
+      __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return __hip_atomic_load(a.xmax + prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void pass_max(const IntraArgs &a, int prog, int32_t m) {
+  __hip_atomic_store(a.xmax + prog, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(a.xfin + prog, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Both pairs of a two-pair item swept by NW waves (the band pipeline of intra_pair),
+// possibly one segment of a split item: the first band of a later segment reads the
+// previous segment's bottom row (both halves packed) and the last band of an earlier one
+// writes its own, as in intra_pair.  Returns this lane's packed running maximum.
 template <int R, int NW>
 __device__ uint32_t intra_pair16(const IntraArgs &a, const PairItem &pa, const PairItem &pb,
                                  const QueryDesc &qd, int w, int2 *ring) {
@@ -696,15 +745,21 @@ __device__ uint32_t intra_pair16(const IntraArgs &a, const PairItem &pa, const P
       if (rd >= st && rd < st + nc) {
         const int k = rd - st;
         const int b = pa.band0 + bl;
-        const int2 *top = ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride;
-        int2 *bot = ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
-        const bool has_top = bl > 0, has_bot = bl < nb - 1;
+        const bool ext_top = bl == 0 && pa.xin >= 0;
+        const bool ext_bot = bl == nb - 1 && pa.xout >= 0;
+        const int2 *top = ext_top ? a.xbnd + pa.xin
+                                  : ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride;
+        int2 *bot = ext_bot ? a.xbnd + pa.xout : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
+        const bool has_top = bl > 0 || ext_top, has_bot = bl < nb - 1 || ext_bot;
+        // the columns this chunk and the next read
+        if (ext_top) wait_columns(a, pa.prog_in, min(nA, 64 * (k + 2)));
         const uint8_t *prof = reinterpret_cast<const uint8_t *>(
             a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
         if (k == 0)
           band_start16(L, lane, nA, nB, top, has_top, resA, csA, resB, csB, prof, pstride);
         band_chunk16(L, vmax, goe2, ge2, lane, k, nA, nB, top, has_top, bot, has_bot, resA,
                      csA, resB, csB, prof, pstride);
+        if (ext_bot) publish_columns(a, pa.prog_out, k == nc - 1 ? nA : min(nA, 64 * k + 1));
         if (k == nc - 1) bl += NW;
       }
     }
@@ -780,38 +835,16 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
         int2 *bot = ext_bot ? a.xbnd + pi.xout : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
         const bool has_top = bl > 0 || ext_top;
         const bool has_bot = bl < nb - 1 || ext_bot;
-        if (ext_top) {
-          // wait until the columns this chunk and the next read are published
-          const int need = min(n, 64 * (k + 2));
-          // (bounded: after a.spin_limit polls, or once any wait has given up, the flag is
-          // set and the kernel runs to its end with whatever the buffer holds)
-          // (polled relaxed, then one acquire fence: an acquire load per poll would
-          // invalidate the cache on every iteration)
-          int polls = 0;
-          while (__hip_atomic_load(a.xprog + pi.prog_in, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-            __builtin_amdgcn_s_sleep(4);
-            if (++polls > a.spin_limit) {
-              __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              break;
-            }
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
+        // wait until the columns this chunk and the next read are published
+        if (ext_top) wait_columns(a, pi.prog_in, min(n, 64 * (k + 2)));
         // this lane's R profile rows of band b
         const uint8_t *prof = reinterpret_cast<const uint8_t *>(
             a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
         if (k == 0) band_start(L, lane, n, top, has_top, resbase, cs, prof, pstride);
         band_chunk(L, vmax, a, lane, k, n, top, has_top, bot, has_bot, resbase, cs, prof,
                    pstride);
-        if (ext_bot) {
-          // columns 0 .. 64k of the bottom row are written (all of them after the last
-          // chunk); every lane stores the same count with release order
-          const int done = k == nc - 1 ? n : min(n, 64 * k + 1);
-          __hip_atomic_store(a.xprog + pi.prog_out, done, __ATOMIC_RELEASE,
-                             __HIP_MEMORY_SCOPE_AGENT);
-        }
+        // columns 0 .. 64k of the bottom row are written (all of them after the last chunk)
+        if (ext_bot) publish_columns(a, pi.prog_out, k == nc - 1 ? n : min(n, 64 * k + 1));
         if (k == nc - 1) bl += NW;
       }
     }
@@ -857,8 +890,14 @@ void k_intra32(IntraArgs a) {
       if (threadIdx.x == 0) {
         uint32_t m = 0;
         for (int i = 0; i < W; ++i) m = pk_max(m, (uint32_t)s_max[i]);
-        finish_half(a, pi, qd, (int)(int16_t)(m & 0xffffu));
-        finish_half(a, pb, qd, (int)(int16_t)(m >> 16));
+        // the packed maxima of a split item's segments are chained like a single pair's
+        if (pi.segment > 0) m = pk_max(m, (uint32_t)wait_max(a, pi.prog_in));
+        if (pi.segment + 1 < pi.nsegments) {
+          pass_max(a, pi.prog_out, (int32_t)m);
+        } else {
+          finish_half(a, pi, qd, (int)(int16_t)(m & 0xffffu));
+          finish_half(a, pb, qd, (int)(int16_t)(m >> 16));
+        }
       }
       continue;
     }
@@ -869,27 +908,10 @@ void k_intra32(IntraArgs a) {
     if (threadIdx.x == 0) {
       int m = 0;
       for (int i = 0; i < W; ++i) m = max(m, s_max[i]);
-      // Segments of a split pair chain their maxima: each waits for the previous
-      // segment's "finished" flag, takes the maximum so far, and passes it on; the last
-      // segment writes the score.  Waits point only to earlier segments.
-      if (pi.segment > 0) {
-        int polls = 0;
-        while (__hip_atomic_load(a.xfin + pi.prog_in, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT) == 0) {
-          if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-          __builtin_amdgcn_s_sleep(4);
-          if (++polls > a.spin_limit) {
-            __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        m = max(m, __hip_atomic_load(a.xmax + pi.prog_in, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT));
-      }
+      // the segments of a split pair chain their maxima; the last one writes the score
+      if (pi.segment > 0) m = max(m, wait_max(a, pi.prog_in));
       if (pi.segment + 1 < pi.nsegments) {
-        __hip_atomic_store(a.xmax + pi.prog_out, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a.xfin + pi.prog_out, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        pass_max(a, pi.prog_out, m);
       } else {
         a.scores[qd.out + pi.out] = m;
       }

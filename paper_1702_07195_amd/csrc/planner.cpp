@@ -231,6 +231,7 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     // ms with four-wave workgroups; a 2005-residue query, at a ratio of 1.1, 8.2 -> 9.3.)
     bool throughput_bound = false;
     p.R = choose_R(lens, intra_res, n_max, wide_len, db.num_cu, k, &throughput_bound);
+    p.throughput_bound = throughput_bound;
     const int64_t mw = k.main_waves;
     p.main_waves = (mw == 4 || mw == 8) ? (int)mw : (throughput_bound ? kNarrowWaves : kIntraWaves);
   }
@@ -328,6 +329,55 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     p.longitems.push_back(it);
     p.second.push_back(none);
   };
+  // Segments of a split pair (and, for a two-pair item, of its second pair, which shares
+  // the first one's bands and boundary rows) are appended consecutively, so segment j is
+  // always claimed after segment j - 1.
+  auto push_segments = [&](const PairItem &it, const PairItem *second, int32_t S) {
+    const int32_t nb = it.band1;
+    const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
+    for (int32_t j = 0; j < S; ++j) {
+      PairItem sg = it;
+      sg.band0 = (int32_t)((int64_t)nb * j / S);
+      sg.band1 = (int32_t)((int64_t)nb * (j + 1) / S);
+      sg.segment = j;
+      sg.nsegments = S;
+      if (j > 0) {
+        sg.xin = p.xbnd_elems - npad;
+        sg.prog_in = p.nprog - 1;
+      }
+      if (j + 1 < S) {
+        sg.xout = p.xbnd_elems;
+        sg.prog_out = p.nprog;
+        p.xbnd_elems += npad;
+        p.nprog += 1;
+      }
+      p.longitems.push_back(sg);
+      if (second) {
+        PairItem sb = *second;
+        sb.band0 = sg.band0;
+        sb.band1 = sg.band1;
+        sb.segment = j;
+        sb.nsegments = S;
+        p.second.push_back(sb);
+        ++p.nduos;
+      } else {
+        p.second.push_back(none);
+      }
+    }
+  };
+  // Split pairs (the costliest, claimed first), then the unsplit wide ones.  When the
+  // search is throughput-bound, consecutive split pairs of the same query, bands and
+  // segment count run two per workgroup in packed int16 (each step about 1.45 times a
+  // single one's, for twice the cells) if the paired pipeline stays within half the
+  // estimated search time.
+  struct Split {
+    PairItem it;
+    int32_t S;
+    bool pairable;
+  };
+  std::vector<Split> splits;
+  std::vector<PairItem> singles;
+  std::vector<bool> singles_pairable;
   for (auto &x : wide) {
     const PairItem &it = x.second;
     const int32_t nb = it.band1;
@@ -342,7 +392,8 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     if (cap > 0) S = std::min<int32_t>(S, (int32_t)cap);
     S = std::max<int32_t>(1, std::min(S, nb));
     if (S == 1) {
-      emit(it, pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
+      singles.push_back(it);
+      singles_pairable.push_back(pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
       continue;
     }
     // A pair whose full pipeline would outlast the search sets its critical path; with
@@ -352,11 +403,17 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     // pipeline.
     // (A wave alone on its SIMD steps in about 0.76 of t_step: 0.38 us at R = 16 on
     // MI355X, where latency keeps a step at about 1.7 times its instruction time.)
-    if (S == s4 && p.R > kCritR && k.intra_rows == 0 && cap == 0 &&
+    // Rows per lane of that launch: 8 (bands of 512 rows), or 4 when SW_KNOB_CRIT_ROWS
+    // asks for it.  (With 4 the step issues fewer instructions but the long mix's
+    // 5478-residue query measured slower, 2,642 against 3,048 GCUPS: a step alone on its
+    // SIMD is bound by latency, not by its instruction count.)
+    p.crit_R = k.crit_rows > 0 ? (int)k.crit_rows : kCritR;
+    const int Rc = p.crit_R;
+    if (S == s4 && p.R > Rc && k.intra_rows == 0 && cap == 0 &&
         piped * 64 * 0.76 * t_step > 0.5 * t_search) {  // still critical with a SIMD per wave
-      const int32_t nbc = (int32_t)((lens[it.query] + 64 * kCritR - 1) / (64 * kCritR));
+      const int32_t nbc = (int32_t)((lens[it.query] + 64 * Rc - 1) / (64 * Rc));
       const double piped_c = (double)(nc + (int64_t)kIntraLag * (nbc - 1));
-      const double step_c = (7.5 * kCritR + 14.0) / (7.5 * p.R + 14.0);
+      const double step_c = (7.5 * Rc + 14.0) / (7.5 * p.R + 14.0);
       if (piped_c * step_c < piped) {
         const int32_t Sc = (nbc + kCritWaves - 1) / kCritWaves;
         const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
@@ -381,27 +438,23 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
         continue;
       }
     }
-    const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
-    for (int32_t j = 0; j < S; ++j) {
-      PairItem sg = it;
-      sg.band0 = (int32_t)((int64_t)nb * j / S);
-      sg.band1 = (int32_t)((int64_t)nb * (j + 1) / S);
-      sg.segment = j;
-      sg.nsegments = S;
-      if (j > 0) {
-        sg.xin = p.xbnd_elems - npad;
-        sg.prog_in = p.nprog - 1;
-      }
-      if (j + 1 < S) {
-        sg.xout = p.xbnd_elems;
-        sg.prog_out = p.nprog;
-        p.xbnd_elems += npad;
-        p.nprog += 1;
-      }
-      p.longitems.push_back(sg);
-      p.second.push_back(none);
-    }
+    const bool pairable = pair_all || (pair_mode == 1 && p.throughput_bound &&
+                                       1.45 * piped * 64 * t_step <= 0.5 * t_search);
+    splits.push_back({it, S, pairable});
   }
+  for (size_t i = 0; i < splits.size(); ++i) {
+    const Split &a = splits[i];
+    if (a.pairable && i + 1 < splits.size()) {
+      const Split &b = splits[i + 1];
+      if (b.pairable && b.it.query == a.it.query && b.it.band1 == a.it.band1 && b.S == a.S) {
+        push_segments(a.it, &b.it, a.S);
+        ++i;
+        continue;
+      }
+    }
+    push_segments(a.it, nullptr, a.S);
+  }
+  for (size_t i = 0; i < singles.size(); ++i) emit(singles[i], singles_pairable[i]);
   p.n_wide = (int32_t)p.longitems.size();
   std::fill(pending.begin(), pending.end(), -1);  // wide and narrow items are not mixed
   for (auto &x : narrow) {
@@ -424,11 +477,11 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     for (size_t k = 0; k < p.longitems.size(); ++k) {
       const PairItem &it = p.longitems[k];
       if (p.second[k].len >= 0)
-        c16 += (int64_t)(it.len + p.second[k].len) * lens[(size_t)it.query];
+        c16 += (int64_t)(it.len + p.second[k].len) * rows_of(it, p.R);
       else
         c32 += (int64_t)it.len * rows_of(it, p.R);
     }
-    for (const PairItem &it : p.crititems) ccrit += (int64_t)it.len * rows_of(it, kCritR);
+    for (const PairItem &it : p.crititems) ccrit += (int64_t)it.len * rows_of(it, p.crit_R);
     int64_t *st = p.stats;
     st[SW_ST_CELLS_INTER16] = sum_all * db.group_res[(size_t)ninter];
     st[SW_ST_CELLS_INTRA32] = c32;

@@ -43,7 +43,7 @@ struct DbView {
 struct Knobs {
   int64_t strip_rows = 0, grid_waves = 0, route_len = 0, wide_len = 0, max_segments = 0,
           intra_rows = 0, intra_pairs = 1, query_pairs = 1, main_waves = 0, mem_cap_mb = 0,
-          flag_cap = 0;
+          flag_cap = 0, crit_rows = 0;
 };
 
 // Recompute-list entries when SW_KNOB_FLAG_CAP is 0 (pairs beyond them are found by the
@@ -64,6 +64,7 @@ struct Plan {
   bool q2 = false;               // two queries per lane (k_inter16q2)
   int R = kIntraR;               // rows per lane of the long-pair intra-task launch
   int main_waves = kIntraWaves;  // waves per workgroup of that launch (8, or 4 at two per CU)
+  bool throughput_bound = false; // the intra-task search is estimated throughput-bound
   int per_cu = 0;                // inter-task workgroups per compute unit
   std::vector<int64_t> lens;     // query lengths
   std::vector<int32_t> qorder;   // queries longest first
@@ -82,7 +83,8 @@ struct Plan {
   std::vector<QueryDesc> qd;
   std::vector<PairItem> longitems;
   std::vector<PairItem> second;     // per long item: its second pair (two-pair items) or len -1
-  std::vector<PairItem> crititems;  // segments of critical pairs, in bands of 64 * kCritR rows
+  std::vector<PairItem> crititems;  // segments of critical pairs, in bands of 64 * crit_R rows
+  int crit_R = 0;                   // rows per lane of the critical-pair launch (0: none)
   int64_t qp16_elems = 0, qp8_elems = 0;
   std::vector<QueryPair> pairs;  // two-query inter-task kernel (empty: k_inter16)
   int64_t qp2_elems = 0;         // dwords of the pair profiles

@@ -29,6 +29,7 @@ using namespace swmi;
 namespace {
 
 std::string g_case;
+int64_t n_split_duos = 0;  // segments of split two-pair items seen
 
 [[noreturn]] void fail(const std::string &msg) {
   std::printf("planner check failed (%s): %s\n", g_case.c_str(), msg.c_str());
@@ -165,14 +166,23 @@ void check_items(const Plan &p, const Db &d, const std::vector<PairItem> &items,
       cover[{it.query, it.out}] += 1;  // a complete pair (or chain)
     }
     if (second && (*second)[i].len >= 0) {
+      // the second pair of a two-pair item shares the first one's rows, segment and
+      // boundary rows (it has none of its own)
       const PairItem &b = (*second)[i];
-      CHECK(it.nsegments == 1 && b.nsegments == 1, L + ": two-pair items are never split");
+      CHECK(b.segment == it.segment && b.nsegments == it.nsegments,
+            L + ": the two pairs of an item are the same segment");
       CHECK(b.query == it.query && b.band0 == it.band0 && b.band1 == it.band1,
             L + ": the two pairs of an item share the query rows");
       CHECK(b.len <= it.len, L + ": the first pair of a two-pair item is the longer");
       CHECK(b.out >= 0 && b.out < d.view.n_seqs && d.len[(size_t)b.out] == b.len,
             L + ": second pair's sequence");
-      cover[{b.query, b.out}] += 1;
+      if (it.segment > 0) {
+        const PairItem &pb = (*second)[writer_at[it.prog_in]];
+        CHECK(pb.out == b.out && pb.segment == b.segment - 1,
+              L + ": the second pair's segment chain");
+      }
+      if (b.segment + 1 == b.nsegments) cover[{b.query, b.out}] += 1;
+      n_split_duos += it.nsegments > 1;
     }
   }
 }
@@ -218,7 +228,9 @@ void check_plan(const Plan &p, const Db &d, const std::vector<int64_t> &qoff, in
   std::vector<int> writers((size_t)std::max(0, p.nprog), 0), readers((size_t)std::max(0, p.nprog), 0);
   CHECK(p.second.size() == p.longitems.size(), "one second entry per main item");
   check_items(p, d, p.longitems, &p.second, p.R, nq, cover, writers, readers, "main list");
-  check_items(p, d, p.crititems, nullptr, kCritR, nq, cover, writers, readers, "critical list");
+  CHECK(p.crititems.empty() || p.crit_R == 4 || p.crit_R == 8, "critical rows per lane");
+  check_items(p, d, p.crititems, nullptr, p.crit_R ? p.crit_R : kCritR, nq, cover, writers,
+              readers, "critical list");
   for (int32_t k = 0; k < p.nprog; ++k)
     CHECK(writers[(size_t)k] == 1 && readers[(size_t)k] == 1, "each boundary written and read once");
   for (int64_t q = 0; q < nq; ++q) {
@@ -315,6 +327,7 @@ int main() {
     k.intra_pairs = pick({1, 1, 0, 2});
     k.query_pairs = pick({1, 1, 0});
     k.main_waves = pick({0, 0, 4, 8});
+    k.crit_rows = pick({0, 0, 4, 8});
     g_case += " n=" + std::to_string(n) + " nq=" + std::to_string(nq) + " cu=" +
               std::to_string(num_cu);
     const Plan p = make_plan(d.view, qoff.data(), nq, k, occ);
@@ -326,9 +339,11 @@ int main() {
     n_q2 += p.q2;
   }
   // the random cases must reach every kind of item
-  if (!n_split || !n_crit || !n_duo || !n_routed || !n_q2) fail("a kind of item never planned");
+  if (!n_split || !n_crit || !n_duo || !n_routed || !n_q2 || !n_split_duos)
+    fail("a kind of item never planned");
   std::printf("planner ok: %d cases (split pairs %lld, critical pairs %lld, two-pair items "
-              "%lld, routed groups %lld, query pairs %lld)\n", cases, (long long)n_split,
-              (long long)n_crit, (long long)n_duo, (long long)n_routed, (long long)n_q2);
+              "%lld, split two-pair segments %lld, routed groups %lld, query pairs %lld)\n", cases,
+              (long long)n_split, (long long)n_crit, (long long)n_duo, (long long)n_split_duos,
+              (long long)n_routed, (long long)n_q2);
   return 0;
 }

@@ -430,18 +430,30 @@ def test_split_pairs_across_workgroups(m, cap, waves):
     assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
 
 
-def test_many_critical_pairs():
-    # A database of long sequences only, against a query of six 1024-row bands: every
-    # pair is on the critical path and goes to the critical-pair launch (8 rows per
-    # lane, 11 bands in three segments on workgroups of their own, 120 segments in
-    # all).  Sequences from 6,000 (in groups) to 12,000 (stored apart).
+@pytest.mark.parametrize("crit_rows", [0, 4, 8])
+def test_critical_pairs(crit_rows):
+    # 2,000 ordinary sequences and 10 of 15,000-30,000 residues against a 5,478-residue
+    # query: the long pairs set the critical path and go to the critical-pair launch, in
+    # bands of 256 or 512 rows (4 or 8 rows per lane, segments of four bands on
+    # workgroups of their own), next to the main intra-task launch at 16 rows per lane.
     rng = np.random.Generator(np.random.PCG64(5478))
-    db = synth.db_from_lengths(rng, rng.integers(6000, 12000, 40))
+    lengths = np.concatenate([synth.lognormal_lengths(rng, 2000, 300, 0.8, 10, 8000),
+                              rng.integers(15000, 30000, 10)])
+    db = synth.db_from_lengths(rng, lengths)
     q = synth.residues(rng, 5478)
-    _say("many critical pairs")
-    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
-        got = h.search(q, synth.BLOSUM62, 10, 2)
-    assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
+    old = swmi.get_knob(swmi.SW_KNOB_CRIT_ROWS)
+    swmi.set_knob(swmi.SW_KNOB_CRIT_ROWS, crit_rows)
+    try:
+        _say(f"critical pairs, rows per lane {crit_rows}")
+        with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+            got = h.search(q, synth.BLOSUM62, 10, 2)
+            st = h.stats()
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_CRIT_ROWS, old)
+    assert st["cells_crit"] > 0 and st["intra_rows"] == 16
+    idx = np.concatenate([np.arange(2000, 2010), rng.choice(2000, 200, replace=False)])
+    want = oracle.search(q, db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
+    assert np.array_equal(got[idx], want)
 
 
 @pytest.fixture(scope="module")
@@ -657,3 +669,53 @@ def test_largest_alphabet(route):
     finally:
         swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, old)
     assert np.array_equal(got, oracle.search(q, db.residues, db.offsets, sm, 7, 3))
+
+
+@pytest.mark.parametrize("pairs", [1, 2])
+def test_split_two_pair_items(pairs):
+    # Long sequences split across workgroups, two per workgroup in packed int16 (pairing
+    # of split pairs: automatic when throughput-bound, or forced), their segments chained
+    # through packed boundary rows and packed maxima; the oracle decides.
+    rng = np.random.Generator(np.random.PCG64(606 + pairs))
+    lengths = np.concatenate([rng.integers(9000, 12000, 12), rng.integers(1, 400, 100)])
+    db = synth.db_from_lengths(rng, lengths)
+    q = synth.residues(rng, 5000)
+    old = swmi.get_knob(swmi.SW_KNOB_INTRA_PAIRS)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, pairs)
+    try:
+        with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+            _say(f"split two-pair items, pairs knob {pairs}")
+            got = h.search(q, synth.BLOSUM62, 10, 2)
+            st = h.stats()
+    finally:
+        swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, old)
+    if pairs == 2:
+        assert st["cells_intra16"] > 0
+    assert np.array_equal(got, _oracle(q, db, synth.BLOSUM62, 10, 2))
+
+
+def test_split_two_pair_items_with_saturation():
+    # SM(a, a) = 7, every pair routed to the intra-task kernel, every pair paired: the
+    # split items pair a^4681 with a^4682 (and a^4680 with its neighbour); the saturated
+    # halves (32767, 32774 against the query a^4700) are recomputed in int32, the others
+    # keep their int16 scores.
+    sm = np.array([[7, -3], [-3, 7]], dtype=np.int32)
+    rng = np.random.Generator(np.random.PCG64(707))
+    seqs = [np.zeros(n, np.uint8) for n in (4680, 4681, 4682)]
+    seqs += [rng.integers(0, 2, size=int(n)).astype(np.uint8) for n in rng.integers(4600, 4700, 9)]
+    db = synth.db_from_seqs(seqs)
+    q = np.zeros(4700, np.uint8)
+    knobs = (swmi.SW_KNOB_ROUTE_LEN, swmi.SW_KNOB_INTRA_PAIRS)
+    old = [swmi.get_knob(k) for k in knobs]
+    swmi.set_knob(swmi.SW_KNOB_ROUTE_LEN, 1)
+    swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, 2)
+    try:
+        with swmi.sw_db_load(db.residues, db.offsets, 2) as h:
+            _say("split two-pair items with saturation")
+            got = h.search(q, sm, 10, 2)
+    finally:
+        for k, v in zip(knobs, old):
+            swmi.set_knob(k, v)
+    want = _oracle(q, db, sm, 10, 2)
+    assert list(want[:3]) == [32760, 32767, 32774]
+    assert np.array_equal(got, want)
