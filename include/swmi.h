@@ -378,6 +378,10 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
  *                          recomputed by a pass over all pairs.  Scores are the same.
  *   SW_KNOB_CRIT_ROWS      query rows per lane of the critical-pair launch: 4 or 8 (bands
  *                          of 256 or 512 rows); 0 (default) = 8.  Scores are the same.
+ *   SW_KNOB_CRIT_SHARE     a split long pair whose band pipeline is estimated to take more
+ *                          than this percentage of the whole intra-task search runs in
+ *                          the critical-pair launch (1..100; 0 = automatic).  Scores are
+ *                          the same.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -395,6 +399,7 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
 #define SW_KNOB_PRIO_COLS      14
 #define SW_KNOB_FLAG_CAP       15
 #define SW_KNOB_CRIT_ROWS      16
+#define SW_KNOB_CRIT_SHARE     17
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

@@ -42,6 +42,7 @@ std::atomic<int64_t> g_knob_main_waves{0};
 std::atomic<int64_t> g_knob_prio_cols{0};
 std::atomic<int64_t> g_knob_flag_cap{0};
 std::atomic<int64_t> g_knob_crit_rows{0};
+std::atomic<int64_t> g_knob_crit_share{0};
 
 // Group width from which an inter-task item runs at raised wave priority: a wave sweeping
 // a group of ncols columns spends about 64 * ncols * waves / residues of the launch's
@@ -299,6 +300,7 @@ Knobs knob_snapshot() {
   k.mem_cap_mb = g_knob_mem_cap_mb.load();
   k.flag_cap = g_knob_flag_cap.load();
   k.crit_rows = g_knob_crit_rows.load();
+  k.crit_share = g_knob_crit_share.load();
   return k;
 }
 
@@ -427,42 +429,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     hip_check(launch_profile2(pb, s));
   }
 
-  if (p.grid_long > 0 || p.grid_crit > 0) hip_check(hipEventRecord(w->fork, s));
-  // critical pairs first (their workgroups are dispatched before the main launch's),
-  // on a stream of their own, with finer bands
-  if (p.grid_crit > 0) {
-    hip_check(hipStreamWaitEvent(w->crit, w->fork, 0));
-    IntraArgs ca;
-    ca.packed = (const uint8_t *)db->packed.ptr;
-    ca.items = d_crit;
-    ca.count_dev = nullptr;
-    ca.count = (int32_t)p.crititems.size();
-    ca.next = &ctr->crit_next;
-    ca.next_narrow = &ctr->crit_narrow;
-    ca.n_wide = ca.count;
-    ca.queries = d_qdesc;
-    ca.qp8 = (const int8_t *)w->qp8.ptr;
-    ca.goe = gap_open + gap_extend;
-    ca.ge = gap_extend;
-    ca.scores = scores_dev;
-    ca.bnd = (int2 *)w->bnd32.ptr + (size_t)(p.grid_long + p.grid_re) * bnd32_slot;
-    ca.bnd_slot_elems = (int64_t)bnd32_slot;
-    ca.bnd_stride = bnd32_stride;
-    ca.xbnd = (int2 *)w->xbnd.ptr;
-    ca.xprog = (int32_t *)w->xprog.ptr;
-    ca.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
-    ca.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
-    ca.error = &ctr->error;
-    ca.second = nullptr;
-    ca.flagged = nullptr;
-    ca.flag_count = nullptr;
-    ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
-    ca.flag_cap = (int32_t)need_flagged;
-    hip_check(launch_intra32(ca, p.crit_R, kCritWaves, p.grid_crit, w->crit));
-    hip_check(hipEventRecord(w->join_crit, w->crit));
-  }
   // long sequences: intra-task kernel on the auxiliary stream, concurrent with the sweep
-  if (p.grid_long > 0) {
+  // (enqueued after the inter-task launch, whose few waves are then dispatched first)
+  auto launch_main = [&]() {
+    if (p.grid_long <= 0) return;
     hip_check(hipStreamWaitEvent(w->aux, w->fork, 0));
     IntraArgs ia;
     ia.packed = (const uint8_t *)db->packed.ptr;
@@ -498,8 +468,48 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       w->timed[1] = true;
     }
     hip_check(hipEventRecord(w->join, w->aux));
-  }
+  };
 
+  if (p.grid_long > 0 || p.grid_crit > 0) hip_check(hipEventRecord(w->fork, s));
+  // critical pairs first (their workgroups are dispatched before the main launch's),
+  // on a stream of their own, with finer bands
+  if (p.grid_crit > 0) {
+    hip_check(hipStreamWaitEvent(w->crit, w->fork, 0));
+    IntraArgs ca;
+    ca.packed = (const uint8_t *)db->packed.ptr;
+    ca.items = d_crit;
+    ca.count_dev = nullptr;
+    ca.count = (int32_t)p.crititems.size();
+    ca.next = &ctr->crit_next;
+    ca.next_narrow = &ctr->crit_narrow;
+    ca.n_wide = ca.count;
+    ca.queries = d_qdesc;
+    ca.qp8 = (const int8_t *)w->qp8.ptr;
+    ca.goe = gap_open + gap_extend;
+    ca.ge = gap_extend;
+    ca.scores = scores_dev;
+    ca.bnd = (int2 *)w->bnd32.ptr + (size_t)(p.grid_long + p.grid_re) * bnd32_slot;
+    ca.bnd_slot_elems = (int64_t)bnd32_slot;
+    ca.bnd_stride = bnd32_stride;
+    ca.xbnd = (int2 *)w->xbnd.ptr;
+    ca.xprog = (int32_t *)w->xprog.ptr;
+    ca.xfin = (int32_t *)w->xprog.ptr + std::max<int32_t>(1, p.nprog);
+    ca.xmax = (int32_t *)w->xprog.ptr + 2 * std::max<int32_t>(1, p.nprog);
+    ca.error = &ctr->error;
+    ca.second = nullptr;
+    ca.flagged = nullptr;
+    ca.flag_count = nullptr;
+    ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
+    ca.flag_cap = (int32_t)need_flagged;
+    hip_check(launch_intra32(ca, p.crit_R, kCritWaves, p.grid_crit, w->crit));
+    hip_check(hipEventRecord(w->join_crit, w->crit));
+  }
+  // An inter-task launch of fewer items than the chip has SIMDs, beside the intra-task
+  // launches, has its waves share SIMDs with theirs; at raised priority it finishes first
+  // instead of last.  (Long-sequence mix, 5478-residue query, on MI355X: its three items
+  // took 4.2-12.4 ms beside a search of about 11 ms, ending last when dispatched late.)
+  const bool inter_beside_intra =
+      (p.grid_long > 0 || p.grid_crit > 0) && nitems16 < 4LL * std::max(1, db->num_cu);
   if (nq > 0) {
     const bool timed = allow_timing && db->timing.load();
     if (timed && p.grid16 > 0) hip_check(hipEventRecord(w->t0[0], s));
@@ -523,7 +533,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.bnd_slot_words = (int64_t)bnd16_slot;
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
-      ia.prio_cols = prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
+      ia.prio_cols = inter_beside_intra
+                         ? 1
+                         : prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
       ia.flag_cap = (int32_t)need_flagged;
       hip_check(launch_inter16q2(ia, p.T, p.grid16, s));
     } else {
@@ -546,7 +558,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.bnd_slot_words = (int64_t)bnd16_slot;
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
-      ia.prio_cols = prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
+      ia.prio_cols = inter_beside_intra
+                         ? 1
+                         : prio_cols_for(db->group_res[(size_t)p.ngroups_inter], p.grid16);
       ia.flag_cap = (int32_t)need_flagged;
       hip_check(launch_inter16(ia, p.T, p.grid16, s));
     }
@@ -554,6 +568,10 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       hip_check(hipEventRecord(w->t1[0], s));
       w->timed[0] = true;
     }
+  }
+  launch_main();
+  if (nq > 0) {
+    const bool timed = allow_timing && db->timing.load();
     // exact int32 recompute of the saturated alignments of both kernels (count read on
     // the device), after the long-pair kernel; it uses the boundary slots after that
     // kernel's
@@ -665,6 +683,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       if (value != 0 && value != 4 && value != 8) return SW_EINVAL;
       g_knob_crit_rows = value;
       return SW_OK;
+    case SW_KNOB_CRIT_SHARE:
+      if (value < 0 || value > 100) return SW_EINVAL;
+      g_knob_crit_share = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -687,6 +709,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_PRIO_COLS: return g_knob_prio_cols.load();
     case SW_KNOB_FLAG_CAP: return g_knob_flag_cap.load();
     case SW_KNOB_CRIT_ROWS: return g_knob_crit_rows.load();
+    case SW_KNOB_CRIT_SHARE: return g_knob_crit_share.load();
     default: return SW_EINVAL;
   }
 }

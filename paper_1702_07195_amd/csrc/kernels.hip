@@ -472,31 +472,49 @@ struct BandLane {
   RowBuf<R> P[IntraBuf<R>::n];
 };
 
-// Profile rows (int8) of one lane: `prof` points at its R rows for code 0; code c's rows
-// are c * pstride bytes further.
+// Profile rows (int8) of one lane.  The band's profile starts at `pbase` (the same for
+// the whole wave), code c's rows of the band are c * pstride bytes further and lane l's R
+// rows l * R bytes further still.  The code travels down the lanes already multiplied by
+// pstride, so a request is one add and one load with a wave-uniform base.
 template <int R>
-__device__ __forceinline__ void load_rows(RowBuf<R> &dst, const uint8_t *prof, uint32_t pstride,
-                                          int code) {
-  dst.v = *reinterpret_cast<const decltype(dst.v) *>(prof + (uint32_t)code * pstride);
+__device__ __forceinline__ void load_rows(RowBuf<R> &dst, const uint8_t *pbase, uint32_t off) {
+  dst.v = *reinterpret_cast<const decltype(dst.v) *>(pbase + off);
+}
+
+// A wave-uniform 64-bit value held in scalar registers (the profile loads take the band's
+// profile address as their scalar base).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Residue code of column `col` of a sequence (kPadCode outside [0, n)), multiplied by
+// the profile's code stride.
+__device__ __forceinline__ int code_off(const uint8_t *resbase, int cs, int col, int n,
+                                        uint32_t pstride) {
+  const int c = col < n ? (int)resbase[(col >> 2) * (int64_t)cs + (col & 3)] : kPadCode;
+  return c * (int)pstride;
 }
 
 // Start a band: zero state, load the first chunk's band-top values and residues, and
 // request the profile rows of steps 0 .. IntraBuf<R>::n - 2.  The code lane l needs at step s
 // is that of column s - l: its left neighbour's code of step s - 1 (lane 0 takes column
-// s's residue), so codes run ahead as a chain of wave shifts.
+// s's residue), so codes run ahead as a chain of wave shifts (as offsets: code * pstride).
 template <int R>
 __device__ __forceinline__ void band_start(BandLane<R> &L, int lane, int n, const int2 *top,
                                            bool has_top, const uint8_t *resbase, int cs,
-                                           const uint8_t *prof, uint32_t pstride) {
+                                           const uint8_t *pbase, uint32_t lane_off,
+                                           uint32_t pstride) {
 #pragma unroll
   for (int r = 0; r < R; ++r) { L.H[r] = 0; L.E[r] = 0; }
-  L.hbot = 0; L.fbot = 0; L.hdiag = 0; L.cfar = kPadCode;
+  L.hbot = 0; L.fbot = 0; L.hdiag = 0; L.cfar = kPadCode * (int)pstride;
   L.tq = (has_top && lane < n) ? top[lane] : make_int2(0, 0);
-  L.rq = lane < n ? resbase[(lane >> 2) * (int64_t)cs + (lane & 3)] : kPadCode;
+  L.rq = code_off(resbase, cs, lane, n, pstride);
 #pragma unroll
   for (int t = 0; t + 1 < IntraBuf<R>::n; ++t) {
     L.cfar = wave_shr1(L.cfar, __builtin_amdgcn_readlane(L.rq, t));
-    load_rows(L.P[t], prof, pstride, L.cfar);
+    load_rows(L.P[t], pbase, (uint32_t)L.cfar + lane_off);
   }
 }
 
@@ -504,29 +522,30 @@ __device__ __forceinline__ void band_start(BandLane<R> &L, int lane, int n, cons
 // computed.  Step s computes with the rows in buffer s % NB (NB = IntraBuf<R>::n) and
 // requests those of step s + NB - 1 into the buffer step s - 1 used, so each request has
 // NB - 1 steps to arrive; steps go in groups of NB, so no buffer is ever
-// copied.  Each row's diagonal sum H(i-1, j-1) + SM is formed before the row above is
-// overwritten, which lets H stay in place from step to step.
+// copied.  The last group's requests reach into the next chunk's residues, so it is
+// unrolled apart from the others and the loop over groups has no branch.  Each row's
+// diagonal sum H(i-1, j-1) + SM is formed before the row above is overwritten, which
+// lets H stay in place from step to step.  Lane 63 (when `store_bot`) stores the bottom
+// row's (H, F) of column s - 63 at every step.
 template <int R>
 __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const IntraArgs &a,
                                            int lane, int k, int n, const int2 *top,
-                                           bool has_top, int2 *bot, bool has_bot,
+                                           bool has_top, int2 *bot, bool store_bot,
                                            const uint8_t *resbase, int cs,
-                                           const uint8_t *prof, uint32_t pstride) {
+                                           const uint8_t *pbase, uint32_t lane_off,
+                                           uint32_t pstride) {
   constexpr int NB = IntraBuf<R>::n;
   constexpr int D = NB - 1;  // prefetch distance in steps
-  static_assert(64 % NB == 0, "a chunk must hold whole groups of steps");
+  static_assert(64 % NB == 0 && NB >= 2, "a chunk must hold whole groups of steps");
   const int col_next = 64 * (k + 1) + lane;
   const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
-  const int rq_next = col_next < n
-      ? (int)resbase[(col_next >> 2) * (int64_t)cs + (col_next & 3)] : kPadCode;
+  const int rq_next = code_off(resbase, cs, col_next, n, pstride);
+  int2 *bchunk = bot + (64 * k - 63);
 
-  auto step = [&](const int i, const RowBuf<R> &P, RowBuf<R> &Pfar) {
-    const int s = 64 * k + i;
-    // request the rows of step s + D (its column residue is in this chunk or the next)
-    const int cin = i + D < 64 ? __builtin_amdgcn_readlane(L.rq, i + D)
-                               : __builtin_amdgcn_readlane(rq_next, i + D - 64);
+  auto step = [&](const int i, const int cin, const RowBuf<R> &P, RowBuf<R> &Pfar) {
+    // request the rows of step s + D
     L.cfar = wave_shr1(L.cfar, cin);
-    load_rows(Pfar, prof, pstride, L.cfar);
+    load_rows(Pfar, pbase, (uint32_t)L.cfar + lane_off);
     const int hup = wave_shr1(L.hbot, __builtin_amdgcn_readlane(L.tq.x, i));
     int f = wave_shr1(L.fbot, __builtin_amdgcn_readlane(L.tq.y, i));
     auto sm = [&](int r) {  // row r's score, sign-extended from its byte
@@ -548,13 +567,19 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
     }
     L.hbot = h;
     L.fbot = f;
-    if (has_bot && lane == 63 && s >= 63 && s - 63 < n) bot[s - 63] = make_int2(h, f);
+    if (store_bot) bchunk[i] = make_int2(h, f);
   };
-  for (int i = 0; i < 64; i += NB) {
+#pragma unroll 1
+  for (int i = 0; i < 64 - NB; i += NB) {
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      step(i + u, L.P[u], L.P[(u + NB - 1) % NB]);
+      step(i + u, __builtin_amdgcn_readlane(L.rq, i + u + D), L.P[u], L.P[(u + NB - 1) % NB]);
   }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    step(64 - NB + u,
+         u == 0 ? __builtin_amdgcn_readlane(L.rq, 63) : __builtin_amdgcn_readlane(rq_next, u - 1),
+         L.P[u], L.P[(u + NB - 1) % NB]);
   L.tq = tq_next;
   L.rq = rq_next;
 }
@@ -592,19 +617,21 @@ template <int R>
 __device__ __forceinline__ void band_start16(BandLane16<R> &L, int lane, int nA, int nB,
                                              const int2 *top, bool has_top,
                                              const uint8_t *resA, int csA, const uint8_t *resB,
-                                             int csB, const uint8_t *prof, uint32_t pstride) {
+                                             int csB, const uint8_t *pbase, uint32_t lane_off,
+                                             uint32_t pstride) {
 #pragma unroll
   for (int r = 0; r < R; ++r) { L.H[r] = 0; L.E[r] = 0; }
-  L.hbot = 0; L.fbot = 0; L.hdiag = 0; L.cfarA = kPadCode; L.cfarB = kPadCode;
+  L.hbot = 0; L.fbot = 0; L.hdiag = 0;
+  L.cfarA = L.cfarB = kPadCode * (int)pstride;
   L.tq = (has_top && lane < nA) ? top[lane] : make_int2(0, 0);
-  L.rqA = lane < nA ? resA[(lane >> 2) * (int64_t)csA + (lane & 3)] : kPadCode;
-  L.rqB = lane < nB ? resB[(lane >> 2) * (int64_t)csB + (lane & 3)] : kPadCode;
+  L.rqA = code_off(resA, csA, lane, nA, pstride);
+  L.rqB = code_off(resB, csB, lane, nB, pstride);
 #pragma unroll
   for (int t = 0; t + 1 < IntraBuf16<R>::n; ++t) {
     L.cfarA = wave_shr1(L.cfarA, __builtin_amdgcn_readlane(L.rqA, t));
     L.cfarB = wave_shr1(L.cfarB, __builtin_amdgcn_readlane(L.rqB, t));
-    load_rows(L.PA[t], prof, pstride, L.cfarA);
-    load_rows(L.PB[t], prof, pstride, L.cfarB);
+    load_rows(L.PA[t], pbase, (uint32_t)L.cfarA + lane_off);
+    load_rows(L.PB[t], pbase, (uint32_t)L.cfarB + lane_off);
   }
 }
 
@@ -614,29 +641,25 @@ template <int R>
 __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, uint32_t goe2,
                                              uint32_t ge2, int lane, int k, int nA, int nB,
                                              const int2 *top, bool has_top, int2 *bot,
-                                             bool has_bot, const uint8_t *resA, int csA,
+                                             bool store_bot, const uint8_t *resA, int csA,
                                              const uint8_t *resB, int csB,
-                                             const uint8_t *prof, uint32_t pstride) {
+                                             const uint8_t *pbase, uint32_t lane_off,
+                                             uint32_t pstride) {
   constexpr int NB = IntraBuf16<R>::n;
   constexpr int D = NB - 1;
+  static_assert(64 % NB == 0 && NB >= 2, "a chunk must hold whole groups of steps");
   const int col_next = 64 * (k + 1) + lane;
   const int2 tq_next = (has_top && col_next < nA) ? top[col_next] : make_int2(0, 0);
-  const int rqA_next = col_next < nA
-      ? (int)resA[(col_next >> 2) * (int64_t)csA + (col_next & 3)] : kPadCode;
-  const int rqB_next = col_next < nB
-      ? (int)resB[(col_next >> 2) * (int64_t)csB + (col_next & 3)] : kPadCode;
+  const int rqA_next = code_off(resA, csA, col_next, nA, pstride);
+  const int rqB_next = code_off(resB, csB, col_next, nB, pstride);
+  int2 *bchunk = bot + (64 * k - 63);
 
-  auto step = [&](const int i, const RowBuf<R> &PA, const RowBuf<R> &PB, RowBuf<R> &PAfar,
-                  RowBuf<R> &PBfar) {
-    const int s = 64 * k + i;
-    const int cinA = i + D < 64 ? __builtin_amdgcn_readlane(L.rqA, i + D)
-                                : __builtin_amdgcn_readlane(rqA_next, i + D - 64);
-    const int cinB = i + D < 64 ? __builtin_amdgcn_readlane(L.rqB, i + D)
-                                : __builtin_amdgcn_readlane(rqB_next, i + D - 64);
+  auto step = [&](const int i, const int cinA, const int cinB, const RowBuf<R> &PA,
+                  const RowBuf<R> &PB, RowBuf<R> &PAfar, RowBuf<R> &PBfar) {
     L.cfarA = wave_shr1(L.cfarA, cinA);
     L.cfarB = wave_shr1(L.cfarB, cinB);
-    load_rows(PAfar, prof, pstride, L.cfarA);
-    load_rows(PBfar, prof, pstride, L.cfarB);
+    load_rows(PAfar, pbase, (uint32_t)L.cfarA + lane_off);
+    load_rows(PBfar, pbase, (uint32_t)L.cfarB + lane_off);
     const uint32_t hup = (uint32_t)wave_shr1((int)L.hbot, __builtin_amdgcn_readlane(L.tq.x, i));
     uint32_t f = (uint32_t)wave_shr1((int)L.fbot, __builtin_amdgcn_readlane(L.tq.y, i));
     uint32_t x = pk_adds(L.hdiag, pair_score<R>(PA, PB, 0));
@@ -655,15 +678,22 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
     }
     L.hbot = h;
     L.fbot = f;
-    if (has_bot && lane == 63 && s >= 63 && s - 63 < nA)
-      bot[s - 63] = make_int2((int)h, (int)f);
+    if (store_bot) bchunk[i] = make_int2((int)h, (int)f);
   };
-  for (int i = 0; i < 64; i += NB) {
+#pragma unroll 1
+  for (int i = 0; i < 64 - NB; i += NB) {
 #pragma unroll
     for (int u = 0; u < NB; ++u)
-      step(i + u, L.PA[u], L.PB[u], L.PA[(u + NB - 1) % NB],
-           L.PB[(u + NB - 1) % NB]);
+      step(i + u, __builtin_amdgcn_readlane(L.rqA, i + u + D),
+           __builtin_amdgcn_readlane(L.rqB, i + u + D), L.PA[u], L.PB[u],
+           L.PA[(u + NB - 1) % NB], L.PB[(u + NB - 1) % NB]);
   }
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+    step(64 - NB + u,
+         u == 0 ? __builtin_amdgcn_readlane(L.rqA, 63) : __builtin_amdgcn_readlane(rqA_next, u - 1),
+         u == 0 ? __builtin_amdgcn_readlane(L.rqB, 63) : __builtin_amdgcn_readlane(rqB_next, u - 1),
+         L.PA[u], L.PB[u], L.PA[(u + NB - 1) % NB], L.PB[(u + NB - 1) % NB]);
   L.tq = tq_next;
   L.rqA = rqA_next;
   L.rqB = rqB_next;
@@ -736,6 +766,7 @@ __device__ uint32_t intra_pair16(const IntraArgs &a, const PairItem &pa, const P
   const int csA = pa.cstride, csB = pb.cstride;
   const uint32_t pstride = (uint32_t)qd.mrows;
   const uint32_t goe2 = (uint32_t)a.goe * 0x10001u, ge2 = (uint32_t)a.ge * 0x10001u;
+  const uint32_t lane_off = (uint32_t)(lane * R);
 
   int bl = w;
   BandLane16<R> L;
@@ -747,18 +778,21 @@ __device__ uint32_t intra_pair16(const IntraArgs &a, const PairItem &pa, const P
         const int b = pa.band0 + bl;
         const bool ext_top = bl == 0 && pa.xin >= 0;
         const bool ext_bot = bl == nb - 1 && pa.xout >= 0;
-        const int2 *top = ext_top ? a.xbnd + pa.xin
-                                  : ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride;
-        int2 *bot = ext_bot ? a.xbnd + pa.xout : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
+        const int2 *top = (ext_top ? a.xbnd + pa.xin
+                                   : ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride) +
+                          kBndLead;
+        int2 *bot = (ext_bot ? a.xbnd + pa.xout
+                             : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride) + kBndLead;
         const bool has_top = bl > 0 || ext_top, has_bot = bl < nb - 1 || ext_bot;
         // the columns this chunk and the next read
         if (ext_top) wait_columns(a, pa.prog_in, min(nA, 64 * (k + 2)));
-        const uint8_t *prof = reinterpret_cast<const uint8_t *>(
-            a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
+        const uint8_t *pbase = reinterpret_cast<const uint8_t *>(a.qp8) +
+                               uniform64(qd.qp8 + (int64_t)b * 64 * R);
         if (k == 0)
-          band_start16(L, lane, nA, nB, top, has_top, resA, csA, resB, csB, prof, pstride);
-        band_chunk16(L, vmax, goe2, ge2, lane, k, nA, nB, top, has_top, bot, has_bot, resA,
-                     csA, resB, csB, prof, pstride);
+          band_start16(L, lane, nA, nB, top, has_top, resA, csA, resB, csB, pbase, lane_off,
+                       pstride);
+        band_chunk16(L, vmax, goe2, ge2, lane, k, nA, nB, top, has_top, bot,
+                     has_bot && lane == 63, resA, csA, resB, csB, pbase, lane_off, pstride);
         if (ext_bot) publish_columns(a, pa.prog_out, k == nc - 1 ? nA : min(nA, 64 * k + 1));
         if (k == nc - 1) bl += NW;
       }
@@ -816,6 +850,7 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
   const uint8_t *resbase = a.packed + pi.base;
   const int cs = pi.cstride;
   const uint32_t pstride = (uint32_t)qd.mrows;
+  const uint32_t lane_off = (uint32_t)(lane * R);
 
   int bl = w;  // band of this segment that this wave works on
   BandLane<R> L;
@@ -830,19 +865,21 @@ __device__ int32_t intra_pair(const IntraArgs &a, const PairItem &pi, const Quer
         // the last band of an earlier segment writes its own for the next segment
         const bool ext_top = bl == 0 && pi.xin >= 0;
         const bool ext_bot = bl == nb - 1 && pi.xout >= 0;
-        const int2 *top = ext_top ? a.xbnd + pi.xin
-                                  : ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride;
-        int2 *bot = ext_bot ? a.xbnd + pi.xout : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride;
+        const int2 *top = (ext_top ? a.xbnd + pi.xin
+                                   : ring + (int64_t)((bl + NW) % (NW + 1)) * a.bnd_stride) +
+                          kBndLead;
+        int2 *bot = (ext_bot ? a.xbnd + pi.xout
+                             : ring + (int64_t)(bl % (NW + 1)) * a.bnd_stride) + kBndLead;
         const bool has_top = bl > 0 || ext_top;
         const bool has_bot = bl < nb - 1 || ext_bot;
         // wait until the columns this chunk and the next read are published
         if (ext_top) wait_columns(a, pi.prog_in, min(n, 64 * (k + 2)));
-        // this lane's R profile rows of band b
-        const uint8_t *prof = reinterpret_cast<const uint8_t *>(
-            a.qp8 + qd.qp8 + (int64_t)b * 64 * R + lane * R);
-        if (k == 0) band_start(L, lane, n, top, has_top, resbase, cs, prof, pstride);
-        band_chunk(L, vmax, a, lane, k, n, top, has_top, bot, has_bot, resbase, cs, prof,
-                   pstride);
+        // the profile rows of band b
+        const uint8_t *pbase = reinterpret_cast<const uint8_t *>(a.qp8) +
+                               uniform64(qd.qp8 + (int64_t)b * 64 * R);
+        if (k == 0) band_start(L, lane, n, top, has_top, resbase, cs, pbase, lane_off, pstride);
+        band_chunk(L, vmax, a, lane, k, n, top, has_top, bot, has_bot && lane == 63, resbase,
+                   cs, pbase, lane_off, pstride);
         // columns 0 .. 64k of the bottom row are written (all of them after the last chunk)
         if (ext_bot) publish_columns(a, pi.prog_out, k == nc - 1 ? n : min(n, 64 * k + 1));
         if (k == nc - 1) bl += NW;
@@ -864,7 +901,7 @@ void k_intra32(IntraArgs a) {
   __shared__ int s_item;
   __shared__ int s_max[W];
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
   int2 *slot = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_elems;
   // (the recompute list: the kernels count every pair they tried to append, and only the
   // first flag_cap are in the list; the others are left to k_rescan)
@@ -878,7 +915,7 @@ void k_intra32(IntraArgs a) {
       s_item = it < n_wide ? it : -1;
     }
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     if (it < 0) break;
     const PairItem pi = a.items[it];
     const QueryDesc qd = a.queries[pi.query];

@@ -14,6 +14,9 @@
 
 namespace swmi {
 
+// the boundary rows below leave room for their writers' reach (kBndLead before column 0)
+static_assert(kBndLead == 64, "boundary padding of 128 entries per row assumes a lead of 64");
+
 namespace {
 
 // Rows per lane of the intra-task kernel for one search.  Its band is 64R query rows,
@@ -126,9 +129,8 @@ int choose_T(const std::vector<int64_t> &lens, const Knobs &k, const Occupancy &
   return best;
 }
 
-}  // namespace
-
-Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k,
+// One plan with the given knobs (make_plan below may plan twice).
+Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k,
                const Occupancy &occ) {
   Plan p;
   const int A = db.alphabet;
@@ -332,6 +334,8 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   // Segments of a split pair (and, for a two-pair item, of its second pair, which shares
   // the first one's bands and boundary rows) are appended consecutively, so segment j is
   // always claimed after segment j - 1.
+  // Each boundary row holds kBndLead entries before column 0 and at least 63 after column
+  // len - 1: its writer stores the columns -63 .. len + 62 its sweep passes through.
   auto push_segments = [&](const PairItem &it, const PairItem *second, int32_t S) {
     const int32_t nb = it.band1;
     const int64_t npad = (((int64_t)it.len + 63) / 64) * 64 + 128;
@@ -409,8 +413,9 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     // SIMD is bound by latency, not by its instruction count.)
     p.crit_R = k.crit_rows > 0 ? (int)k.crit_rows : kCritR;
     const int Rc = p.crit_R;
+    const double share = k.crit_share > 0 ? (double)k.crit_share / 100.0 : 0.5;
     if (S == s4 && p.R > Rc && k.intra_rows == 0 && cap == 0 &&
-        piped * 64 * 0.76 * t_step > 0.5 * t_search) {  // still critical with a SIMD per wave
+        piped * 64 * 0.76 * t_step > share * t_search) {  // still critical with a SIMD per wave
       const int32_t nbc = (int32_t)((lens[it.query] + 64 * Rc - 1) / (64 * Rc));
       const double piped_c = (double)(nc + (int64_t)kIntraLag * (nbc - 1));
       const double step_c = (7.5 * Rc + 14.0) / (7.5 * p.R + 14.0);
@@ -515,7 +520,7 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   // workspace sizes
   p.qbytes = qoff[nq];
   p.bnd16_slot = (size_t)db.max_ncols * 64 * (q2 ? 2 : 1);  // dwords
-  p.bnd32_stride = ((db.max_len + 128 + 63) / 64) * 64;
+  p.bnd32_stride = ((db.max_len + 128 + 63) / 64) * 64;  // >= kBndLead + max_len + 63
   p.bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * p.bnd32_stride;
   // saturated pairs: any database sequence, from either kernel, up to the list's capacity
   // (the pairs beyond it are marked in the scores and found by the overflow pass)
@@ -539,6 +544,25 @@ Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   p.off_cr = p.off_se + up(p.second.size() * sizeof(PairItem));
   p.off_pr = p.off_cr + up(p.crititems.size() * sizeof(PairItem));
   p.stage_bytes = p.off_pr + p.pairs.size() * sizeof(QueryPair) + 64;
+  return p;
+}
+
+}  // namespace
+
+// Four-wave main workgroups serve a throughput-bound search because one fits beside a
+// critical-pair workgroup; when no pair goes to that launch, eight-wave workgroups (one
+// per CU, the same two waves per SIMD) were faster (long-sequence mix on MI355X, the
+// 35000-residue query: 53.5 against 55.1 ms), so such a search is planned again with
+// them.
+Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k,
+               const Occupancy &occ) {
+  Plan p = plan_with(db, qoff, nq, k, occ);
+  if (k.main_waves == 0 && p.main_waves == kNarrowWaves && p.crititems.empty() &&
+      !p.longitems.empty()) {
+    Knobs k8 = k;
+    k8.main_waves = kIntraWaves;
+    return plan_with(db, qoff, nq, k8, occ);
+  }
   return p;
 }
 

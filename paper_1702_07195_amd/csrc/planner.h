@@ -43,7 +43,7 @@ struct DbView {
 struct Knobs {
   int64_t strip_rows = 0, grid_waves = 0, route_len = 0, wide_len = 0, max_segments = 0,
           intra_rows = 0, intra_pairs = 1, query_pairs = 1, main_waves = 0, mem_cap_mb = 0,
-          flag_cap = 0, crit_rows = 0;
+          flag_cap = 0, crit_rows = 0, crit_share = 0;
 };
 
 // Recompute-list entries when SW_KNOB_FLAG_CAP is 0 (pairs beyond them are found by the

@@ -113,6 +113,12 @@ constexpr int kCritR = 8;        // rows per lane of the critical-pair launch
 constexpr int kCritWaves = 4;    // waves per workgroup of the critical-pair launch
 constexpr int kNarrowWaves = 4;  // waves per workgroup of a throughput-bound main intra launch
 constexpr int kIntraLag = 3;   // chunks between consecutive bands (see kernels.hip)
+// Band-boundary rows (the bottom row of a band, read as the top row of the next) start
+// kBndLead entries into their buffers, and a buffer holds at least n + 127 entries past
+// its start for a sequence of n residues: the lane that writes the bottom row then stores
+// at every step, also for the columns -63 .. -1 and n .. n + 62 its sweep passes
+// through, which nothing reads.
+constexpr int kBndLead = 64;
 constexpr int kSpinLimit = 1 << 24;  // default polls before a wait between segments gives up
 
 }  // namespace swmi

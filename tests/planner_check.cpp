@@ -117,7 +117,8 @@ int64_t nbands_of(int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); }
 void check_items(const Plan &p, const Db &d, const std::vector<PairItem> &items,
                  const std::vector<PairItem> *second, int R, int64_t nq,
                  std::map<std::pair<int, int>, int> &cover, std::vector<int> &prog_writers,
-                 std::vector<int> &prog_readers, const char *list) {
+                 std::vector<int> &prog_readers,
+                 std::vector<std::pair<int64_t, int64_t>> &extents, const char *list) {
   const std::string L(list);
   std::map<int32_t, size_t> writer_at;  // progress counter -> index of its writer
   for (size_t i = 0; i < items.size(); ++i) {
@@ -139,13 +140,16 @@ void check_items(const Plan &p, const Db &d, const std::vector<PairItem> &items,
         CHECK(it.base >= 0 && last < d.view.packed_bytes, L + ": group residues");
       }
     }
-    const int64_t npad = ((int64_t)it.len + 63) / 64 * 64 + 128;
+    // A segment's bottom-row writer (lane 63 of the last band) stores at every step, the
+    // columns -63 .. len + 62, kBndLead entries into the boundary; the next segment reads
+    // columns 0 .. len - 1 of it.
+    const int64_t reach_lo = kBndLead - 63, reach_hi = kBndLead + (int64_t)it.len + 62;
     // segment chain
     CHECK(it.nsegments >= 1 && it.segment >= 0 && it.segment < it.nsegments, L + ": segment");
     if (it.segment == 0) {
       CHECK(it.xin < 0 && it.prog_in < 0 && it.band0 == 0, L + ": first segment reads nothing");
     } else {
-      CHECK(it.xin >= 0 && it.xin + npad <= p.xbnd_elems, L + ": boundary read range");
+      CHECK(it.xin >= 0 && it.xin + kBndLead + it.len <= p.xbnd_elems, L + ": boundary read range");
       CHECK(it.prog_in >= 0 && it.prog_in < p.nprog, L + ": progress counter read");
       auto w = writer_at.find(it.prog_in);
       CHECK(w != writer_at.end(), L + ": waits for a segment that is not earlier in the list");
@@ -156,7 +160,9 @@ void check_items(const Plan &p, const Db &d, const std::vector<PairItem> &items,
       prog_readers[(size_t)it.prog_in] += 1;
     }
     if (it.segment + 1 < it.nsegments) {
-      CHECK(it.xout >= 0 && it.xout + npad <= p.xbnd_elems, L + ": boundary write range");
+      CHECK(it.xout + reach_lo >= 0 && it.xout + reach_hi < p.xbnd_elems,
+            L + ": boundary write range");
+      extents.emplace_back(it.xout + reach_lo, it.xout + reach_hi);
       CHECK(it.prog_out >= 0 && it.prog_out < p.nprog, L + ": progress counter write");
       CHECK(!writer_at.count(it.prog_out), L + ": progress counter written twice");
       writer_at[it.prog_out] = i;
@@ -227,10 +233,15 @@ void check_plan(const Plan &p, const Db &d, const std::vector<int64_t> &qoff, in
   std::map<std::pair<int, int>, int> cover;
   std::vector<int> writers((size_t)std::max(0, p.nprog), 0), readers((size_t)std::max(0, p.nprog), 0);
   CHECK(p.second.size() == p.longitems.size(), "one second entry per main item");
-  check_items(p, d, p.longitems, &p.second, p.R, nq, cover, writers, readers, "main list");
+  std::vector<std::pair<int64_t, int64_t>> extents;  // boundary entries each writer touches
+  check_items(p, d, p.longitems, &p.second, p.R, nq, cover, writers, readers, extents,
+              "main list");
   CHECK(p.crititems.empty() || p.crit_R == 4 || p.crit_R == 8, "critical rows per lane");
   check_items(p, d, p.crititems, nullptr, p.crit_R ? p.crit_R : kCritR, nq, cover, writers,
-              readers, "critical list");
+              readers, extents, "critical list");
+  std::sort(extents.begin(), extents.end());
+  for (size_t k = 1; k < extents.size(); ++k)
+    CHECK(extents[k].first > extents[k - 1].second, "two segment boundaries overlap");
   for (int32_t k = 0; k < p.nprog; ++k)
     CHECK(writers[(size_t)k] == 1 && readers[(size_t)k] == 1, "each boundary written and read once");
   for (int64_t q = 0; q < nq; ++q) {
@@ -262,7 +273,8 @@ void check_plan(const Plan &p, const Db &d, const std::vector<int64_t> &qoff, in
   // workspace and staging
   CHECK(p.need_flagged >= 1, "recompute list");
   CHECK(p.bnd16_slot >= (size_t)v.max_ncols * 64 * (p.q2 ? 2 : 1), "inter-task boundary slot");
-  CHECK(p.bnd32_stride >= v.max_len + 128, "band buffer");
+  // a band buffer holds the bottom row's reach, kBndLead entries in (see above)
+  CHECK(p.bnd32_stride >= kBndLead + v.max_len + 63, "band buffer");
   CHECK(p.bnd32_slot >= (size_t)2 * kIntraWaves * p.bnd32_stride, "band ring");
   const size_t parts[][2] = {
       {0, (size_t)p.qbytes},
@@ -328,10 +340,13 @@ int main() {
     k.query_pairs = pick({1, 1, 0});
     k.main_waves = pick({0, 0, 4, 8});
     k.crit_rows = pick({0, 0, 4, 8});
+    k.crit_share = pick({0, 0, 10, 30, 100});
     g_case += " n=" + std::to_string(n) + " nq=" + std::to_string(nq) + " cu=" +
               std::to_string(num_cu);
     const Plan p = make_plan(d.view, qoff.data(), nq, k, occ);
     check_plan(p, d, qoff, nq);
+    if (k.main_waves == 0 && p.crititems.empty() && !p.longitems.empty())
+      CHECK(p.main_waves == 8, "four-wave main workgroups without a critical-pair launch");
     n_split += p.nprog > 0;
     n_crit += !p.crititems.empty();
     n_duo += p.nduos > 0;
