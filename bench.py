@@ -201,15 +201,9 @@ def run_searches(args, w, db, queries):
     outs = [torch.zeros(db.n_seqs, dtype=torch.int32, device=dev) for _ in queries]
     stream = torch.cuda.current_stream()
 
-    def step(per_query=None):
+    def step():
         for k, q in enumerate(queries):
-            if per_query is not None:
-                torch.cuda.synchronize()
-                t = time.perf_counter()
             h.search_async(q, sm, go, ge, outs[k], stream)
-            if per_query is not None:
-                torch.cuda.synchronize()
-                per_query[k] += time.perf_counter() - t
 
     if args.copy_mib > 0:
         n = args.copy_mib << 20
@@ -230,14 +224,17 @@ def run_searches(args, w, db, queries):
     timing = {k: h.timing_read(k) for k in (swmi.SW_KERNEL_INTER16, swmi.SW_KERNEL_INTRA_LONG,
                                              swmi.SW_KERNEL_RECOMPUTE)}
     h.timing_enable(False)
-    # each query alone (synchronised before and after), the median of `steps` runs
-    runs = []
-    for _ in range(max(1, args.steps)):
-        per_q = [0.0] * len(queries)
-        step(per_q)
-        runs.append(per_q)
-    per_query = {str(len(q)): round(len(q) * D / float(np.median([r[k] for r in runs])) / 1e9, 1)
-                 for k, q in enumerate(queries)}
+    # each query alone (synchronised before and after), the median of five runs
+    per_query = {}
+    for k, q in enumerate(queries):
+        ts = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            h.search_async(q, sm, go, ge, outs[k], stream)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        per_query[str(len(q))] = round(len(q) * D / float(np.median(ts)) / 1e9, 1)
     # per-launch algorithmic cells of each kernel, query by query (same plans as timed)
     stats = []
     for k, q in enumerate(queries):
