@@ -224,11 +224,14 @@ def run_searches(args, w, db, queries):
     timing = {k: h.timing_read(k) for k in (swmi.SW_KERNEL_INTER16, swmi.SW_KERNEL_INTRA_LONG,
                                              swmi.SW_KERNEL_RECOMPUTE)}
     h.timing_enable(False)
-    # each query alone (synchronised before and after), the median of five runs
+    # each query alone (synchronised before and after): one warm-up run, then the median
+    # of seven
     per_query = {}
     for k, q in enumerate(queries):
+        h.search_async(q, sm, go, ge, outs[k], stream)
+        torch.cuda.synchronize()
         ts = []
-        for _ in range(5):
+        for _ in range(7):
             torch.cuda.synchronize()
             t = time.perf_counter()
             h.search_async(q, sm, go, ge, outs[k], stream)

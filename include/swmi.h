@@ -382,6 +382,11 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
  *                          than this percentage of the whole intra-task search runs in
  *                          the critical-pair launch (1..100; 0 = automatic).  Scores are
  *                          the same.
+ *   SW_KNOB_INTRA_PRIO     1 (default): the intra-task kernel sweeps the critical pairs at
+ *                          the highest wave priority and the main launch's wide items (a
+ *                          whole workgroup per pair, the longest pairs) above its narrow
+ *                          ones; 0: every wave at the default priority.  Scores are the
+ *                          same.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -400,6 +405,7 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
 #define SW_KNOB_FLAG_CAP       15
 #define SW_KNOB_CRIT_ROWS      16
 #define SW_KNOB_CRIT_SHARE     17
+#define SW_KNOB_INTRA_PRIO     18
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

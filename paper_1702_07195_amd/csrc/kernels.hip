@@ -908,6 +908,11 @@ void k_intra32(IntraArgs a) {
   const int count = a.count_dev ? min(*a.count_dev, a.flag_cap) : a.count;
   const int n_wide = a.n_wide < count ? a.n_wide : count;
 
+  // Wide items hold the longest pairs, whose band pipelines set the critical path: their
+  // waves issue first on their SIMDs (critical-pair launch 3, main launch 2), and the
+  // narrow phase below, which fills the remaining issue slots, runs at priority 0.
+  if (a.wide_prio == 3) __builtin_amdgcn_s_setprio(3);
+  else if (a.wide_prio == 2) __builtin_amdgcn_s_setprio(2);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -955,6 +960,7 @@ void k_intra32(IntraArgs a) {
     }
   }
 
+  if (a.wide_prio) __builtin_amdgcn_s_setprio(0);
   int2 *ring = slot + (int64_t)w * 2 * a.bnd_stride;  // two band buffers per wave
   // Narrow phase.  The waves run independently, so the claim cannot go through LDS and a
   // barrier.  It must not sit in a lane-0-only branch either: the compiler may then split

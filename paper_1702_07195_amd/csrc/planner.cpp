@@ -382,6 +382,15 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   std::vector<Split> splits;
   std::vector<PairItem> singles;
   std::vector<bool> singles_pairable;
+  // The longest band pipeline of the split and critical pairs seen so far (wide pairs come
+  // longest first): an item whose paired time stays within 0.6 of it, or within a quarter
+  // of the estimated search time, is short enough to pair.  (Long-sequence mix on
+  // MI355X: the 5478-residue query, whose split pairs' pipelines take about 9 ms of a
+  // 10.4 ms search, 10.4 -> 10.2 ms with its longer narrow and wide pairs paired; the
+  // 35000-residue query keeps the quarter, since pairing its longest narrow items, 35
+  // bands swept by one wave, only lengthened the tail: 53.7 -> 55.9 ms.)
+  double max_path = 0;
+  auto pair_limit = [&]() { return std::max(0.25 * t_search, 0.6 * max_path); };
   for (auto &x : wide) {
     const PairItem &it = x.second;
     const int32_t nb = it.band1;
@@ -397,7 +406,7 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     S = std::max<int32_t>(1, std::min(S, nb));
     if (S == 1) {
       singles.push_back(it);
-      singles_pairable.push_back(pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= 0.25 * t_search));
+      singles_pairable.push_back(pair_all || (pair_wide && 1.45 * whole * 64 * t_step <= pair_limit()));
       continue;
     }
     // A pair whose full pipeline would outlast the search sets its critical path; with
@@ -440,9 +449,11 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
           }
           p.crititems.push_back(sg);
         }
+        max_path = std::max(max_path, piped_c * 64 * 0.76 * t_step * step_c);
         continue;
       }
     }
+    max_path = std::max(max_path, piped * 64 * t_step);
     const bool pairable = pair_all || (pair_mode == 1 && p.throughput_bound &&
                                        1.45 * piped * 64 * t_step <= 0.5 * t_search);
     splits.push_back({it, S, pairable});
@@ -465,7 +476,7 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   for (auto &x : narrow) {
     const PairItem &it = x.second;
     const double single = (double)it.band1 * (double)((it.len + 126) / 64) * 64 * t_step;
-    emit(it, pair_all || (pair_narrow && 1.45 * single <= 0.25 * t_search));
+    emit(it, pair_all || (pair_narrow && 1.45 * single <= pair_limit()));
   }
 
   const int64_t nitems16 = p.nitems16 = (int64_t)ninter * nunits;
