@@ -456,6 +456,37 @@ def test_critical_pairs(crit_rows):
     assert np.array_equal(got[idx], want)
 
 
+@pytest.mark.parametrize("share,prio", [(0, 0), (10, 1), (100, 1)])
+def test_critical_share_and_wave_priority(share, prio):
+    # the database of test_critical_pairs under other shares of the search time above
+    # which a split long pair goes to the critical-pair launch, with wave priorities on
+    # or off: scores must not change
+    rng = np.random.Generator(np.random.PCG64(5478))
+    lengths = np.concatenate([synth.lognormal_lengths(rng, 2000, 300, 0.8, 10, 8000),
+                              rng.integers(15000, 30000, 10)])
+    db = synth.db_from_lengths(rng, lengths)
+    q = synth.residues(rng, 5478)
+    knobs = (swmi.SW_KNOB_CRIT_SHARE, swmi.SW_KNOB_INTRA_PRIO)
+    old = [swmi.get_knob(k) for k in knobs]
+    cells = {}
+    try:
+        with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+            for s_, p_ in ((0, 1), (share, prio)):
+                swmi.set_knob(swmi.SW_KNOB_CRIT_SHARE, s_)
+                swmi.set_knob(swmi.SW_KNOB_INTRA_PRIO, p_)
+                _say(f"critical share {s_}, intra priority {p_}")
+                got = h.search(q, synth.BLOSUM62, 10, 2)
+                cells[(s_, p_)] = h.stats()["cells_crit"]
+    finally:
+        for k, v in zip(knobs, old):
+            swmi.set_knob(k, v)
+    if share == 10:
+        assert cells[(10, 1)] >= cells[(0, 1)]
+    idx = np.concatenate([np.arange(2000, 2010), rng.choice(2000, 200, replace=False)])
+    want = oracle.search(q, db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
+    assert np.array_equal(got[idx], want)
+
+
 @pytest.fixture(scope="module")
 def mixed_db():
     # lengths from empty to 3000 (narrow pairs below 1152, wide pairs above)
