@@ -140,6 +140,26 @@ def test_intra_pairs_knob_values():
         swmi.set_knob(swmi.SW_KNOB_INTRA_PAIRS, old)
 
 
+@pytest.mark.parametrize("name,bad,good,default", [
+    ("SW_KNOB_CRIT_SHARE", (-1, 101), (1, 50, 100, 0), 0),
+    ("SW_KNOB_INTRA_PRIO", (-1, 2), (0, 1), 1),
+    ("SW_KNOB_CRIT_ROWS", (2, 16, -8), (4, 8, 0), 0),
+])
+def test_critical_pair_knob_values(name, bad, good, default):
+    knob = getattr(swmi, name)
+    old = swmi.get_knob(knob)
+    assert old == default
+    try:
+        for v in bad:
+            with pytest.raises(swmi.SwError):
+                swmi.set_knob(knob, v)
+        for v in good:
+            swmi.set_knob(knob, v)
+            assert swmi.get_knob(knob) == v
+    finally:
+        swmi.set_knob(knob, old)
+
+
 def test_spin_limit_knob_range():
     old = swmi.get_knob(swmi.SW_KNOB_SPIN_LIMIT)
     try:
