@@ -40,7 +40,7 @@ def _lines(workload):
             if not line.strip() or line.startswith("#"):
                 continue
             w = line.split()
-            if w[0] != workload:
+            if len(w) != 12 or w[0] != workload:  # (a line still being written is skipped)
                 continue
             out.append(dict(matrix=w[1], go=int(w[2]), ge=int(w[3]), query=int(w[4]),
                             qlen=int(w[5]), begin=int(w[6]), end=int(w[7]), sha=w[8],
