@@ -305,7 +305,7 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 
 /*
  * sw_search_stats -- how the latest search enqueued on the handle was laid out, written
- * to values[0 .. min(n, 9)) (algorithmic cells count query rows x unpadded residues):
+ * to values[0 .. min(n, 10)) (algorithmic cells count query rows x unpadded residues):
  *   SW_ST_CELLS_INTER16  cells of the packed-int16 inter-task launch
  *   SW_ST_CELLS_INTRA32  int32 cells of the main intra-task launch
  *   SW_ST_CELLS_INTRA16  cells of its two-pairs-per-wave (packed int16) items
@@ -315,6 +315,8 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
  *   SW_ST_ROUTED_GROUPS  database groups routed to the intra-task kernel
  *   SW_ST_STRIP_ROWS     strip rows of the inter-task launch
  *   SW_ST_QUERY_PAIRS    1 if the inter-task launch ran two queries per lane
+ *   SW_ST_BIG_WAVES      waves of that launch with boundary slots for the widest groups,
+ *                        when the others' slots are narrower (0: one slot width)
  * Errors: SW_ENODB, SW_EINVAL (NULL values or n < 0).
  */
 #define SW_ST_CELLS_INTER16   0
@@ -326,7 +328,8 @@ int sw_timing_read_kernel(const sw_db *db, int32_t kernel, int64_t *launches,
 #define SW_ST_ROUTED_GROUPS   6
 #define SW_ST_STRIP_ROWS      7
 #define SW_ST_QUERY_PAIRS     8
-#define SW_SEARCH_NSTATS      9
+#define SW_ST_BIG_WAVES       9
+#define SW_SEARCH_NSTATS      10
 int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
 
 /*

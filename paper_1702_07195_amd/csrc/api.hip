@@ -367,7 +367,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   grow(w->qp8, (size_t)std::max<int64_t>(16, p.qp8_elems));
   grow(w->ctr, sizeof(Counters));
   grow(w->flagged, need_flagged * sizeof(PairItem));
-  grow(w->bnd16, std::max<size_t>(1, (size_t)p.grid16 * bnd16_slot) * 4);
+  grow(w->bnd16, std::max<size_t>(1, bnd16_words(p)) * 4);
   grow(w->bnd32, std::max<size_t>(1, (size_t)grid32 * bnd32_slot) * 8);
   grow(w->xbnd, (size_t)std::max<int64_t>(1, p.xbnd_elems) * 8);
   // per segment boundary: progress, finished flag (both cleared per search), maximum
@@ -534,6 +534,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.ctr = ctr;
       ia.bnd = (uint32_t *)w->bnd16.ptr;
       ia.bnd_slot_words = (int64_t)bnd16_slot;
+      ia.small_slot_words = (int64_t)p.bnd16_small;
+      ia.big_waves = p.big_waves;
+      ia.wide_items = (int32_t)p.wide_items;
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
       ia.prio_cols = inter_beside_intra

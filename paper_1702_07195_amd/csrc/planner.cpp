@@ -530,7 +530,39 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
 
   // workspace sizes
   p.qbytes = qoff[nq];
-  p.bnd16_slot = (size_t)db.max_ncols * 64 * (q2 ? 2 : 1);  // dwords
+  // Inter-task boundary slots, one per persistent wave, as wide as the widest group the
+  // kernel gets.  For the two-query kernel (two dwords per lane and column), when one
+  // such slot per wave would pass kSlotBudget, the widest groups -- those holding at most
+  // a sixteenth of the inter-task work -- are left to an eighth of the waves, which take
+  // them first (they are the longest items) and keep full-width slots; the other waves'
+  // slots only need the width of the widest remaining group.  (A 64-query batch over the
+  // 6e6-sequence database: 12.6 GB of slots as one class, about 3.4 GB as two.)
+  int32_t inter_cols = 0;
+  for (int32_t g = 0; g < p.ngroups_inter; ++g) inter_cols = std::max(inter_cols, db.groups[g].ncols);
+  const size_t words_per_col = 64 * (q2 ? 2 : 1);
+  p.bnd16_slot = std::max<size_t>(1, (size_t)inter_cols * words_per_col);  // dwords
+  p.bnd16_small = p.bnd16_slot;
+  p.big_waves = 0;
+  p.wide_items = 0;
+  constexpr size_t kSlotBudget = size_t(1) << 30;
+  if (q2 && p.grid16 >= 64 && (size_t)p.grid16 * p.bnd16_slot * 4 > kSlotBudget) {
+    double total = 0;
+    for (int32_t g = 0; g < p.ngroups_inter; ++g) total += (double)db.groups[g].ncols;
+    int32_t nwide = 0;  // widest groups taken by the big-slot waves
+    double wide_work = 0;
+    for (int32_t g = p.ngroups_inter - 1; g > 0; --g) {
+      if (wide_work + db.groups[g].ncols > total / 16) break;
+      wide_work += db.groups[g].ncols;
+      ++nwide;
+    }
+    const int32_t small_cols = p.ngroups_inter - nwide > 0 ? db.groups[p.ngroups_inter - 1 - nwide].ncols : 0;
+    if (nwide > 0 && small_cols < inter_cols) {
+      p.big_waves = std::max(1, p.grid16 / 8);
+      p.wide_items = (int64_t)nwide * nunits;
+      p.bnd16_small = std::max<size_t>(1, (size_t)small_cols * words_per_col);
+    }
+  }
+  p.stats[SW_ST_BIG_WAVES] = p.big_waves;
   p.bnd32_stride = ((db.max_len + 128 + 63) / 64) * 64;  // >= kBndLead + max_len + 63
   p.bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * p.bnd32_stride;
   // saturated pairs: any database sequence, from either kernel, up to the list's capacity
@@ -542,7 +574,7 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
                  sizeof(Counters) + p.pairs.size() * sizeof(QueryPair) +
                  p.need_flagged * sizeof(PairItem) +
                  (2 * p.longitems.size() + p.crititems.size()) * sizeof(PairItem) +
-                 (size_t)p.grid16 * p.bnd16_slot * 4 + (size_t)p.grid32 * p.bnd32_slot * 8 +
+                 bnd16_words(p) * 4 + (size_t)p.grid32 * p.bnd32_slot * 8 +
                  (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
   // small per-call inputs, staged in one block (64-byte aligned parts)
   auto up = [](size_t x) { return (x + 63) & ~size_t(63); };

@@ -2,6 +2,7 @@
 // builds with a host compiler too.
 #pragma once
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <vector>
@@ -91,7 +92,13 @@ struct Plan {
   int64_t stats[SW_SEARCH_NSTATS] = {};  // see sw_search_stats
   // workspace sizes
   int64_t qbytes = 0;         // concatenated query residues
-  size_t bnd16_slot = 0;      // dwords per inter-task wave's boundary slot
+  size_t bnd16_slot = 0;      // dwords per inter-task wave's boundary slot (the widest group)
+  // Two-query kernel on a database whose widest groups would make one slot per wave too
+  // large: the first big_waves waves have slots of bnd16_slot dwords and take the
+  // wide_items widest items first; the other waves' slots have bnd16_small dwords.
+  int32_t big_waves = 0;
+  int64_t wide_items = 0;
+  size_t bnd16_small = 0;
   int32_t bnd32_stride = 0;   // int2 elements per intra-task band buffer
   size_t bnd32_slot = 0;      // int2 elements per intra-task workgroup's band ring
   size_t need_flagged = 0;    // recompute-list entries
@@ -100,6 +107,13 @@ struct Plan {
   size_t off_qoff = 0, off_qd = 0, off_mx = 0, off_qo = 0, off_li = 0, off_se = 0,
          off_cr = 0, off_pr = 0, stage_bytes = 0;
 };
+
+// Dwords of all inter-task boundary slots: big_waves slots of bnd16_slot, then the others
+// of bnd16_small.
+inline size_t bnd16_words(const Plan &p) {
+  const size_t big = (size_t)std::max(0, std::min(p.big_waves, p.grid16));
+  return big * p.bnd16_slot + ((size_t)std::max(0, p.grid16) - big) * p.bnd16_small;
+}
 
 // Plan a search of nq queries (offsets qoff[0..nq]) against the database.
 Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k,

@@ -62,9 +62,10 @@ SW_ST_MAIN_WAVES = 5
 SW_ST_ROUTED_GROUPS = 6
 SW_ST_STRIP_ROWS = 7
 SW_ST_QUERY_PAIRS = 8
-SW_SEARCH_NSTATS = 9
+SW_ST_BIG_WAVES = 9
+SW_SEARCH_NSTATS = 10
 SW_ST_NAMES = ("cells_inter16", "cells_intra32", "cells_intra16", "cells_crit", "intra_rows",
-               "main_waves", "routed_groups", "strip_rows", "query_pairs")
+               "main_waves", "routed_groups", "strip_rows", "query_pairs", "big_waves")
 
 # sw_server_counters indices
 SW_SC_LAUNCHES = 0

@@ -272,7 +272,26 @@ void check_plan(const Plan &p, const Db &d, const std::vector<int64_t> &qoff, in
   CHECK(p.R == 2 || p.R == 4 || p.R == 8 || p.R == 16, "rows per lane");
   // workspace and staging
   CHECK(p.need_flagged >= 1, "recompute list");
-  CHECK(p.bnd16_slot >= (size_t)v.max_ncols * 64 * (p.q2 ? 2 : 1), "inter-task boundary slot");
+  // inter-task boundary slots: every item's group fits the slot of every wave that may
+  // take it (items [0, wide_items) only the big-slot waves, the others every wave)
+  {
+    const size_t wpc = 64 * (p.q2 ? 2 : 1);
+    int32_t inter_cols = 0;
+    for (int32_t g = 0; g < p.ngroups_inter; ++g) inter_cols = std::max(inter_cols, v.groups[g].ncols);
+    CHECK(p.bnd16_slot >= (size_t)inter_cols * wpc, "inter-task boundary slot");
+    if (p.big_waves > 0) {
+      CHECK(p.q2 && p.big_waves <= p.grid16 && p.wide_items > 0 && p.wide_items < p.nitems16 &&
+                p.wide_items % units == 0, "two classes of boundary slots");
+      const int32_t g_small = p.ngroups_inter - 1 - (int32_t)(p.wide_items / units);
+      for (int32_t g = 0; g <= g_small; ++g)
+        CHECK((size_t)v.groups[g].ncols * wpc <= p.bnd16_small, "a group wider than the small slots");
+      CHECK(bnd16_words(p) == (size_t)p.big_waves * p.bnd16_slot +
+                                  (size_t)(p.grid16 - p.big_waves) * p.bnd16_small,
+            "boundary slot words");
+    } else {
+      CHECK(p.wide_items == 0 && p.bnd16_small == p.bnd16_slot, "one class of boundary slots");
+    }
+  }
   // a band buffer holds the bottom row's reach, kBndLead entries in (see above)
   CHECK(p.bnd32_stride >= kBndLead + v.max_len + 63, "band buffer");
   CHECK(p.bnd32_slot >= (size_t)2 * kIntraWaves * p.bnd32_stride, "band ring");
@@ -308,7 +327,7 @@ int main() {
   };
   std::lognormal_distribution<double> logn(std::log(200.0), 0.9);
   const int cases = 3000;
-  int64_t n_split = 0, n_crit = 0, n_duo = 0, n_routed = 0, n_q2 = 0;
+  int64_t n_split = 0, n_crit = 0, n_duo = 0, n_routed = 0, n_q2 = 0, n_slots2 = 0;
   for (int c = 0; c < cases; ++c) {
     g_case = "case " + std::to_string(c);
     const int num_cu = (int)pick({1, 4, 16, 256});
@@ -352,13 +371,32 @@ int main() {
     n_duo += p.nduos > 0;
     n_routed += p.ngroups_inter < d.view.ngroups;
     n_q2 += p.q2;
+    n_slots2 += p.big_waves > 0;
+  }
+  // batches of 64 queries against databases that fill the device: the two-query kernel's
+  // boundary slots then come in two classes
+  for (int c = 0; c < 6; ++c) {
+    g_case = "batch case " + std::to_string(c);
+    const int64_t n = (int64_t)pick({6000, 12000, 20000});
+    std::vector<int64_t> len((size_t)n);
+    for (auto &x : len) x = std::max<int64_t>(10, std::min<int64_t>(8000, (int64_t)logn(rng)));
+    Db d = make_db(len, 8192, 256, 24);
+    std::vector<int64_t> qoff(1, 0);
+    for (int q = 0; q < 64; ++q) qoff.push_back(qoff.back() + 50 + (int64_t)(rng() % 4951));
+    Knobs k;
+    k.strip_rows = pick({0, 28, 24});
+    const Plan p = make_plan(d.view, qoff.data(), 64, k, occ);
+    check_plan(p, d, qoff, 64);
+    n_q2 += p.q2;
+    n_slots2 += p.big_waves > 0;
   }
   // the random cases must reach every kind of item
-  if (!n_split || !n_crit || !n_duo || !n_routed || !n_q2 || !n_split_duos)
+  if (!n_split || !n_crit || !n_duo || !n_routed || !n_q2 || !n_split_duos || !n_slots2)
     fail("a kind of item never planned");
   std::printf("planner ok: %d cases (split pairs %lld, critical pairs %lld, two-pair items "
-              "%lld, split two-pair segments %lld, routed groups %lld, query pairs %lld)\n", cases,
+              "%lld, split two-pair segments %lld, routed groups %lld, query pairs %lld, two "
+              "classes of boundary slots %lld)\n", cases,
               (long long)n_split, (long long)n_crit, (long long)n_duo, (long long)n_split_duos,
-              (long long)n_routed, (long long)n_q2);
+              (long long)n_routed, (long long)n_q2, (long long)n_slots2);
   return 0;
 }

@@ -151,3 +151,29 @@ def test_pair_only_height_on_a_single_query(pdb, phandle):
     with _Knobs(strip_rows=28, route_len=1 << 30):
         got = phandle.search(q, synth.BLOSUM62, 10, 2)
     assert np.array_equal(got, oracle.search(q, pdb.residues, pdb.offsets, synth.BLOSUM62, 10, 2))
+
+
+def test_two_widths_of_boundary_slots():
+    # 64 queries against a database whose groups fill the device many times over: one
+    # boundary slot per wave as wide as the widest group would pass the slot budget, so the
+    # widest groups go to an eighth of the waves (full-width slots) and the others' slots
+    # are as wide as the remaining groups.  Scores must equal those of one query per lane
+    # (every score) and the oracle's (the widest sequences and a sample of the others).
+    rng = np.random.Generator(np.random.PCG64(6464))
+    lengths = synth.lognormal_lengths(rng, 60000, 200, 0.8, 10, 8000)
+    db = synth.db_from_lengths(rng, lengths)
+    qs = [synth.residues(rng, int(m)) for m in rng.integers(30, 121, size=64)]
+    with swmi.sw_db_load(db.residues, db.offsets, ALPHA) as h:
+        _say("64 queries, two classes of boundary slots")
+        got = h.search_batch(qs, synth.BLOSUM62, 10, 2)
+        st = h.stats()
+        with _Knobs(query_pairs=0):
+            _say("the same batch, one query per lane")
+            single = h.search_batch(qs, synth.BLOSUM62, 10, 2)
+    assert st["query_pairs"] == 1 and st["big_waves"] > 0, st
+    assert np.array_equal(got, single)
+    order = np.argsort(lengths, kind="stable")
+    idx = np.concatenate([order[-640:], rng.choice(order[:-640], 300, replace=False)])
+    for k in range(0, len(qs), 7):
+        want = oracle.search(qs[k], db.residues, db.offsets, synth.BLOSUM62, 10, 2, index=idx)
+        assert np.array_equal(got[k][idx], want), k
