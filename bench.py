@@ -606,7 +606,7 @@ def main():
         print(json.dumps(calibrate()), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
               "across GPUs the database would be sharded by sequence groups, each GPU "
               "searching its shard and the scores gathered", file=sys.stderr)
         sys.exit(2)
