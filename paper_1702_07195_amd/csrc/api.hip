@@ -562,6 +562,9 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       ia.ctr = ctr;
       ia.bnd = (uint32_t *)w->bnd16.ptr;
       ia.bnd_slot_words = (int64_t)bnd16_slot;
+      ia.small_slot_words = (int64_t)p.bnd16_small;
+      ia.big_waves = p.big_waves;
+      ia.wide_items = (int32_t)p.wide_items;
       ia.recompute_all = g_knob_recompute_all.load() ? 1 : 0;
       ia.nitems = (int32_t)nitems16;
       ia.prio_cols = inter_beside_intra

@@ -307,19 +307,36 @@ void k_inter16(InterArgs a) {
   constexpr int RS = Inter16Lds<T>::RS;
   __shared__ __attribute__((aligned(16))) uint8_t lds[Inter16Lds<T>::bytes];
   const int lane = threadIdx.x;
-  uint32_t *bnd = a.bnd + (int64_t)blockIdx.x * a.bnd_slot_words + lane;
+  // The first big_waves waves have full-width boundary slots and take the widest items
+  // [0, wide_items) first; every wave then takes the others in order from wide_items.
+  const int wave = (int)blockIdx.x;
+  const bool big = wave < a.big_waves;
+  uint32_t *bnd = a.bnd + lane +
+                  (big ? (int64_t)wave * a.bnd_slot_words
+                       : (int64_t)a.big_waves * a.bnd_slot_words +
+                             (int64_t)(wave - a.big_waves) * a.small_slot_words);
   const uint32_t goe2 = (uint32_t)a.goe * 0x10001u;
   const uint32_t ge2 = (uint32_t)a.ge * 0x10001u;
   __shared__ int s_item;
+  bool wide_left = big && a.wide_items > 0;
 
   for (;;) {
     // claim the next item: lane 0 takes it, the (single-wave) workgroup barrier makes the
     // value visible to every lane and keeps the wave converged around the claim
     __syncthreads();
-    if (lane == 0) s_item = atomicAdd(&a.ctr->inter_next, 1);
+    if (lane == 0) {
+      int it = -1;
+      if (wide_left) {
+        it = atomicAdd(&a.ctr->inter_wide, 1);
+        if (it >= a.wide_items) it = -1;
+      }
+      if (it < 0) it = a.wide_items + atomicAdd(&a.ctr->inter_next, 1);
+      s_item = it;
+    }
     __syncthreads();
     const int item = s_item;
     if (item >= a.nitems) break;
+    wide_left = wide_left && item < a.wide_items;
     const int g = a.ngroups - 1 - item / a.nqueries;  // longest groups first
     const int qi = a.qorder[item % a.nqueries];       // then longest queries first
     const GroupDesc gd = a.groups[g];

@@ -531,12 +531,13 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   // workspace sizes
   p.qbytes = qoff[nq];
   // Inter-task boundary slots, one per persistent wave, as wide as the widest group the
-  // kernel gets.  For the two-query kernel (two dwords per lane and column), when one
+  // kernel gets (one dword per lane and column, two in the two-query kernel).  When one
   // such slot per wave would pass kSlotBudget, the widest groups -- those holding at most
   // a sixteenth of the inter-task work -- are left to an eighth of the waves, which take
   // them first (they are the longest items) and keep full-width slots; the other waves'
-  // slots only need the width of the widest remaining group.  (A 64-query batch over the
-  // 6e6-sequence database: 12.6 GB of slots as one class, about 3.4 GB as two.)
+  // slots only need the width of the widest remaining group.  (The 6e6-sequence database:
+  // 6.3 GB of slots as one class for one query per lane and 12.6 GB for a 64-query
+  // batch, about 1.7 and 3.4 GB as two.)
   int32_t inter_cols = 0;
   for (int32_t g = 0; g < p.ngroups_inter; ++g) inter_cols = std::max(inter_cols, db.groups[g].ncols);
   const size_t words_per_col = 64 * (q2 ? 2 : 1);
@@ -545,7 +546,7 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   p.big_waves = 0;
   p.wide_items = 0;
   constexpr size_t kSlotBudget = size_t(1) << 30;
-  if (q2 && p.grid16 >= 64 && (size_t)p.grid16 * p.bnd16_slot * 4 > kSlotBudget) {
+  if (p.grid16 >= 64 && (size_t)p.grid16 * p.bnd16_slot * 4 > kSlotBudget) {
     double total = 0;
     for (int32_t g = 0; g < p.ngroups_inter; ++g) total += (double)db.groups[g].ncols;
     int32_t nwide = 0;  // widest groups taken by the big-slot waves

@@ -93,9 +93,9 @@ struct Plan {
   // workspace sizes
   int64_t qbytes = 0;         // concatenated query residues
   size_t bnd16_slot = 0;      // dwords per inter-task wave's boundary slot (the widest group)
-  // Two-query kernel on a database whose widest groups would make one slot per wave too
-  // large: the first big_waves waves have slots of bnd16_slot dwords and take the
-  // wide_items widest items first; the other waves' slots have bnd16_small dwords.
+  // On a database whose widest groups would make one slot per wave too large: the first
+  // big_waves waves have slots of bnd16_slot dwords and take the wide_items widest items
+  // first; the other waves' slots have bnd16_small dwords.
   int32_t big_waves = 0;
   int64_t wide_items = 0;
   size_t bnd16_small = 0;

@@ -26,7 +26,12 @@ struct InterArgs {
   PairItem *flagged;
   Counters *ctr;
   uint32_t *bnd;             // boundary scratch, one slot per persistent wave
-  int64_t bnd_slot_words;    // dwords per slot
+  int64_t bnd_slot_words;    // dwords per slot of the first big_waves waves (>= 64 * widest
+                             // group's columns)
+  int64_t small_slot_words;  // dwords per slot of the other waves (>= 64 * the columns of
+                             // every item from wide_items on)
+  int32_t big_waves;         // waves with full-width slots; they take items [0, wide_items)
+  int32_t wide_items;        // the widest groups' items (0: one slot class, one counter)
   int32_t recompute_all;
   int32_t nitems;            // ngroups * nqueries
   int32_t prio_cols;         // items of groups at least this wide run at raised wave priority

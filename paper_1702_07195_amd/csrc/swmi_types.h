@@ -76,7 +76,7 @@ struct Counters {
   int32_t crit_next;      // next wide item of the critical-pair list
   int32_t crit_narrow;    // (unused: that list has no narrow items)
   int32_t rescan_next;    // next chunk of the pass over an overflowed recompute list
-  int32_t inter_wide;     // next of the widest inter-task items (big-slot waves only)
+  int32_t inter_wide;     // next of the widest inter-task items (full-width-slot waves)
 };
 
 // Two queries sharing the lanes of the two-query inter-task kernel (batched searches).

@@ -280,7 +280,7 @@ void check_plan(const Plan &p, const Db &d, const std::vector<int64_t> &qoff, in
     for (int32_t g = 0; g < p.ngroups_inter; ++g) inter_cols = std::max(inter_cols, v.groups[g].ncols);
     CHECK(p.bnd16_slot >= (size_t)inter_cols * wpc, "inter-task boundary slot");
     if (p.big_waves > 0) {
-      CHECK(p.q2 && p.big_waves <= p.grid16 && p.wide_items > 0 && p.wide_items < p.nitems16 &&
+      CHECK(p.big_waves <= p.grid16 && p.wide_items > 0 && p.wide_items < p.nitems16 &&
                 p.wide_items % units == 0, "two classes of boundary slots");
       const int32_t g_small = p.ngroups_inter - 1 - (int32_t)(p.wide_items / units);
       for (int32_t g = 0; g <= g_small; ++g)
