@@ -390,6 +390,11 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
  *                          whole workgroup per pair, the longest pairs) above its narrow
  *                          ones; 0: every wave at the default priority.  Scores are the
  *                          same.
+ *   SW_KNOB_INTRA_CHAIN    1 (default): a pair the intra-task kernel sweeps with one wave
+ *                          (at least 192 residues, two or more query bands) runs its
+ *                          bands back to back as one stream instead of one band after
+ *                          another, which saves each band's fill and drain; 0: one band
+ *                          after another.  Scores are the same.
  */
 #define SW_KNOB_INTRA_MIN_LEN  1
 #define SW_KNOB_RECOMPUTE_ALL  2
@@ -409,6 +414,7 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
 #define SW_KNOB_CRIT_ROWS      16
 #define SW_KNOB_CRIT_SHARE     17
 #define SW_KNOB_INTRA_PRIO     18
+#define SW_KNOB_INTRA_CHAIN    19
 int sw_set_knob(int32_t knob, int64_t value);
 int64_t sw_get_knob(int32_t knob);
 

@@ -44,6 +44,7 @@ std::atomic<int64_t> g_knob_flag_cap{0};
 std::atomic<int64_t> g_knob_crit_rows{0};
 std::atomic<int64_t> g_knob_crit_share{0};
 std::atomic<int64_t> g_knob_intra_prio{1};
+std::atomic<int64_t> g_knob_intra_chain{1};
 
 // Group width from which an inter-task item runs at raised wave priority: a wave sweeping
 // a group of ncols columns spends about 64 * ncols * waves / residues of the launch's
@@ -462,6 +463,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
     ia.flag_cap = (int32_t)need_flagged;
     ia.wide_prio = g_knob_intra_prio.load() ? 2 : 0;
+    ia.chain = g_knob_intra_chain.load() ? 1 : 0;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
     hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, w->aux));
@@ -504,6 +506,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ca.spin_limit = g_knob_spin_limit.load() > 0 ? (int32_t)g_knob_spin_limit.load() : kSpinLimit;
     ca.flag_cap = (int32_t)need_flagged;
     ca.wide_prio = g_knob_intra_prio.load() ? 3 : 0;
+    ca.chain = g_knob_intra_chain.load() ? 1 : 0;
     hip_check(launch_intra32(ca, p.crit_R, kCritWaves, p.grid_crit, w->crit));
     hip_check(hipEventRecord(w->join_crit, w->crit));
   }
@@ -613,6 +616,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.spin_limit = kSpinLimit;
     ra.flag_cap = (int32_t)need_flagged;
     ra.wide_prio = 0;
+    ra.chain = g_knob_intra_chain.load() ? 1 : 0;
     if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
     hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
     if (timed && p.grid_re > 0) {
@@ -701,6 +705,10 @@ SW_API int sw_set_knob(int32_t knob, int64_t value) {
       if (value != 0 && value != 1) return SW_EINVAL;
       g_knob_intra_prio = value;
       return SW_OK;
+    case SW_KNOB_INTRA_CHAIN:
+      if (value != 0 && value != 1) return SW_EINVAL;
+      g_knob_intra_chain = value;
+      return SW_OK;
     default: return SW_EINVAL;
   }
 }
@@ -725,6 +733,7 @@ SW_API int64_t sw_get_knob(int32_t knob) {
     case SW_KNOB_CRIT_ROWS: return g_knob_crit_rows.load();
     case SW_KNOB_CRIT_SHARE: return g_knob_crit_share.load();
     case SW_KNOB_INTRA_PRIO: return g_knob_intra_prio.load();
+    case SW_KNOB_INTRA_CHAIN: return g_knob_intra_chain.load();
     default: return SW_EINVAL;
   }
 }

@@ -20,6 +20,9 @@
 //               every pair of a database too small to fill the GPU, and for the exact
 //               recompute of saturated alignments (Section 4.2): int32, or two pairs
 //               per wave in packed int16 with the same saturation rule.
+#include <algorithm>
+#include <atomic>
+
 #include "swmi_internal.h"
 
 namespace swmi {
@@ -454,9 +457,9 @@ __device__ __forceinline__ int wave_shr1(int src, int lane0_value) {
 // IntraBuf<R>::n steps, already requested (cfar is the residue code of the last of them).
 // One lane's R int8 profile rows for one code (R = 2, 4, 8 or 16: one 2-, 4-, 8- or
 // 16-byte load).
-// Profile-row buffers per lane (prefetch distance + 1): 8 where the registers allow (for
-// the latency-bound long pairs of the 8-row launch the deeper prefetch was about 5%
-// faster); the two-pair path at R = 16, which holds two sets, keeps kIntraBuf.
+// Profile-row buffers per lane (prefetch distance + 1): 8 (for the latency-bound long
+// pairs of the 8-row launch the deeper prefetch was about 5% faster than 4); the two-pair
+// path at R = 16, which holds two sets, keeps kIntraBuf (8 measured no faster there).
 template <int R> struct IntraBuf { static constexpr int n = 8; };
 template <int R> struct IntraBuf16 { static constexpr int n = R <= 8 ? 8 : kIntraBuf; };
 
@@ -544,22 +547,27 @@ __device__ __forceinline__ void band_start(BandLane<R> &L, int lane, int n, cons
 // diagonal sum H(i-1, j-1) + SM is formed before the row above is overwritten, which
 // lets H stay in place from step to step.  Lane 63 (when `store_bot`) stores the bottom
 // row's (H, F) of column s - 63 at every step.
-template <int R>
-__device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const IntraArgs &a,
-                                           int lane, int k, int n, const int2 *top,
-                                           bool has_top, int2 *bot, bool store_bot,
-                                           const uint8_t *resbase, int cs,
-                                           const uint8_t *pbase, uint32_t lane_off,
-                                           uint32_t pstride) {
+//
+// The 64 steps themselves are sweep_chunk: `bchunk` is where lane 63 stores step i's
+// bottom row (bchunk[i]), rq_next the next chunk's code offsets.  With WRAP (chained
+// bands, below) the lane that enters a new band at step i (lane i - w0) first clears its
+// rows' H and E and its diagonal: the band's left boundary.
+template <int R, bool WRAP>
+__device__ __forceinline__ void sweep_chunk(BandLane<R> &L, int32_t &vmax, const IntraArgs &a,
+                                            int lane, int2 *bchunk, bool store_bot,
+                                            int rq_next, const uint8_t *pbase,
+                                            uint32_t lane_off, int w0) {
   constexpr int NB = IntraBuf<R>::n;
   constexpr int D = NB - 1;  // prefetch distance in steps
   static_assert(64 % NB == 0 && NB >= 2, "a chunk must hold whole groups of steps");
-  const int col_next = 64 * (k + 1) + lane;
-  const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
-  const int rq_next = code_off(resbase, cs, col_next, n, pstride);
-  int2 *bchunk = bot + (64 * k - 63);
 
   auto step = [&](const int i, const int cin, const RowBuf<R> &P, RowBuf<R> &Pfar) {
+    if (WRAP && (unsigned)(i - w0) < 64u) {  // (uniform)
+      const int keep = lane == i - w0 ? 0 : -1;
+#pragma unroll
+      for (int r = 0; r < R; ++r) { L.H[r] &= keep; L.E[r] &= keep; }
+      L.hdiag &= keep;
+    }
     // request the rows of step s + D
     L.cfar = wave_shr1(L.cfar, cin);
     load_rows(Pfar, pbase, (uint32_t)L.cfar + lane_off);
@@ -585,6 +593,12 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
     L.hbot = h;
     L.fbot = f;
     if (store_bot) bchunk[i] = make_int2(h, f);
+    // The running maximum is brought up to date at every step.  Left free, the compiler
+    // defers the maxima of a whole group of steps to the group's end, which keeps every
+    // H of the group live (about 80 more VGPRs at R = 16) and leaves no room to clear a
+    // lane's rows in place.  (An empty asm statement without side effects: no instruction
+    // is emitted, and the scheduler may still interleave neighbouring steps.)
+    asm("" : "+v"(vmax));
   };
 #pragma unroll 1
   for (int i = 0; i < 64 - NB; i += NB) {
@@ -597,6 +611,20 @@ __device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const 
     step(64 - NB + u,
          u == 0 ? __builtin_amdgcn_readlane(L.rq, 63) : __builtin_amdgcn_readlane(rq_next, u - 1),
          L.P[u], L.P[(u + NB - 1) % NB]);
+}
+
+template <int R>
+__device__ __forceinline__ void band_chunk(BandLane<R> &L, int32_t &vmax, const IntraArgs &a,
+                                           int lane, int k, int n, const int2 *top,
+                                           bool has_top, int2 *bot, bool store_bot,
+                                           const uint8_t *resbase, int cs,
+                                           const uint8_t *pbase, uint32_t lane_off,
+                                           uint32_t pstride) {
+  const int col_next = 64 * (k + 1) + lane;
+  const int2 tq_next = (has_top && col_next < n) ? top[col_next] : make_int2(0, 0);
+  const int rq_next = code_off(resbase, cs, col_next, n, pstride);
+  sweep_chunk<R, false>(L, vmax, a, lane, bot + (64 * k - 63), store_bot, rq_next, pbase,
+                        lane_off, 0);
   L.tq = tq_next;
   L.rq = rq_next;
 }
@@ -654,25 +682,24 @@ __device__ __forceinline__ void band_start16(BandLane16<R> &L, int lane, int nA,
 
 // Chunk k of a band sweep for both pairs (nA >= nB; B's columns past nB carry the
 // padding code).  Same schedule as band_chunk.
-template <int R>
-__device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, uint32_t goe2,
-                                             uint32_t ge2, int lane, int k, int nA, int nB,
-                                             const int2 *top, bool has_top, int2 *bot,
-                                             bool store_bot, const uint8_t *resA, int csA,
-                                             const uint8_t *resB, int csB,
-                                             const uint8_t *pbase, uint32_t lane_off,
-                                             uint32_t pstride) {
+template <int R, bool WRAP>
+__device__ __forceinline__ void sweep_chunk16(BandLane16<R> &L, uint32_t &vmax, uint32_t goe2,
+                                              uint32_t ge2, int lane, int2 *bchunk,
+                                              bool store_bot, int rqA_next, int rqB_next,
+                                              const uint8_t *pbase, uint32_t lane_off,
+                                              int w0) {
   constexpr int NB = IntraBuf16<R>::n;
   constexpr int D = NB - 1;
   static_assert(64 % NB == 0 && NB >= 2, "a chunk must hold whole groups of steps");
-  const int col_next = 64 * (k + 1) + lane;
-  const int2 tq_next = (has_top && col_next < nA) ? top[col_next] : make_int2(0, 0);
-  const int rqA_next = code_off(resA, csA, col_next, nA, pstride);
-  const int rqB_next = code_off(resB, csB, col_next, nB, pstride);
-  int2 *bchunk = bot + (64 * k - 63);
 
   auto step = [&](const int i, const int cinA, const int cinB, const RowBuf<R> &PA,
                   const RowBuf<R> &PB, RowBuf<R> &PAfar, RowBuf<R> &PBfar) {
+    if (WRAP && (unsigned)(i - w0) < 64u) {  // (uniform)
+      const int keep = lane == i - w0 ? 0 : -1;
+#pragma unroll
+      for (int r = 0; r < R; ++r) { L.H[r] &= keep; L.E[r] &= keep; }
+      L.hdiag &= keep;
+    }
     L.cfarA = wave_shr1(L.cfarA, cinA);
     L.cfarB = wave_shr1(L.cfarB, cinB);
     load_rows(PAfar, pbase, (uint32_t)L.cfarA + lane_off);
@@ -696,6 +723,7 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
     L.hbot = h;
     L.fbot = f;
     if (store_bot) bchunk[i] = make_int2((int)h, (int)f);
+    asm("" : "+v"(vmax));  // (as in sweep_chunk)
   };
 #pragma unroll 1
   for (int i = 0; i < 64 - NB; i += NB) {
@@ -711,9 +739,153 @@ __device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, u
          u == 0 ? __builtin_amdgcn_readlane(L.rqA, 63) : __builtin_amdgcn_readlane(rqA_next, u - 1),
          u == 0 ? __builtin_amdgcn_readlane(L.rqB, 63) : __builtin_amdgcn_readlane(rqB_next, u - 1),
          L.PA[u], L.PB[u], L.PA[(u + NB - 1) % NB], L.PB[(u + NB - 1) % NB]);
+}
+
+template <int R>
+__device__ __forceinline__ void band_chunk16(BandLane16<R> &L, uint32_t &vmax, uint32_t goe2,
+                                             uint32_t ge2, int lane, int k, int nA, int nB,
+                                             const int2 *top, bool has_top, int2 *bot,
+                                             bool store_bot, const uint8_t *resA, int csA,
+                                             const uint8_t *resB, int csB,
+                                             const uint8_t *pbase, uint32_t lane_off,
+                                             uint32_t pstride) {
+  const int col_next = 64 * (k + 1) + lane;
+  const int2 tq_next = (has_top && col_next < nA) ? top[col_next] : make_int2(0, 0);
+  const int rqA_next = code_off(resA, csA, col_next, nA, pstride);
+  const int rqB_next = code_off(resB, csB, col_next, nB, pstride);
+  sweep_chunk16<R, false>(L, vmax, goe2, ge2, lane, bot + (64 * k - 63), store_bot, rqA_next,
+                          rqB_next, pbase, lane_off, 0);
   L.tq = tq_next;
   L.rqA = rqA_next;
   L.rqB = rqB_next;
+}
+
+// ---- Chained bands.  Swept one after another, the bands of a pair each pay the wave's
+// fill and drain: 63 steps in which some lanes lie outside [0, n), plus the rounding up
+// to whole chunks; on sequences of a few hundred residues that is a fifth of the steps.
+// A single wave (no segment boundary) can instead run a pair's nb bands back to back as
+// one stream of nb * n steps: lane 0 takes column j of band b at step b * n + j and lane
+// l the same column l steps later, so at a band boundary the upper lanes finish the old
+// band while the lower ones start the new one.  A lane entering band b >= 1 clears its
+// rows' H and E and its diagonal at that step (the band's left boundary); nothing else
+// changes, since its first row's H and F from above come from the lane above, already in
+// the new band, or (lane 0) from the band above's bottom row.  The code offsets carry the
+// band (code * pstride + b * 64R), so every profile request follows the band of the step
+// it is for.  Bottom rows go to one linear buffer, buf[b * n + j] for band b, column j,
+// which lane 63 writes at step b * n + j + 63; band b + 1's lane 0 reads it a chunk
+// ahead, at step (b + 1) * n + j - 127 or later, which comes after the write in program
+// order when n >= 191 (kChainMinLen).  With n >= 64 at most one lane enters a band per
+// step, and the 64 steps in which lanes do fall in one chunk or two consecutive ones.
+constexpr int kChainMinLen = 192;
+
+struct ChainPos {
+  int b, j;  // band and column lane 0 works on at one of the chunk's steps
+};
+
+__device__ __forceinline__ ChainPos chain_next(ChainPos p, int n) {
+  p.j += 64;
+  if (p.j >= n) { p.j -= n; p.b += 1; }
+  return p;
+}
+
+// Code offset of position p: the residue (padding past len, and past the last band) times
+// pstride, plus the band's rows.
+__device__ __forceinline__ int chain_code(const uint8_t *res, int cs, ChainPos p, int len,
+                                          int nb, uint32_t pstride, int band_bytes) {
+  if (p.b >= nb) return kPadCode * (int)pstride;
+  return code_off(res, cs, p.j, len, pstride) + p.b * band_bytes;
+}
+
+// Top-row input of position p: the bottom row of the band above (zero for band 0 and
+// past the last band).
+__device__ __forceinline__ int2 chain_top(const int2 *buf, ChainPos p, int n, int nb) {
+  return (p.b >= 1 && p.b < nb) ? buf[(p.b - 1) * n + p.j] : make_int2(0, 0);
+}
+
+// The step within chunk (lane 0 at position p0) at which lane 0 enters a band >= 1, so
+// that lane l enters it at step w0 + l; 64 if no lane enters a band in this chunk.
+__device__ __forceinline__ int chain_window(ChainPos p0, int n) {
+  if (p0.b >= 1 && p0.j < 64) return -p0.j;
+  if (n - p0.j < 64) return n - p0.j;
+  return 64;
+}
+
+// Whether a narrow item runs as chained bands: no segment boundary, two bands or more,
+// n >= kChainMinLen, and buf (kBndLead + nb * n + 63 entries) fits the wave's ring.
+__device__ __forceinline__ bool chain_fits(const IntraArgs &a, const PairItem &pi) {
+  const int nb = pi.band1 - pi.band0;
+  return a.chain && pi.xin < 0 && pi.xout < 0 && nb >= 2 && pi.len >= kChainMinLen &&
+         (int64_t)kBndLead + (int64_t)nb * pi.len + 64 <= 2 * (int64_t)a.bnd_stride;
+}
+
+template <int R>
+__device__ int32_t intra_chain(const IntraArgs &a, const PairItem &pi, const QueryDesc &qd,
+                               int2 *ring) {
+  const int lane = threadIdx.x & 63;
+  const int n = pi.len, nb = pi.band1 - pi.band0;
+  const int nch = (nb * n + 63 + 63) / 64;
+  int2 *buf = ring + kBndLead;
+  const uint8_t *resbase = a.packed + pi.base;
+  const int cs = pi.cstride;
+  const uint32_t pstride = (uint32_t)qd.mrows;
+  const uint32_t lane_off = (uint32_t)(lane * R);
+  const uint8_t *pbase = reinterpret_cast<const uint8_t *>(a.qp8) +
+                         uniform64(qd.qp8 + (int64_t)pi.band0 * 64 * R);
+  int32_t vmax = 0;
+  BandLane<R> L;
+  band_start(L, lane, n, nullptr, false, resbase, cs, pbase, lane_off, pstride);
+  ChainPos cp{0, lane};
+  for (int k = 0; k < nch; ++k) {
+    const ChainPos p0{__builtin_amdgcn_readfirstlane(cp.b), __builtin_amdgcn_readfirstlane(cp.j)};
+    const int w0 = chain_window(p0, n);
+    const ChainPos nx = chain_next(cp, n);
+    const int2 tq_next = chain_top(buf, nx, n, nb);
+    const int rq_next = chain_code(resbase, cs, nx, n, nb, pstride, 64 * R);
+    int2 *bchunk = buf + (64 * k - 63);
+    sweep_chunk<R, true>(L, vmax, a, lane, bchunk, lane == 63, rq_next, pbase, lane_off, w0);
+    L.tq = tq_next;
+    L.rq = rq_next;
+    cp = nx;
+  }
+  return vmax;
+}
+
+// Chained bands of a two-pair item (nA >= nB: the stream's period is nA, B's columns
+// past nB carry the padding code).
+template <int R>
+__device__ uint32_t intra_chain16(const IntraArgs &a, const PairItem &pa, const PairItem &pb,
+                                  const QueryDesc &qd, int2 *ring) {
+  const int lane = threadIdx.x & 63;
+  const int nA = pa.len, nB = pb.len, nb = pa.band1 - pa.band0;
+  const int nch = (nb * nA + 63 + 63) / 64;
+  int2 *buf = ring + kBndLead;
+  const uint8_t *resA = a.packed + pa.base, *resB = a.packed + pb.base;
+  const int csA = pa.cstride, csB = pb.cstride;
+  const uint32_t pstride = (uint32_t)qd.mrows;
+  const uint32_t goe2 = (uint32_t)a.goe * 0x10001u, ge2 = (uint32_t)a.ge * 0x10001u;
+  const uint32_t lane_off = (uint32_t)(lane * R);
+  const uint8_t *pbase = reinterpret_cast<const uint8_t *>(a.qp8) +
+                         uniform64(qd.qp8 + (int64_t)pa.band0 * 64 * R);
+  uint32_t vmax = 0;
+  BandLane16<R> L;
+  band_start16(L, lane, nA, nB, nullptr, false, resA, csA, resB, csB, pbase, lane_off, pstride);
+  ChainPos cp{0, lane};
+  for (int k = 0; k < nch; ++k) {
+    const ChainPos p0{__builtin_amdgcn_readfirstlane(cp.b), __builtin_amdgcn_readfirstlane(cp.j)};
+    const int w0 = chain_window(p0, nA);
+    const ChainPos nx = chain_next(cp, nA);
+    const int2 tq_next = chain_top(buf, nx, nA, nb);
+    const int rqA_next = chain_code(resA, csA, nx, nA, nb, pstride, 64 * R);
+    const int rqB_next = chain_code(resB, csB, nx, nB, nb, pstride, 64 * R);
+    int2 *bchunk = buf + (64 * k - 63);
+    sweep_chunk16<R, true>(L, vmax, goe2, ge2, lane, bchunk, lane == 63, rqA_next, rqB_next,
+                           pbase, lane_off, w0);
+    L.tq = tq_next;
+    L.rqA = rqA_next;
+    L.rqB = rqB_next;
+    cp = nx;
+  }
+  return vmax;
 }
 
 // Segments of a split pair hand the bottom row of their last band to the next segment
@@ -992,15 +1164,43 @@ void k_intra32(IntraArgs a) {
     const QueryDesc qd = a.queries[pi.query];
     if (a.second && a.second[it].len >= 0) {
       const PairItem pb = a.second[it];
-      const uint32_t v = wave_pk_max(intra_pair16<R, 1>(a, pi, pb, qd, 0, ring));
+      const uint32_t v = wave_pk_max(chain_fits(a, pi) ? intra_chain16<R>(a, pi, pb, qd, ring)
+                                                       : intra_pair16<R, 1>(a, pi, pb, qd, 0, ring));
       finish_half(a, pi, qd, (int)(int16_t)(v & 0xffffu));
       finish_half(a, pb, qd, (int)(int16_t)(v >> 16));
       continue;
     }
-    int32_t vmax = intra_pair<R, 1>(a, pi, qd, 0, ring);
+    int32_t vmax = chain_fits(a, pi) ? intra_chain<R>(a, pi, qd, ring)
+                                     : intra_pair<R, 1>(a, pi, qd, 0, ring);
     for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, __shfl_xor(vmax, off));
     a.scores[qd.out + pi.out] = vmax;
   }
+}
+
+// LDS that an intra-task workgroup reserves and does not use, so that a CU holds at most
+// two four-wave workgroups, or one eight-wave workgroup (with room for a four-wave one
+// beside it): the residency the launches are planned for.  With 85-178 VGPRs the
+// registers alone would admit more; a third four-wave workgroup beside the critical
+// pairs' waves slowed the 5478-residue query over the long-sequence mix by 10-15%.
+// Sized from the device's LDS per CU and per workgroup (kept per device).
+static size_t intra_lds_reserve(int waves) {
+  static std::atomic<int> cache4[64], cache8[64];  // reserve + 1, 0 = not yet known
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  std::atomic<int> &c = waves == 4 ? cache4[dev] : cache8[dev];
+  const int known = c.load(std::memory_order_relaxed);
+  if (known > 0) return (size_t)(known - 1);
+  int per_cu = 0, per_wg = 0;
+  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+          hipSuccess ||
+      hipDeviceGetAttribute(&per_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 0;
+  const int limit = std::max(0, per_wg - 4096);  // (the kernels' own LDS is under 2 KB)
+  const int four = std::min(limit, std::max(0, per_cu / 2 - 4096));
+  const int eight = per_cu / 2 + 1024 <= limit ? per_cu / 2 + 1024 : four;
+  const int r = waves == 4 ? four : eight;
+  c.store(r + 1, std::memory_order_relaxed);
+  return (size_t)r;
 }
 
 // Workgroups of kIntraWaves (8) or 4 waves at R = 2, 4, 8 or 16.  Four-wave workgroups
@@ -1009,33 +1209,25 @@ void k_intra32(IntraArgs a) {
 hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
   if (grid == 0) return hipSuccess;
   static_assert(kCritWaves == 4 && kNarrowWaves == 4, "four-wave instances below");
+  const size_t lds = intra_lds_reserve(waves);
   if (waves == 4) {
     switch (R) {
-      case 2: hipLaunchKernelGGL((k_intra32<2, 4>), dim3(grid), dim3(256), 0, s, a); break;
-      case 4: hipLaunchKernelGGL((k_intra32<4, 4>), dim3(grid), dim3(256), 0, s, a); break;
-      case 8: hipLaunchKernelGGL((k_intra32<8, 4>), dim3(grid), dim3(256), 0, s, a); break;
-      case 16: hipLaunchKernelGGL((k_intra32<16, 4>), dim3(grid), dim3(256), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_intra32<2, 4>), dim3(grid), dim3(256), lds, s, a); break;
+      case 4: hipLaunchKernelGGL((k_intra32<4, 4>), dim3(grid), dim3(256), lds, s, a); break;
+      case 8: hipLaunchKernelGGL((k_intra32<8, 4>), dim3(grid), dim3(256), lds, s, a); break;
+      case 16: hipLaunchKernelGGL((k_intra32<16, 4>), dim3(grid), dim3(256), lds, s, a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   if (waves != kIntraWaves) return hipErrorInvalidValue;
+  const dim3 blk(64 * kIntraWaves);
   switch (R) {
-    case 2:
-      hipLaunchKernelGGL((k_intra32<2, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
-      break;
-    case 4:
-      hipLaunchKernelGGL((k_intra32<4, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_intra32<8, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s, a);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_intra32<16, kIntraWaves>), dim3(grid), dim3(64 * kIntraWaves), 0, s,
-                         a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 2: hipLaunchKernelGGL((k_intra32<2, kIntraWaves>), dim3(grid), blk, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_intra32<4, kIntraWaves>), dim3(grid), blk, lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_intra32<8, kIntraWaves>), dim3(grid), blk, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k_intra32<16, kIntraWaves>), dim3(grid), blk, lds, s, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

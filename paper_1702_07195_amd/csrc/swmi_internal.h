@@ -92,6 +92,7 @@ struct IntraArgs {
   int32_t spin_limit;        // polls before a wait between segments gives up (sets *error)
   int32_t flag_cap;          // recompute-list entries; pairs beyond it are marked kSat16
   int32_t wide_prio;         // wave priority of the wide phase (0, 2 or 3); narrow is 0
+  int32_t chain;             // non-zero: narrow items may run as chained bands
 };
 
 // The pass over a recompute list that overflowed: every (query, sequence) whose score

@@ -43,6 +43,7 @@ SW_KNOB_FLAG_CAP = 15
 SW_KNOB_CRIT_ROWS = 16
 SW_KNOB_CRIT_SHARE = 17
 SW_KNOB_INTRA_PRIO = 18
+SW_KNOB_INTRA_CHAIN = 19
 
 # Every entry point declared in include/swmi.h.
 SYMBOLS = ("sw_db_load", "sw_db_size", "sw_db_free", "sw_search", "sw_search_async",

@@ -143,6 +143,7 @@ def test_intra_pairs_knob_values():
 @pytest.mark.parametrize("name,bad,good,default", [
     ("SW_KNOB_CRIT_SHARE", (-1, 101), (1, 50, 100, 0), 0),
     ("SW_KNOB_INTRA_PRIO", (-1, 2), (0, 1), 1),
+    ("SW_KNOB_INTRA_CHAIN", (-1, 2), (0, 1), 1),
     ("SW_KNOB_CRIT_ROWS", (2, 16, -8), (4, 8, 0), 0),
 ])
 def test_critical_pair_knob_values(name, bad, good, default):
