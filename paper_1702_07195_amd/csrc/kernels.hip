@@ -20,9 +20,6 @@
 //               every pair of a database too small to fill the GPU, and for the exact
 //               recompute of saturated alignments (Section 4.2): int32, or two pairs
 //               per wave in packed int16 with the same saturation rule.
-#include <algorithm>
-#include <atomic>
-
 #include "swmi_internal.h"
 
 namespace swmi {
