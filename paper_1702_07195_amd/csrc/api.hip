@@ -352,7 +352,6 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   const int64_t qbytes = p.qbytes;
   const size_t bnd16_slot = p.bnd16_slot, bnd32_slot = p.bnd32_slot;
   const int bnd32_stride = p.bnd32_stride;
-  const int grid32 = p.grid32;
   const size_t need_flagged = p.need_flagged;
   if (knobs.mem_cap_mb > 0 &&
       (int64_t)(std::max(p.need_bytes, w->total_bytes()) >> 20) > knobs.mem_cap_mb)
@@ -369,7 +368,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   grow(w->ctr, sizeof(Counters));
   grow(w->flagged, need_flagged * sizeof(PairItem));
   grow(w->bnd16, std::max<size_t>(1, bnd16_words(p)) * 4);
-  grow(w->bnd32, std::max<size_t>(1, (size_t)grid32 * bnd32_slot) * 8);
+  grow(w->bnd32, std::max<size_t>(1, p.bnd32_elems) * 8);
   grow(w->xbnd, (size_t)std::max<int64_t>(1, p.xbnd_elems) * 8);
   // per segment boundary: progress, finished flag (both cleared per search), maximum
   grow(w->xprog, (size_t)std::max<int32_t>(1, p.nprog) * 12);
@@ -466,7 +465,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.chain = g_knob_intra_chain.load() ? 1 : 0;
     const bool timed = allow_timing && db->timing.load();
     if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
-    hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, w->aux));
+    hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, w->aux, p.main_per_cu));
     if (timed) {
       hip_check(hipEventRecord(w->t1[1], w->aux));
       w->timed[1] = true;
@@ -492,8 +491,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ca.goe = gap_open + gap_extend;
     ca.ge = gap_extend;
     ca.scores = scores_dev;
-    ca.bnd = (int2 *)w->bnd32.ptr + (size_t)(p.grid_long + p.grid_re) * bnd32_slot;
-    ca.bnd_slot_elems = (int64_t)bnd32_slot;
+    ca.bnd = (int2 *)w->bnd32.ptr + p.bnd32_off_crit;
+    ca.bnd_slot_elems = (int64_t)p.bnd32_slot_crit;
     ca.bnd_stride = bnd32_stride;
     ca.xbnd = (int2 *)w->xbnd.ptr;
     ca.xprog = (int32_t *)w->xprog.ptr;
@@ -507,7 +506,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ca.flag_cap = (int32_t)need_flagged;
     ca.wide_prio = g_knob_intra_prio.load() ? 3 : 0;
     ca.chain = g_knob_intra_chain.load() ? 1 : 0;
-    hip_check(launch_intra32(ca, p.crit_R, kCritWaves, p.grid_crit, w->crit));
+    hip_check(launch_intra32(ca, p.crit_R, kCritWaves, p.grid_crit, w->crit, 2));
     hip_check(hipEventRecord(w->join_crit, w->crit));
   }
   // An inter-task launch of fewer items than the chip has SIMDs, beside the intra-task
@@ -602,8 +601,8 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.goe = gap_open + gap_extend;
     ra.ge = gap_extend;
     ra.scores = scores_dev;
-    ra.bnd = (int2 *)w->bnd32.ptr + (size_t)p.grid_long * bnd32_slot;
-    ra.bnd_slot_elems = (int64_t)bnd32_slot;
+    ra.bnd = (int2 *)w->bnd32.ptr + p.bnd32_off_re;
+    ra.bnd_slot_elems = (int64_t)p.bnd32_slot_re;
     ra.bnd_stride = bnd32_stride;
     ra.xbnd = (int2 *)w->xbnd.ptr;
     ra.xprog = (int32_t *)w->xprog.ptr;
@@ -618,7 +617,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ra.wide_prio = 0;
     ra.chain = g_knob_intra_chain.load() ? 1 : 0;
     if (timed && p.grid_re > 0) hip_check(hipEventRecord(w->t0[2], s));
-    hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s));
+    hip_check(launch_intra32(ra, kIntraR, kIntraWaves, p.grid_re, s, 1));
     if (timed && p.grid_re > 0) {
       hip_check(hipEventRecord(w->t1[2], s));
       w->timed[2] = true;

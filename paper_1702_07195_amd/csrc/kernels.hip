@@ -1174,39 +1174,41 @@ void k_intra32(IntraArgs a) {
   }
 }
 
-// LDS that an intra-task workgroup reserves and does not use, so that a CU holds at most
-// two four-wave workgroups, or one eight-wave workgroup (with room for a four-wave one
-// beside it): the residency the launches are planned for.  With 85-178 VGPRs the
-// registers alone would admit more; a third four-wave workgroup beside the critical
-// pairs' waves slowed the 5478-residue query over the long-sequence mix by 10-15%.
-// Sized from the device's LDS per CU and per workgroup (kept per device).
-static size_t intra_lds_reserve(int waves) {
-  static std::atomic<int> cache4[64], cache8[64];  // reserve + 1, 0 = not yet known
+// LDS that an intra-task workgroup reserves and does not use, so that at most per_cu
+// workgroups of its launch share a CU (per_cu = 1: more than half the CU's LDS, which
+// still leaves room for one four-wave workgroup of another launch at per_cu = 2).  With
+// 85-146 VGPRs the registers alone would admit more than the launches are planned for;
+// a third four-wave workgroup beside the critical pairs' waves slowed the 5478-residue
+// query over the long-sequence mix by 10-15%.  Sized from the device's LDS per CU and
+// per workgroup (read once per device).
+static size_t intra_lds_reserve(int per_cu) {
+  static std::atomic<int> lds_cu[64], lds_wg[64];  // 0 = not yet known
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  std::atomic<int> &c = waves == 4 ? cache4[dev] : cache8[dev];
-  const int known = c.load(std::memory_order_relaxed);
-  if (known > 0) return (size_t)(known - 1);
-  int per_cu = 0, per_wg = 0;
-  if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
-          hipSuccess ||
-      hipDeviceGetAttribute(&per_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    return 0;
-  const int limit = std::max(0, per_wg - 4096);  // (the kernels' own LDS is under 2 KB)
-  const int four = std::min(limit, std::max(0, per_cu / 2 - 4096));
-  const int eight = per_cu / 2 + 1024 <= limit ? per_cu / 2 + 1024 : four;
-  const int r = waves == 4 ? four : eight;
-  c.store(r + 1, std::memory_order_relaxed);
-  return (size_t)r;
+  int cu = lds_cu[dev].load(std::memory_order_relaxed);
+  int wg = lds_wg[dev].load(std::memory_order_relaxed);
+  if (cu <= 0 || wg <= 0) {
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        cu <= 0 || wg <= 0)
+      return 0;
+    lds_cu[dev].store(cu, std::memory_order_relaxed);
+    lds_wg[dev].store(wg, std::memory_order_relaxed);
+  }
+  const int limit = std::max(0, wg - 4096);  // (the kernels' own LDS is under 2 KB)
+  const int r = per_cu <= 1 ? cu / 2 + 1024 : cu / per_cu - 4096;
+  return (size_t)std::max(0, std::min(limit, r));
 }
 
 // Workgroups of kIntraWaves (8) or 4 waves at R = 2, 4, 8 or 16.  Four-wave workgroups
 // serve the critical-pair launch (one wave per SIMD, none idle) and throughput-bound
-// main launches (two per CU; one fits beside a critical-pair workgroup).
-hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s) {
+// main launches (two per CU beside a critical-pair workgroup, else three).
+hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s,
+                          int per_cu) {
   if (grid == 0) return hipSuccess;
   static_assert(kCritWaves == 4 && kNarrowWaves == 4, "four-wave instances below");
-  const size_t lds = intra_lds_reserve(waves);
+  const size_t lds = intra_lds_reserve(per_cu);
   if (waves == 4) {
     switch (R) {
       case 2: hipLaunchKernelGGL((k_intra32<2, 4>), dim3(grid), dim3(256), lds, s, a); break;

@@ -509,19 +509,22 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
     st[SW_ST_STRIP_ROWS] = p.T;
     st[SW_ST_QUERY_PAIRS] = q2 ? 1 : 0;
   }
-  // Two waves per SIMD: one persistent 8-wave workgroup per compute unit, or two 4-wave
-  // ones.  The kernel's per-step profile gathers touch one cache line per lane, and a
-  // second resident 8-wave workgroup per CU (four waves per SIMD) measured slower and
-  // erratic on MI355X (86 ms vs 103-115 ms for a 35000-residue query over the
-  // long-sequence mix), not faster.
+  // Persistent workgroups per compute unit of the main launch: one of eight waves (two
+  // per SIMD), or four-wave ones: two beside a critical-pair launch (whose workgroup
+  // takes the third slot; a third main workgroup there slowed the critical waves by
+  // 10-15%), else three (three waves per SIMD: the 35000-residue query over the
+  // long-sequence mix on MI355X, 49.2-50.0 ms against 50.1-50.9 with two and 51.2-51.4
+  // with one eight-wave workgroup).  Four waves per SIMD (two eight-wave workgroups)
+  // measured slower and erratic: the per-step profile gathers touch one cache line per
+  // lane.  Each launch reserves LDS so that no more than that many share a CU.
   const int64_t n_narrow = (int64_t)p.longitems.size() - p.n_wide;
+  p.main_per_cu = p.main_waves == kIntraWaves ? 1 : (p.crititems.empty() ? 3 : 2);
   // The critical pairs' launch (a workgroup of kCritWaves waves per CU, one band and one
-  // wave per SIMD) is enqueued first and gets its CUs first; the main launch still asks
-  // for one workgroup per CU, and the ones that find no free CU start as the critical
-  // workgroups finish.
+  // wave per SIMD) is enqueued first and gets its CUs first; the main launch's
+  // workgroups that find no room start as the critical workgroups finish.
   p.grid_crit = (int)std::min<int64_t>((int64_t)p.crititems.size(), std::max(1, db.num_cu));
   p.grid_long = (int)std::min<int64_t>((int64_t)p.n_wide + (n_narrow + p.main_waves - 1) / p.main_waves,
-                                       (int64_t)db.num_cu * (kIntraWaves / p.main_waves));
+                                       (int64_t)db.num_cu * p.main_per_cu);
   // the recompute list is usually empty; a quarter of the CUs is plenty when it is not,
   // and nothing is launched when no kernel can append to it
   const bool may_flag = (nitems16 > 0 && p.grid16 > 0) || p.nduos > 0;
@@ -565,7 +568,13 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
   }
   p.stats[SW_ST_BIG_WAVES] = p.big_waves;
   p.bnd32_stride = ((db.max_len + 128 + 63) / 64) * 64;  // >= kBndLead + max_len + 63
-  p.bnd32_slot = (size_t)std::max(kIntraWaves + 1, 2 * kIntraWaves) * p.bnd32_stride;
+  auto ring = [&](int w) { return (size_t)std::max(w + 1, 2 * w) * p.bnd32_stride; };
+  p.bnd32_slot = ring(p.main_waves);
+  p.bnd32_slot_re = ring(kIntraWaves);
+  p.bnd32_slot_crit = ring(kCritWaves);
+  p.bnd32_off_re = (size_t)p.grid_long * p.bnd32_slot;
+  p.bnd32_off_crit = p.bnd32_off_re + (size_t)p.grid_re * p.bnd32_slot_re;
+  p.bnd32_elems = p.bnd32_off_crit + (size_t)p.grid_crit * p.bnd32_slot_crit;
   // saturated pairs: any database sequence, from either kernel, up to the list's capacity
   // (the pairs beyond it are marked in the scores and found by the overflow pass)
   const int64_t list_cap = k.flag_cap > 0 ? k.flag_cap : kFlagCap;
@@ -575,7 +584,7 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
                  sizeof(Counters) + p.pairs.size() * sizeof(QueryPair) +
                  p.need_flagged * sizeof(PairItem) +
                  (2 * p.longitems.size() + p.crititems.size()) * sizeof(PairItem) +
-                 bnd16_words(p) * 4 + (size_t)p.grid32 * p.bnd32_slot * 8 +
+                 bnd16_words(p) * 4 + p.bnd32_elems * 8 +
                  (size_t)p.xbnd_elems * 8 + (size_t)p.nprog * 12;
   // small per-call inputs, staged in one block (64-byte aligned parts)
   auto up = [](size_t x) { return (x + 63) & ~size_t(63); };
@@ -593,21 +602,9 @@ Plan plan_with(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k
 
 }  // namespace
 
-// Four-wave main workgroups serve a throughput-bound search because one fits beside a
-// critical-pair workgroup; when no pair goes to that launch, eight-wave workgroups (one
-// per CU, the same two waves per SIMD) were faster (long-sequence mix on MI355X, the
-// 35000-residue query: 53.5 against 55.1 ms), so such a search is planned again with
-// them.
 Plan make_plan(const DbView &db, const int64_t *qoff, int64_t nq, const Knobs &k,
                const Occupancy &occ) {
-  Plan p = plan_with(db, qoff, nq, k, occ);
-  if (k.main_waves == 0 && p.main_waves == kNarrowWaves && p.crititems.empty() &&
-      !p.longitems.empty()) {
-    Knobs k8 = k;
-    k8.main_waves = kIntraWaves;
-    return plan_with(db, qoff, nq, k8, occ);
-  }
-  return p;
+  return plan_with(db, qoff, nq, k, occ);
 }
 
 }  // namespace swmi

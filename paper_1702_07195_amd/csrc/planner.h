@@ -64,7 +64,9 @@ struct Plan {
   int T = 32;                    // inter-task strip rows (half-strip for one query per lane)
   bool q2 = false;               // two queries per lane (k_inter16q2)
   int R = kIntraR;               // rows per lane of the long-pair intra-task launch
-  int main_waves = kIntraWaves;  // waves per workgroup of that launch (8, or 4 at two per CU)
+  int main_waves = kIntraWaves;  // waves per workgroup of that launch (8, or 4)
+  int main_per_cu = 1;           // its workgroups per compute unit (8 waves: 1; 4 waves: 2
+                                 // beside a critical-pair launch, else 3)
   bool throughput_bound = false; // the intra-task search is estimated throughput-bound
   int per_cu = 0;                // inter-task workgroups per compute unit
   std::vector<int64_t> lens;     // query lengths
@@ -100,7 +102,11 @@ struct Plan {
   int64_t wide_items = 0;
   size_t bnd16_small = 0;
   int32_t bnd32_stride = 0;   // int2 elements per intra-task band buffer
-  size_t bnd32_slot = 0;      // int2 elements per intra-task workgroup's band ring
+  // Band rings of the intra-task launches, int2 elements per workgroup (max(W + 1, 2W)
+  // band buffers for W waves): the main launch's grid_long slots, then the recompute
+  // launch's grid_re, then the critical-pair launch's grid_crit.
+  size_t bnd32_slot = 0, bnd32_slot_re = 0, bnd32_slot_crit = 0;
+  size_t bnd32_off_re = 0, bnd32_off_crit = 0, bnd32_elems = 0;
   size_t need_flagged = 0;    // recompute-list entries
   size_t need_bytes = 0;      // device bytes of the whole workspace
   // staging layout: byte offsets of the parts of the per-call input block

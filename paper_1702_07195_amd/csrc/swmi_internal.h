@@ -208,7 +208,9 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_inter16(const InterArgs &a, int T, int grid, hipStream_t s);
 hipError_t launch_profile2(const Profile2Args &a, hipStream_t s);
 hipError_t launch_inter16q2(const Inter2Args &a, int T, int grid, hipStream_t s);
-hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s);
+// per_cu: the most workgroups of this launch that may share a compute unit (LDS reserved).
+hipError_t launch_intra32(const IntraArgs &a, int R, int waves, int grid, hipStream_t s,
+                          int per_cu);
 hipError_t launch_serve(const ServeArgs &a, int grid, hipStream_t s);
 hipError_t launch_rescan(const RescanArgs &a, int grid, hipStream_t s);
 int serve_max_blocks_per_cu();

@@ -294,7 +294,21 @@ void check_plan(const Plan &p, const Db &d, const std::vector<int64_t> &qoff, in
   }
   // a band buffer holds the bottom row's reach, kBndLead entries in (see above)
   CHECK(p.bnd32_stride >= kBndLead + v.max_len + 63, "band buffer");
-  CHECK(p.bnd32_slot >= (size_t)2 * kIntraWaves * p.bnd32_stride, "band ring");
+  // band rings: a workgroup of W waves needs max(W + 1, 2W) band buffers, and the three
+  // launches' slot ranges follow one another
+  auto ring = [&](int w) { return (size_t)std::max(w + 1, 2 * w) * p.bnd32_stride; };
+  CHECK(p.bnd32_slot >= ring(p.main_waves), "main band ring");
+  CHECK(p.bnd32_slot_re >= ring(kIntraWaves), "recompute band ring");
+  CHECK(p.bnd32_slot_crit >= ring(kCritWaves), "critical-pair band ring");
+  CHECK(p.bnd32_off_re >= (size_t)p.grid_long * p.bnd32_slot, "band rings overlap");
+  CHECK(p.bnd32_off_crit >= p.bnd32_off_re + (size_t)p.grid_re * p.bnd32_slot_re,
+        "band rings overlap");
+  CHECK(p.bnd32_elems >= p.bnd32_off_crit + (size_t)p.grid_crit * p.bnd32_slot_crit,
+        "band rings beyond the buffer");
+  CHECK(p.main_per_cu == (p.main_waves == 8 ? 1 : (p.crititems.empty() ? 3 : 2)),
+        "main workgroups per CU");
+  CHECK(p.grid_long <= (int64_t)std::max(1, v.num_cu) * p.main_per_cu, "main grid per CU");
+  CHECK(p.grid_crit <= std::max(1, v.num_cu), "critical-pair grid per CU");
   const size_t parts[][2] = {
       {0, (size_t)p.qbytes},
       {p.off_qoff, (size_t)(nq + 1) * 8},
@@ -364,8 +378,6 @@ int main() {
               std::to_string(num_cu);
     const Plan p = make_plan(d.view, qoff.data(), nq, k, occ);
     check_plan(p, d, qoff, nq);
-    if (k.main_waves == 0 && p.crititems.empty() && !p.longitems.empty())
-      CHECK(p.main_waves == 8, "four-wave main workgroups without a critical-pair launch");
     n_split += p.nprog > 0;
     n_crit += !p.crititems.empty();
     n_duo += p.nduos > 0;
