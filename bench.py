@@ -44,19 +44,25 @@ PEAK_INT16_TOPS = 2 * PEAK_INT32_TOPS
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_07195_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "inter16_full_scale_traffic.json")
 TRAFFIC_FILE_Q2 = os.path.join(ROOT, "profiles", "inter16q2_batched_traffic.json")
+TRAFFIC_FILE_INTRA = os.path.join(ROOT, "profiles", "intra32_long_mix_traffic.json")
 _SECTION = b"// ------------------------------------------------------------------------ "
 
 
 def kernel_hash(section: str = "inter") -> str:
-    """Hash of the source an inter-task kernel is built from: for k_inter16 ("inter") the
-    shared helpers, profile and packing kernels and k_inter16 (everything before the
-    intra-task section); for k_inter16q2 ("inter_q2") those plus its own section."""
+    """Hash of the source a kernel is built from: for k_inter16 ("inter") the shared
+    helpers, profile and packing kernels and k_inter16 (everything before the intra-task
+    section); for k_inter16q2 ("inter_q2") those plus its own section; for k_intra32
+    ("intra") those plus the intra-task section."""
     with open(KERNEL_SRC, "rb") as f:
         src = f.read()
     cut = src.find(_SECTION + b"intra-task")
     head = src[:cut if cut >= 0 else len(src)]
     if section == "inter":
         return hashlib.sha256(head).hexdigest()[:16]
+    if section == "intra":
+        end = src.find(_SECTION, cut + len(_SECTION)) if cut >= 0 else -1
+        body = src[cut:end if end >= 0 else len(src)] if cut >= 0 else b""
+        return hashlib.sha256(head + body).hexdigest()[:16]
     q2 = src.find(_SECTION + b"inter-task, two queries")
     return hashlib.sha256(head + (src[q2:] if q2 >= 0 else b"")).hexdigest()[:16]
 
@@ -303,10 +309,11 @@ def longest_pair_bound(args, db, queries, sm, go, ge, elapsed):
                     "its longest pair's dependency chain"}
 
 
-def intra_roofline(stats, launches, total_ms):
+def intra_roofline(stats, launches, total_ms, counters=None):
     """Roofline of the main intra-task launch from its own algorithmic cells: int32 cells
     at the int32 peak and packed-int16 (two pairs per wave) cells at the int16 peak; frac
-    is the time that work needs at those peaks over the measured launch time."""
+    is the time that work needs at those peaks over the measured launch time.  HBM
+    traffic and VALU issue come from committed PMC runs of the same kernel source."""
     if launches <= 0 or total_ms <= 0:
         return None
     c32 = sum(st["cells_intra32"] for st in stats)
@@ -319,7 +326,9 @@ def intra_roofline(stats, launches, total_ms):
     peak = OPS_PER_CELL * (c32l + c16l) / t_peak / 1e12
     return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
             "unit": "Tops/s (int32, with packed-int16 cells at twice the rate)",
-            "frac": round(t_peak / avg_s, 3), "traffic": None,
+            "frac": round(t_peak / avg_s, 3),
+            "traffic": counters.get("bytes_per_launch") if counters else None,
+            "valu_issue": valu_issue(counters, avg_s),
             "kernel": "k_intra32 (main intra-task launch)",
             "avg_launch_ms": round(avg_s * 1e3, 3), "launches": launches,
             "cells_int32_per_launch": int(c32l), "cells_int16_per_launch": int(c16l),
@@ -348,7 +357,9 @@ def bench_search(args, w, label):
         if roof is not None:
             roof["valu_issue"] = valu_issue(counters, roof["avg_launch_ms"] / 1e3)
     else:
-        roof = intra_roofline(stats, nlo, mslo)
+        counters = (load_counters(TRAFFIC_FILE_INTRA, "intra")
+                    if label == "long-sequence mix" else None)
+        roof = intra_roofline(stats, nlo, mslo, counters)
     config = {"workload": label, "db_seqs": db.n_seqs, "db_residues": D,
               "query_lengths": [len(q) for q in queries], "matrix": w.matrix,
               "gap_open": w.gap_open, "gap_extend": w.gap_extend}
