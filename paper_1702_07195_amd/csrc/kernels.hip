@@ -590,12 +590,14 @@ __device__ __forceinline__ void sweep_chunk(BandLane<R> &L, int32_t &vmax, const
     L.hbot = h;
     L.fbot = f;
     if (store_bot) bchunk[i] = make_int2(h, f);
-    // The running maximum is brought up to date at every step.  Left free, the compiler
-    // defers the maxima of a whole group of steps to the group's end, which keeps every
-    // H of the group live (about 80 more VGPRs at R = 16) and leaves no room to clear a
-    // lane's rows in place.  (An empty asm statement without side effects: no instruction
-    // is emitted, and the scheduler may still interleave neighbouring steps.)
-    asm("" : "+v"(vmax));
+    // The running maximum is brought up to date at every step of a chained sweep and at
+    // R = 16.  Left free, the compiler defers the maxima of a whole group of steps to the
+    // group's end, which keeps every H of the group live (about 80 more VGPRs at R = 16)
+    // and leaves no room to clear a lane's rows in place.  At R = 2 to 8 in a band sweep
+    // the deferred form is kept: there the registers are not short, and pinning made the
+    // latency-bound searches (a wave alone on its SIMD) 2-6% slower.  (An empty asm
+    // statement without side effects: no instruction is emitted.)
+    if (WRAP || R >= 16) asm("" : "+v"(vmax));
   };
 #pragma unroll 1
   for (int i = 0; i < 64 - NB; i += NB) {
