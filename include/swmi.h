@@ -386,10 +386,11 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
  *                          the critical-pair launch (1..100; 0 = automatic).  Scores are
  *                          the same.
  *   SW_KNOB_INTRA_PRIO     1 (default): the intra-task kernel sweeps the critical pairs at
- *                          the highest wave priority and the main launch's wide items (a
+ *                          the highest wave priority, the main launch's wide items (a
  *                          whole workgroup per pair, the longest pairs) above its narrow
- *                          ones; 0: every wave at the default priority.  Scores are the
- *                          same.
+ *                          ones, and the narrow items within 70% of the longest narrow
+ *                          one's cost above the others; 0: every wave at the default
+ *                          priority.  Scores are the same.
  *   SW_KNOB_INTRA_CHAIN    1 (default): a pair the intra-task kernel sweeps with one wave
  *                          (at least 192 residues, two or more query bands) runs its
  *                          bands back to back as one stream instead of one band after
