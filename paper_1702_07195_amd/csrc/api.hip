@@ -431,10 +431,14 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
   }
 
   // long sequences: intra-task kernel on the auxiliary stream, concurrent with the sweep
-  // (enqueued after the inter-task launch, whose few waves are then dispatched first)
+  // (enqueued after the inter-task launch, whose few waves are then dispatched first);
+  // with no inter-task launch to run beside, on the search's own stream (a fork and a
+  // join between streams cost a latency-bound search about 5% of its time)
+  const bool main_aside = p.grid_long > 0 && p.grid16 > 0;
+  hipStream_t main_stream = main_aside ? w->aux : s;
   auto launch_main = [&]() {
     if (p.grid_long <= 0) return;
-    hip_check(hipStreamWaitEvent(w->aux, w->fork, 0));
+    if (main_aside) hip_check(hipStreamWaitEvent(w->aux, w->fork, 0));
     IntraArgs ia;
     ia.packed = (const uint8_t *)db->packed.ptr;
     ia.items = d_items;
@@ -464,16 +468,16 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     ia.wide_prio = g_knob_intra_prio.load() ? 2 : 0;
     ia.chain = g_knob_intra_chain.load() ? 1 : 0;
     const bool timed = allow_timing && db->timing.load();
-    if (timed) hip_check(hipEventRecord(w->t0[1], w->aux));
-    hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, w->aux, p.main_per_cu));
+    if (timed) hip_check(hipEventRecord(w->t0[1], main_stream));
+    hip_check(launch_intra32(ia, p.R, p.main_waves, p.grid_long, main_stream, p.main_per_cu));
     if (timed) {
-      hip_check(hipEventRecord(w->t1[1], w->aux));
+      hip_check(hipEventRecord(w->t1[1], main_stream));
       w->timed[1] = true;
     }
-    hip_check(hipEventRecord(w->join, w->aux));
+    if (main_aside) hip_check(hipEventRecord(w->join, w->aux));
   };
 
-  if (p.grid_long > 0 || p.grid_crit > 0) hip_check(hipEventRecord(w->fork, s));
+  if (main_aside || p.grid_crit > 0) hip_check(hipEventRecord(w->fork, s));
   // critical pairs first (their workgroups are dispatched before the main launch's),
   // on a stream of their own, with finer bands
   if (p.grid_crit > 0) {
@@ -586,7 +590,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
     // exact int32 recompute of the saturated alignments of both kernels (count read on
     // the device), after the long-pair kernel; it uses the boundary slots after that
     // kernel's
-    if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
+    if (main_aside) hip_check(hipStreamWaitEvent(s, w->join, 0));
     if (p.grid_crit > 0) hip_check(hipStreamWaitEvent(s, w->join_crit, 0));
     IntraArgs ra;
     ra.packed = (const uint8_t *)db->packed.ptr;
@@ -638,7 +642,7 @@ void enqueue_search(sw_db *db, Workspace *w, const uint8_t *queries, const int64
       hip_check(launch_rescan(rs, p.grid_re * kIntraWaves, s));
     }
   }
-  if (p.grid_long > 0) hip_check(hipStreamWaitEvent(s, w->join, 0));
+  if (main_aside) hip_check(hipStreamWaitEvent(s, w->join, 0));
   if (p.grid_crit > 0) hip_check(hipStreamWaitEvent(s, w->join_crit, 0));
   std::lock_guard<std::mutex> lk(db->mu);
   std::memcpy(db->last_stats, p.stats, sizeof(p.stats));
