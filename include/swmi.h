@@ -383,8 +383,8 @@ int sw_search_stats(const sw_db *db, int64_t *values, int32_t n);
  *                          of 256 or 512 rows); 0 (default) = 8.  Scores are the same.
  *   SW_KNOB_CRIT_SHARE     a split long pair whose band pipeline is estimated to take more
  *                          than this percentage of the whole intra-task search runs in
- *                          the critical-pair launch (1..100; 0 = automatic).  Scores are
- *                          the same.
+ *                          the critical-pair launch (1..100; 0 = automatic, 20).  Scores
+ *                          are the same.
  *   SW_KNOB_INTRA_PRIO     1 (default): the intra-task kernel sweeps the critical pairs at
  *                          the highest wave priority, the main launch's wide items (a
  *                          whole workgroup per pair, the longest pairs) above its narrow
