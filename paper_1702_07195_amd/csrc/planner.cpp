@@ -33,13 +33,16 @@ namespace {
 //     short steps measured less efficient (0.77 at R = 8, 0.34 at R = 4, on a 35,000-row
 //     query; 0.15 assumed at R = 2), and R = 2 reached 0.45 of that rate even with few
 //     bands (a 1,000-row query over 6.4e6 residues), and
-//   - the longest pair's path: one band alone is one wave among two per SIMD, n + 63
-//     steps of 0.5 us x (7.5 R + 14) / 134 per band; several bands (a pair at least
-//     `wide_len` long) are a pipeline of waves alone on their SIMDs, 0.76 of that step,
-//     which at R > kCritR may run at kCritR rows in the critical-pair launch,
+//   - the longest pair's path: n + 63 steps per band of a wave alone on its SIMD, about
+//     0.083 + 0.0118 R us (measured 0.13, 0.17 and 0.27 us at R = 4, 8 and 16); several
+//     bands (a pair at least `wide_len` long) are a pipeline of a workgroup's waves,
+//     alone on their SIMDs up to four bands and 1.66 times slower beyond (two waves per
+//     SIMD), and a pair of more than four bands at R > kCritR may instead run at kCritR
+//     rows in the critical-pair launch (segments of four bands, one wave per SIMD),
 // and the smallest estimate wins, a tie going to the larger R (R = 16 and 8 tie when
 // both leave the longest pairs to the critical-pair launch, and 16 measured faster
-// there).  R = 2 is weighed only when the path at R = 4 exceeds a millisecond: below
+// there).  (With step times priced from instruction counts, the 2005-row query over the
+// long-sequence mix took R = 4, 7.5 ms, against 6.2 ms at R = 8, which it now takes.)  R = 2 is weighed only when the path at R = 4 exceeds a millisecond: below
 // that, per-search costs the estimate leaves out dominate, and R = 2 measured no faster
 // (a 144-row query over 2,000 sequences of at most 2,000 residues).  (Measured on the
 // long-sequence mix, whose longest sequence has 35,000 residues: queries of 300 and
@@ -49,9 +52,13 @@ int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
              int64_t wide_len, int num_cu, const Knobs &k, bool *throughput_bound) {
   auto step_scale = [](int R) { return (7.5 * R + 14.0) / (7.5 * 16 + 14.0); };
   auto bands = [](int64_t m, int R) { return (m + 64 * R - 1) / (64 * R); };
-  auto pipe = [&](int64_t m, int R) {  // a pipeline of waves alone on their SIMDs
-    const double chunks = (double)((n_max + 126) / 64 + (int64_t)kIntraLag * (bands(m, R) - 1));
-    return chunks * 64 * 0.76 * 0.5e-6 * step_scale(R);
+  // anti-diagonal step of a wave alone on its SIMD (MI355X: about 0.13, 0.17 and 0.27 us
+  // at R = 4, 8 and 16); two waves on a SIMD take 1.66 times as long
+  auto step_alone = [](int R) { return 0.083e-6 + 0.0118e-6 * R; };
+  auto pipe = [&](int64_t m, int R, int waves) {  // a band pipeline of `waves` waves
+    const int64_t b = bands(m, R);
+    const double chunks = (double)((n_max + 126) / 64 + (int64_t)kIntraLag * (b - 1));
+    return chunks * 64 * step_alone(R) * (std::min<int64_t>(b, waves) > 4 ? 1.66 : 1.0);
   };
   // (throughput time, longest path) at R
   auto estimate = [&](int R, double &thr, double &path) {
@@ -66,10 +73,11 @@ int choose_R(const std::vector<int64_t> &lens, double intra_res, int64_t n_max,
       thr += (double)b * 64 * R * intra_res / (rate * (b > kIntraWaves ? eff_rounds : eff_few));
       double t;
       if (b >= 2 && n_max >= wide_len) {
-        t = pipe(m, R);
-        if (R > kCritR) t = std::min(t, pipe(m, kCritR));
+        t = pipe(m, R, kIntraWaves);
+        // a pair of more than four bands may be split into the critical-pair launch
+        if (R > kCritR && b > kCritWaves) t = std::min(t, pipe(m, kCritR, kCritWaves));
       } else {
-        t = (double)b * (double)(n_max + 63) * 0.5e-6 * step_scale(R);
+        t = (double)b * (double)(n_max + 63) * step_alone(R);
       }
       path = std::max(path, t);
     }
