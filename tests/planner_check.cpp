@@ -402,6 +402,33 @@ int main() {
     n_q2 += p.q2;
     n_slots2 += p.big_waves > 0;
   }
+  // Rows per lane on a database shaped like the long-sequence mix (9,900 log-normal
+  // sequences of median 300 and 100 of 10,000-35,000 residues): the choices measured
+  // fastest on MI355X for queries of 144 to 35,000 residues (300: R = 2, 1000: 4,
+  // 2005: 8, 5478 and 35000: 16, 5478 with a critical-pair launch and four-wave
+  // workgroups).
+  {
+    g_case = "long-mix rows per lane";
+    std::mt19937_64 r2(35000);
+    std::lognormal_distribution<double> ln300(std::log(300.0), 0.8);
+    std::vector<int64_t> len;
+    for (int i = 0; i < 9900; ++i)
+      len.push_back(std::max<int64_t>(10, std::min<int64_t>(8000, (int64_t)ln300(r2))));
+    for (int i = 0; i < 99; ++i) len.push_back(10000 + (int64_t)(r2() % 25001));
+    len.push_back(35000);
+    Db d = make_db(len, 8192, 256, 24);
+    const int64_t ms[] = {300, 1000, 2005, 5478, 35000};
+    const int want[] = {2, 4, 8, 16, 16};
+    for (int i = 0; i < 5; ++i) {
+      const int64_t qoff[2] = {0, ms[i]};
+      const Plan p = make_plan(d.view, qoff, 1, Knobs{}, occ);
+      check_plan(p, d, std::vector<int64_t>(qoff, qoff + 2), 1);
+      if (p.R != want[i])
+        std::fprintf(stderr, "long mix, %lld-row query: R = %d (want %d)\n", (long long)ms[i],
+                     p.R, want[i]);
+      CHECK(p.R == want[i], "rows per lane on the long mix");
+    }
+  }
   // the random cases must reach every kind of item
   if (!n_split || !n_crit || !n_duo || !n_routed || !n_q2 || !n_split_duos || !n_slots2)
     fail("a kind of item never planned");
