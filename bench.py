@@ -587,7 +587,9 @@ def calibrate():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    # default: 3 timed steps, 100 for the plain search, whose step (one search of about
+    # 0.3 ms) is otherwise dominated by the first launch's start from an idle device
+    ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="full",
                     choices=["full", "plain", "long_mix", "batched", "served"])
@@ -613,6 +615,8 @@ def main():
                     help="time register-only copies of the DP cell at int16 x 2, int32 and "
                          "SWAR int8 x 4 (libswmi_calib.so) and exit")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 100 if args.workload == "plain" else 3
     if args.calibrate:
         print(json.dumps(calibrate()), flush=True)
         return

@@ -284,9 +284,10 @@ const char *sw_strerror(int code);
 /*
  * Kernel timing of the inter-task DP kernel (the dominant kernel), measured with HIP
  * events recorded on the stream that launches it.  sw_timing_enable(db, 1) turns the
- * events on and clears the totals; sw_timing_read reports the number of launches and
- * the summed device time in milliseconds since then.  Not thread-safe with concurrent
- * searches on the same handle.
+ * events on, clears the totals and creates the events of the next 128 timed launches
+ * (so that no search in a timed region creates one); sw_timing_read reports the number
+ * of launches and the summed device time in milliseconds since then.  Not thread-safe
+ * with concurrent searches on the same handle.
  */
 int sw_timing_enable(sw_db *db, int32_t enable);
 int sw_timing_read(const sw_db *db, int64_t *launches, double *total_ms);

@@ -110,6 +110,9 @@ struct Workspace {
 
 }  // namespace
 
+// Timing events created when timing is turned on (two per timed launch).
+constexpr size_t kTimingSpares = 256;
+
 struct sw_db {
   int device = 0;
   int num_cu = 0;
@@ -1041,6 +1044,16 @@ SW_API int sw_timing_enable(sw_db *db, int32_t enable) {
     for (int k = 0; k < 3; ++k) {
       db->timing_launches[k] = 0;
       db->timing_ms[k] = 0.0;
+    }
+    // events for the searches to come, created here rather than inside a timed region
+    // (a first hipEventCreate took about 0.1 ms; a search of the plain workload 0.3)
+    if (db->timing) {
+      hip_check(hipSetDevice(db->device));
+      while (db->spare_events.size() < kTimingSpares) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        db->spare_events.push_back(e);
+      }
     }
     for (auto &e : db->timing_events) {  // recorded, possibly unfinished: not reused
       (void)hipEventDestroy(e.e0);
